@@ -1,0 +1,192 @@
+"""ALM-BM solve in FP64 (test infrastructure only).
+
+The loop follows Alg. 1 (ALORA, Sec. 5) in its order: y starts at the given
+y0 (zero by default, as Alg. 1 initialises it); each outer iteration
+approximately minimises the BM subproblem eq. (AL-BM) by gradient descent
+(eq. GD, Sec. 4.2), then looks at the smallest eigenpair of
+grad_X L = C - A*(y + sigma (b - A(RR^T))), expands the factor by one column
+when that eigenvalue is sufficiently negative (p = 1 case of Alg. 1 lines 5-9),
+then updates y (eq. ALM) and tests the relative KKT measure of Sec. 6.
+
+Readings where the paper is silent (shared with the HIP path through the
+solve options):
+* step size: exact minimiser over t >= 0 of the quartic phi(t) = Lbar(R - tG)
+  (ties to the smallest t); a fixed step is the alternative;
+* inner stop: ||G||_F ||R||_F <= tol_k (1 + |<C, RR^T>|), or max_inner
+  iterations, with tol_k = max(eps/10, min(0.1, pinf_{k-1}, kappa tol_{k-1}))
+  and kappa = 0.7 (pinf and tol are +inf before the first outer iteration).
+  The left side bounds |<grad_X L, RR^T>| = |<G, R>|/2, the subproblem's share
+  of the duality-gap term of the KKT measure, so the rule is scale free; the
+  tolerance shrinks at least geometrically, as inexact ALM needs;
+* rank step with p = 1: s* = max(0, -theta / (sigma ||A(v v^T)||^2)) is the
+  exact minimiser over s >= 0 of L(RR^T + s v v^T, y), whose expansion is
+  L(X) + s theta + (sigma/2) s^2 ||A(v v^T)||^2; expand iff theta < -tau_rank
+  (default eps (1 + ||C||_F)) and r < r_cap = min(r_max, Barvinok-Pataki bound
+  floor((sqrt(8m+1)-1)/2) of Sec. 3.3);
+* fixed penalty sigma.
+
+Pins: the quartic coefficients against direct evaluation of the objective at
+R - tG (tests/test_oracle_alm.py); solve values against closed-form MaxCut and
+Lovasz-theta values, brute-force max cuts and an independent dense convex ALM.
+Trajectory-level agreement with the HIP solve is parity unpinned beyond
+final invariants (discrete rank/root decisions may differ near ties).
+"""
+
+import math
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+from .sdp import (amap, amap_uv, cost_apply, cost_fro_norm, kkt, min_eig,
+                  objective_grad, rank_one_norm2)
+
+
+@dataclass
+class SolveOptions:
+    eps_kkt: float = 1e-6
+    sigma: float = 1.0
+    max_outer: int = 1000
+    max_inner: int = 500
+    step_rule: str = "exact"       # 'exact' | 'fixed'
+    eta_fixed: float = 1e-3
+    rank_policy: str = "adapt"     # 'adapt' | 'fixed'
+    r_max: int = 64
+    tau_rank: Optional[float] = None
+    inner_tol_scale: float = 0.1   # the 0.1 in min(0.1, pinf_prev, kappa tol_prev)
+    inner_tol_decay: float = 0.7   # kappa
+    expand_needs_inner: bool = True  # expand only after an inner solve met its tolerance
+
+
+def line_search_coeffs(p, R, G, y, sigma, P=None, a=None):
+    """Coefficients k0..k4 of phi(t) = Lbar_sigma(R - t G, y) = sum_k k_k t^k.
+
+    With c0 = <C, RR^T>, c1 = 2<G, CR>, c2 = <G, CG>, a0 = A(RR^T),
+    a1 = A(RG^T + GR^T), a2 = A(GG^T) and e = a0 - b:
+      <C, (R-tG)(R-tG)^T> = c0 - t c1 + t^2 c2,
+      A((R-tG)(R-tG)^T)   = a0 - t a1 + t^2 a2.
+    """
+    if P is None:
+        P = cost_apply(p, R)
+    if a is None:
+        a = amap(p, R)
+    Q = cost_apply(p, G)
+    c0 = float(np.sum(R * P))
+    c1 = 2.0 * float(np.sum(G * P))
+    c2 = float(np.sum(G * Q))
+    a1 = 2.0 * amap_uv(p, R, G)
+    a2 = amap(p, G)
+    e = a - p.b
+    k0 = c0 + float(np.dot(y, p.b - a)) + 0.5 * sigma * float(np.dot(e, e))
+    k1 = -c1 + float(np.dot(y, a1)) - sigma * float(np.dot(e, a1))
+    k2 = c2 - float(np.dot(y, a2)) + 0.5 * sigma * (float(np.dot(a1, a1)) + 2.0 * float(np.dot(e, a2)))
+    k3 = -sigma * float(np.dot(a1, a2))
+    k4 = 0.5 * sigma * float(np.dot(a2, a2))
+    return np.array([k0, k1, k2, k3, k4])
+
+
+def _phi(k, t):
+    return k[0] + t * (k[1] + t * (k[2] + t * (k[3] + t * k[4])))
+
+
+def quartic_argmin(k):
+    """argmin over t >= 0 of the quartic with coefficients k (smallest t on ties).
+
+    Candidates are t = 0 and the real non-negative roots of phi'(t)
+    (numpy.roots, i.e. companion-matrix eigenvalues).  Returns 0 when phi is
+    unbounded below on t >= 0 (degenerate directions).
+    """
+    d = np.array([4.0 * k[4], 3.0 * k[3], 2.0 * k[2], k[1]])
+    nz = np.flatnonzero(d != 0.0)
+    if nz.size == 0:
+        return 0.0
+    d = d[nz[0]:]
+    lead_deg = d.size - 1  # degree of phi' actually present
+    # phi unbounded below on t >= 0 when the leading term of phi is negative
+    if lead_deg >= 1 and d[0] < 0.0:
+        return 0.0
+    cands = [0.0]
+    if lead_deg >= 1:
+        for z in np.roots(d):
+            if abs(z.imag) <= 1e-9 * max(1.0, abs(z.real)) and z.real > 0.0:
+                cands.append(float(z.real))
+    best_t, best_v = 0.0, _phi(k, 0.0)
+    for t in sorted(cands):
+        v = _phi(k, t)
+        if v < best_v:
+            best_t, best_v = t, v
+    return best_t
+
+
+def inner_gd(p, R, y, sigma, tol, max_inner, step_rule="exact", eta_fixed=1e-3):
+    """Gradient descent R <- R - t G on eq. (AL-BM) until
+    ||G||_F ||R||_F <= tol (1 + |<C, RR^T>|)."""
+    R = np.array(R, dtype=np.float64, copy=True)
+    it = 0
+    gnorm = math.inf
+    f = math.nan
+    for it in range(max_inner):
+        f, G, a, P = objective_grad(p, R, y, sigma)
+        gnorm = float(np.linalg.norm(G))
+        c0 = float(np.sum(R * P))
+        if gnorm * float(np.linalg.norm(R)) <= tol * (1.0 + abs(c0)):
+            return R, {"iters": it, "f": f, "gnorm": gnorm, "converged": True}
+        if step_rule == "exact":
+            t = quartic_argmin(line_search_coeffs(p, R, G, y, sigma, P, a))
+        else:
+            t = eta_fixed
+        R = R - t * G
+    return R, {"iters": max_inner, "f": f, "gnorm": gnorm, "converged": False}
+
+
+def bp_rank_cap(m):
+    """Largest r with r(r+1)/2 <= m (Barvinok-Pataki bound, Sec. 3.3)."""
+    return int((math.isqrt(8 * m + 1) - 1) // 2)
+
+
+def solve(p, R0, y0=None, opts=None, callback=None):
+    """ALM-BM with p = 1 rank adaptation (Alg. 1); see the module docstring."""
+    opts = opts or SolveOptions()
+    R = np.array(R0, dtype=np.float64, copy=True)
+    y = np.zeros(p.m) if y0 is None else np.array(y0, dtype=np.float64, copy=True)
+    sigma = opts.sigma
+    cnorm = cost_fro_norm(p)
+    tau_rank = opts.tau_rank if opts.tau_rank is not None else opts.eps_kkt * (1.0 + cnorm)
+    r_cap = min(opts.r_max, bp_rank_cap(p.m))
+    pinf_prev = math.inf
+    tol_prev = math.inf
+    hist = []
+    info = None
+    status = "not_converged"
+    for k in range(opts.max_outer):
+        tol = max(opts.eps_kkt / 10.0, min(opts.inner_tol_scale, pinf_prev,
+                                                 opts.inner_tol_decay * tol_prev))
+        tol_prev = tol
+        R, inner = inner_gd(p, R, y, sigma, tol, opts.max_inner, opts.step_rule, opts.eta_fixed)
+        a = amap(p, R)
+        w = y - sigma * (a - p.b)
+        expanded = False
+        if opts.rank_policy == "adapt":
+            theta, v = min_eig(p, w, want_vector=True)
+            gate = inner["converged"] or not opts.expand_needs_inner
+            if gate and theta < -tau_rank and R.shape[1] < r_cap:
+                s = max(0.0, -theta / (sigma * rank_one_norm2(p, v)))
+                R = np.concatenate([R, math.sqrt(s) * v[:, None]], axis=1)
+                a = amap(p, R)
+                w = y - sigma * (a - p.b)
+                expanded = True
+        else:
+            theta = min_eig(p, w)
+        y = w
+        lam = theta if not expanded else min_eig(p, y)
+        info = kkt(p, R, y, lam_min=lam)
+        info.update({"outer": k, "inner_iters": inner["iters"], "rank": R.shape[1],
+                     "expanded": expanded, "theta": theta, "f": inner["f"]})
+        hist.append(info)
+        if callback is not None:
+            callback(info)
+        pinf_prev = info["pinf"]
+        if info["kkt"] <= opts.eps_kkt:
+            status = "converged"
+            break
+    return {"R": R, "y": y, "status": status, "history": hist, "kkt": info}
