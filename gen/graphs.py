@@ -43,11 +43,12 @@ def _canonical_sorted(n, i, j):
 
 
 def er_graph(n, m_edges, seed, weights="unit"):
-    """Erdos-Renyi G(n, M): M distinct pairs i != j drawn uniformly.
+    """Erdos-Renyi G(n, M): a uniformly random set of M distinct pairs i != j.
 
-    Pairs are drawn in batches; self pairs are dropped and a pair already drawn
-    is drawn again (duplicates resampled), until M distinct pairs exist.  The
-    edge list is then sorted by (i, j) and weights are drawn in that order.
+    Pairs are drawn uniformly in batches (self pairs dropped) until at least M
+    distinct pairs are held; a uniformly random M-subset of them is kept, which
+    is again a uniform M-subset of all pairs.  Edges are sorted by (i, j) and
+    weights are drawn in that order.
     """
     n = int(n)
     m_edges = int(m_edges)
@@ -57,22 +58,16 @@ def er_graph(n, m_edges, seed, weights="unit"):
     keys = np.empty(0, dtype=np.int64)
     while keys.shape[0] < m_edges:
         need = m_edges - keys.shape[0]
-        k = int(need * 1.05) + 64
+        k = int(need * 1.02) + 64
         a = rng.integers(0, n, size=k, dtype=np.int64)
         b = rng.integers(0, n, size=k, dtype=np.int64)
         keep = a != b
         a, b = a[keep], b[keep]
-        lo = np.minimum(a, b)
-        hi = np.maximum(a, b)
-        new = lo * np.int64(n) + hi
-        # drop pairs already held and duplicates inside the batch, keeping the
-        # first draw of each pair, then take only as many as still needed
-        new_u, first = np.unique(new, return_index=True)
-        new_u = new_u[np.argsort(first, kind="stable")]
-        if keys.shape[0]:
-            new_u = new_u[~np.isin(new_u, keys, assume_unique=True)]
-        keys = np.concatenate([keys, new_u[:need]])
-    keys.sort()
+        new = np.minimum(a, b) * np.int64(n) + np.maximum(a, b)
+        keys = np.unique(np.concatenate([keys, new]))
+    if keys.shape[0] > m_edges:
+        pick = rng.choice(keys.shape[0], size=m_edges, replace=False)
+        keys = np.sort(keys[pick])
     ei = keys // n
     ej = keys % n
     w = draw_weights(rng, m_edges, weights)

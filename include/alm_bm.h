@@ -1,0 +1,241 @@
+/*
+ * alm_bm.h -- C ABI of the MI355X (gfx950) ALM-BM library (libalmbm.so).
+ *
+ * The library computes the data-parallel hot path of the augmented Lagrangian
+ * Burer-Monteiro method (ALM-BM) of arxiv 2505.15775 for semidefinite programs
+ *
+ *     (P)   minimise <C, X>  subject to  A(X) = b,  X PSD          (Sec. 1.2)
+ *
+ * on a factor R (n x r), X = R R^T, with the augmented Lagrangian
+ *
+ *     Lbar_sigma(R, y) = <C, RR^T> + <y, b - A(RR^T)> + sigma/2 ||A(RR^T) - b||^2
+ *
+ * (eq. AL-BM; the paper writes rho for sigma and F for R).
+ *
+ * Problem structure accepted
+ *   cost        C = S + Diag(d) - j_coef * J, with S a sparse symmetric matrix
+ *               holding only off-diagonal entries (both triangles), d a dense
+ *               diagonal and J the all-ones matrix.  MaxCut (Sec. 6.1) uses
+ *               C = -L/4: S_ij = w_ij/4, d_i = -sum_k w_ik/4, j_coef = 0.
+ *   constraints ALM_BM_CONS_DIAG:  A_i = e_i e_i^T, m = n (X_ii = b_i).
+ *               ALM_BM_CONS_TRACE_EDGES: A_0 = trace_coef * I and, for each
+ *               edge e = {i, j} (i < j), A_{1+e} = (e_i e_j^T + e_j e_i^T)/2,
+ *               so <A_{1+e}, X> = X_ij; m = n_edges + 1.  This is the entry
+ *               constraint of the examples of Sec. 3.3 and Sec. 4.3 and the
+ *               constraint set of the Lovasz-theta SDP.
+ *
+ * Conventions (all entry points)
+ *   - Every call returns alm_bm_status.  Nothing throws or aborts across the
+ *     ABI.  Argument checks return ALM_BM_ERR_INVALID_ARG before any launch.
+ *     alm_bm_last_error() gives a message for the last failing call on the
+ *     calling thread.
+ *   - Pointers named "device" are device memory owned by the caller; they must
+ *     stay valid while the handle uses them (the problem arrays for the life of
+ *     the handle).  Pointers named "host" are host memory.
+ *   - R and G are row-major n x r arrays with row stride r, in the handle's
+ *     storage precision (double, float or bfloat16).  y, b, Av and every scalar
+ *     are double in every precision mode.
+ *   - Indices are 0-based int32.
+ *   - All work is enqueued on the given stream; only alm_bm_solve and
+ *     alm_bm_lanczos_min_eig synchronise it (the latter to run the small
+ *     tridiagonal eigensolve on the host).
+ *   - A handle is not thread-safe.  Calls that overlap on one handle race.
+ *   - The handle owns its workspace (allocated in alm_bm_create and sized for
+ *     r_max and lanczos_kmax); no other call allocates device memory except
+ *     alm_bm_solve, which builds HIP graphs of its inner loop.
+ */
+#ifndef ALM_BM_H
+#define ALM_BM_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  ALM_BM_OK = 0,
+  ALM_BM_NOT_CONVERGED = 1,        /* solve: outputs valid, tolerance not met     */
+  ALM_BM_ERR_INVALID_ARG = -1,     /* null pointer, bad size, r > r_max, ...      */
+  ALM_BM_ERR_INVALID_PATTERN = -2, /* CSR / edge list malformed (validate = 1)    */
+  ALM_BM_ERR_HIP = -3,             /* a HIP runtime call failed                   */
+  ALM_BM_ERR_OOM = -4,             /* workspace allocation failed                 */
+  ALM_BM_ERR_NUMERIC = -5,         /* NaN or Inf in a scalar the solve depends on */
+  ALM_BM_ERR_UNSUPPORTED = -6      /* combination of options not implemented      */
+} alm_bm_status;
+
+typedef enum {
+  ALM_BM_F64 = 0,  /* R, G stored and computed in double                       */
+  ALM_BM_F32 = 1,  /* R, G and the sparse values in float, float accumulation   */
+  ALM_BM_BF16 = 2  /* R, G stored as bfloat16 (round to nearest even), float
+                      arithmetic and accumulation, float sparse values          */
+} alm_bm_precision;
+
+typedef enum {
+  ALM_BM_CONS_DIAG = 0,
+  ALM_BM_CONS_TRACE_EDGES = 1
+} alm_bm_cons_kind;
+
+typedef struct {
+  int64_t n;                 /* matrix order                                         */
+  /* cost C = S + Diag(diag) - j_coef * J                                              */
+  int64_t nnz;               /* stored off-diagonal entries of S (both triangles)    */
+  const int32_t* row_ptr;    /* device, n+1 (CSR); NULL when ell_width > 0 or nnz = 0 */
+  const int32_t* col_idx;    /* device, nnz; within a row sorted ascending (CSR)     */
+  const double* val;         /* device, nnz                                          */
+  int32_t ell_width;         /* > 0: ELL layout, row i holds entries
+                                [i*ell_width, (i+1)*ell_width) of col_idx/val; pad
+                                with col = i and val = 0; nnz must be n*ell_width   */
+  const double* diag;        /* device, n; NULL means d = 0                          */
+  double j_coef;             /* coefficient of -J (0 for MaxCut, 1 for Lovasz theta) */
+  /* constraints                                                                       */
+  alm_bm_cons_kind cons_kind;
+  int64_t m;                 /* n (DIAG) or n_edges + 1 (TRACE_EDGES)                */
+  const double* b;           /* device, m                                            */
+  double trace_coef;         /* TRACE_EDGES: A_0 = trace_coef * I                    */
+  int64_t n_edges;           /* TRACE_EDGES                                          */
+  const int32_t* edge_i;     /* device, n_edges; edges sorted by (i, j), i < j,      */
+  const int32_t* edge_j;     /*   no duplicates; y[1+e] belongs to edge e            */
+  /* storage                                                                           */
+  alm_bm_precision precision;
+  int32_t r_max;             /* largest rank any call will use (1..128)              */
+  int32_t lanczos_kmax;      /* largest Lanczos basis (0 disables Lanczos; <= 512)   */
+  int32_t validate;          /* 1: check CSR/ELL and edge list on create (D2H copy)  */
+} alm_bm_problem_desc;
+
+typedef struct alm_bm_problem alm_bm_problem;
+
+typedef enum { ALM_BM_STEP_EXACT = 0, ALM_BM_STEP_FIXED = 1 } alm_bm_step_rule;
+typedef enum { ALM_BM_RANK_ADAPT = 0, ALM_BM_RANK_FIXED = 1 } alm_bm_rank_policy;
+
+/* Options of alm_bm_solve.  alm_bm_default_options() fills the defaults given
+ * after each field; readings of points the paper leaves open are stated there. */
+typedef struct {
+  double eps_kkt;            /* 1e-6   stop when the relative KKT measure <= eps      */
+  double sigma;              /* 1.0    penalty (fixed, as the input rho of Alg. 1)    */
+  int32_t max_outer;         /* 1000                                                   */
+  int32_t max_inner;         /* 500    gradient steps per subproblem                  */
+  alm_bm_step_rule step_rule;/* EXACT  exact minimiser of the quartic Lbar(R - tG)    */
+  double eta_fixed;          /* 1e-3   step for ALM_BM_STEP_FIXED                     */
+  alm_bm_rank_policy rank_policy; /* ADAPT p = 1 expansion of Alg. 1 lines 5-9       */
+  int32_t r_cap;             /* 0 -> min(r_max, floor((sqrt(8m+1)-1)/2))              */
+  double tau_rank;           /* <= 0 -> eps_kkt (1 + ||C||_F)                        */
+  int32_t expand_needs_inner;/* 1      expand only after an inner solve converged     */
+  double inner_tol_scale;    /* 0.1    tol_k = max(eps/10, min(0.1, pinf, kappa tol)) */
+  double inner_tol_decay;    /* 0.7    kappa                                           */
+  int32_t lanczos_kmax;      /* 0 -> the handle's lanczos_kmax                        */
+  double lanczos_tol_rel;    /* 0.1    Ritz residual <= 0.1 eps (1 + ||C||_F)         */
+  uint64_t seed;             /* 1      Lanczos start vector                            */
+  int32_t graph_unroll;      /* 8      inner iterations per captured HIP graph; 0 = no graph */
+  int32_t verbose;           /* 0      1: one line per outer iteration on stderr      */
+  double time_limit_s;       /* 0      > 0: stop (NOT_CONVERGED) after this wall time  */
+  int32_t bf16_promote;      /* 1      BF16 handle: ladder to float storage when stalled */
+} alm_bm_options;
+
+typedef struct {
+  int32_t outer;             /* outer iterations run                                  */
+  int64_t inner_total;       /* gradient steps over all outer iterations              */
+  int32_t rank;              /* final rank                                            */
+  int32_t expansions;        /* rank expansions taken                                 */
+  double pobj;               /* <C, RR^T>                                             */
+  double dobj;               /* b^T y                                                 */
+  double pinf, dinf, gap, kkt; /* relative KKT terms (Sec. 6) at (RR^T, y)            */
+  double lam_min;            /* lambda_min(C - A* y) estimate (Lanczos, an upper bound) */
+  double time_s;             /* wall time of the solve                                */
+  double time_lanczos_s;     /* of which in Lanczos                                   */
+  int32_t promoted_at_outer; /* BF16 ladder switch point (-1 = none)                  */
+  double time_promoted_s;    /* wall time spent after the switch                       */
+} alm_bm_result;
+
+/* --------------------------------------------------------------------------- */
+
+/* Create a handle for one problem.  Validates sizes, allocates the workspace,
+ * converts the sparse values to float in the F32/BF16 modes and, for
+ * TRACE_EDGES, builds the symmetric adjacency with edge ids (host round trip).
+ * stream: where set-up copies and kernels run; synchronised before return.     */
+alm_bm_status alm_bm_create(const alm_bm_problem_desc* desc, hipStream_t stream,
+                            alm_bm_problem** out);
+alm_bm_status alm_bm_destroy(alm_bm_problem* prob);
+
+/* Objective and gradient of eq. (AL-BM) at (R, y):
+ *   f  = Lbar_sigma(R, y)                         (device, 1 double)
+ *   G  = 2 (C - A*(w)) R,  w = y - sigma (A(RR^T) - b)   (device n x r, nullable)
+ *   Av = A(RR^T)                                  (device m doubles, nullable)
+ * The factor 2 is that of grad h(F) = 2 grad f(X) F (Sec. 4.2).
+ * r: 1..r_max.  R device n x r.  y device m.                                    */
+alm_bm_status alm_bm_objective_grad(alm_bm_problem* prob, int32_t r, const void* R,
+                                    const double* y, double sigma, double* f, void* G,
+                                    double* Av, hipStream_t stream);
+
+/* Coefficients k[0..4] of phi(t) = Lbar_sigma(R - t G, y) = sum_k k[k] t^k
+ * (device, 5 doubles) and the exact minimiser t* over t >= 0 (device, 1 double,
+ * nullable; ties to the smallest t; 0 when phi is unbounded below).  G is any
+ * direction of the same shape as R (the solve uses the gradient).               */
+alm_bm_status alm_bm_line_search(alm_bm_problem* prob, int32_t r, const void* R,
+                                 const void* G, const double* y, double sigma,
+                                 double* coeffs, double* t_star, hipStream_t stream);
+
+/* One gradient-descent step of eq. (GD) (Sec. 4.2) with the exact line search:
+ * G = grad Lbar_sigma(R, y), t* = argmin_{t >= 0} Lbar_sigma(R - t G, y), then
+ * R <- R - t* G in place.  f (device, 1 double, nullable) receives the objective
+ * before the step, t (device, 1 double, nullable) the step, G (device n x r,
+ * nullable: the handle's workspace is used) the gradient.  This is the body of
+ * the inner loop of alm_bm_solve.                                              */
+alm_bm_status alm_bm_gd_step(alm_bm_problem* prob, int32_t r, void* R, const double* y,
+                             double sigma, double* f, double* t, void* G, hipStream_t stream);
+
+/* Dual update of eq. (ALM): y <- y + sigma (b - Av) in place (device, m);
+ * pinf = ||Av - b|| / (1 + ||b||) (device, 1 double, nullable), Sec. 6.           */
+alm_bm_status alm_bm_dual_update(alm_bm_problem* prob, const double* Av, double sigma,
+                                 double* y, double* pinf, hipStream_t stream);
+
+/* Smallest eigenvalue of the dual slack Z(y) = C - A*(y) (Sec. 1.2) by Lanczos
+ * with full FP64 reorthogonalisation (two classical Gram-Schmidt passes),
+ * start vector drawn from `seed` by a counter-based generator.  Stops when the
+ * Ritz residual ||Z v - theta v|| <= tol or after max_iter (<= lanczos_kmax) steps.
+ * theta, resid: device 1 double each; iters: device 1 int32 (all nullable except
+ * theta); v: device n doubles, unit Ritz vector (nullable).  Synchronises stream.
+ * theta is a Ritz value, hence an upper bound on lambda_min.                    */
+alm_bm_status alm_bm_lanczos_min_eig(alm_bm_problem* prob, const double* y, int32_t max_iter,
+                                     double tol, uint64_t seed, double* theta, double* v,
+                                     double* resid, int32_t* iters, hipStream_t stream);
+
+/* Full ALM-BM solve (Alg. 1, ALORA, with p = 1 rank adaptation).
+ * R: device buffer of n x r_max elements; its first n*(*r) elements hold the
+ * starting factor (row stride *r) and on return the final factor (row stride
+ * the returned *r).  r: host in/out.  y: device m, in/out (start and final dual).
+ * opts: host, NULL = defaults.  out: host, nullable.  Synchronous.
+ * Returns ALM_BM_OK when the KKT measure met eps_kkt, ALM_BM_NOT_CONVERGED when
+ * max_outer or the time limit ran out (outputs still valid).                   */
+alm_bm_status alm_bm_solve(alm_bm_problem* prob, const alm_bm_options* opts, void* R,
+                           int32_t* r, double* y, alm_bm_result* out, hipStream_t stream);
+
+/* Relative KKT measure of Sec. 6 at (RR^T, y) with lambda_min supplied by the
+ * caller (host double); kkt_out: host array of 6 doubles
+ * {pinf, dinf, gap, kkt, pobj, dobj}.  Synchronises stream.                      */
+alm_bm_status alm_bm_kkt(alm_bm_problem* prob, int32_t r, const void* R, const double* y,
+                         double lam_min, double* kkt_out, hipStream_t stream);
+
+void alm_bm_default_options(alm_bm_options* opts);
+const char* alm_bm_last_error(void);
+
+/* sizeof(alm_bm_problem_desc), sizeof(alm_bm_options), sizeof(alm_bm_result)
+ * into out[0..3) (host), so that bindings can check their struct mirrors.       */
+void alm_bm_abi_sizes(int64_t* out);
+
+/* Host helper: the MaxCut cost of Sec. 6.1, C = -L/4, as CSR + diagonal from an
+ * undirected edge list (host arrays).  ei[k] != ej[k]; duplicates are summed.
+ * Outputs (host, caller-allocated): row_ptr n+1, col_idx 2M, val 2M, diag n;
+ * columns sorted ascending within each row.  *nnz_out receives the entry count
+ * (2M minus merged duplicates).                                                  */
+alm_bm_status alm_bm_maxcut_cost_host(int64_t n, int64_t m_edges, const int32_t* ei,
+                                      const int32_t* ej, const double* w, int32_t* row_ptr,
+                                      int32_t* col_idx, double* val, double* diag,
+                                      int64_t* nnz_out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ALM_BM_H */

@@ -34,6 +34,7 @@ from .sdp import (  # noqa: F401
     min_eig,
     kkt,
     rank_one_norm2,
+    maxcut_objective_grad_rows,
 )
 from .alm import (  # noqa: F401
     SolveOptions,

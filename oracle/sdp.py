@@ -253,3 +253,30 @@ def kkt(p, R, y, lam_min=None):
     gap = abs(pobj - dobj) / (1.0 + abs(pobj) + abs(dobj))
     return {"pinf": pinf, "dinf": dinf, "gap": gap, "kkt": max(pinf, dinf, gap),
             "pobj": pobj, "dobj": dobj, "lam_min": float(lam_min)}
+
+
+def maxcut_objective_grad_rows(graph, R, y, sigma, rows):
+    """G and a = A(RR^T) of the MaxCut SDP (C = -L/4, X_ii = 1) at selected rows
+    only, evaluated row by row from the edge list:
+      (CR)_i = sum_{j ~ i} w_ij R_j / 4 - (sum_{j ~ i} w_ij) R_i / 4,
+      a_i = ||R_i||^2,  G_i = 2 ((CR)_i - (y_i - sigma (a_i - 1)) R_i).
+    For parity checks at sizes where assembling the full oracle is slow."""
+    rows = np.asarray(rows, dtype=np.int64)
+    pos = {int(r): k for k, r in enumerate(rows)}
+    sel = np.isin(graph.ei, rows) | np.isin(graph.ej, rows)
+    P = np.zeros((rows.shape[0], R.shape[1]))
+    deg = np.zeros(rows.shape[0])
+    for i, j, wij in zip(graph.ei[sel], graph.ej[sel], graph.w[sel]):
+        for u, v in ((int(i), int(j)), (int(j), int(i))):
+            k = pos.get(u)
+            if k is not None:
+                P[k] += 0.25 * wij * R[v]
+                deg[k] += wij
+    G = np.zeros_like(P)
+    a = np.zeros(rows.shape[0])
+    for k, i in enumerate(rows):
+        P[k] -= 0.25 * deg[k] * R[i]
+        a[k] = float(R[i] @ R[i])
+        wi = y[i] - sigma * (a[k] - 1.0)
+        G[k] = 2.0 * (P[k] - wi * R[i])
+    return G, a

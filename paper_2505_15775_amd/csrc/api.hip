@@ -1,0 +1,1047 @@
+// C ABI of libalmbm: handle, workspace, entry points and the host side of the
+// ALM-BM solve (Alg. 1 of arxiv 2505.15775 with p = 1 rank adaptation).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cfloat>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "alm_bm.h"
+#include "launch.hpp"
+
+using namespace almbm;
+
+// --------------------------------------------------------------------- errors
+
+static thread_local std::string g_err;
+
+static alm_bm_status fail(alm_bm_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+#define HIPCHK(x)                                                                                         \
+  do {                                                                                                    \
+    hipError_t e_ = (x);                                                                                  \
+    if (e_ != hipSuccess) return fail(ALM_BM_ERR_HIP, std::string(#x) + ": " + hipGetErrorString(e_));   \
+  } while (0)
+
+#define STCHK(x)                       \
+  do {                                 \
+    alm_bm_status s_ = (x);            \
+    if (s_ < 0) return s_;             \
+  } while (0)
+
+// --------------------------------------------------------------------- handle
+
+struct alm_bm_problem {
+  alm_bm_problem_desc d{};
+  double cnorm = 0.0;  // ||C||_F
+  double bnorm = 0.0;  // ||b||_2
+  Cost<double> C64{};
+  Cost<float> C32{};
+  EdgeAdj adj{};
+  double* wE = nullptr;
+  int nblk = 0;
+  int variant = 0;
+  double* part = nullptr;     // nblk * (NUM_P + kMaxR)
+  double* part_c2 = nullptr;  // nblk
+  double* part_vec = nullptr; // vec kernels
+  DevScalars* sc_api = nullptr;
+  DevScalars* sc_solve = nullptr;
+  DevScalars* sc_host = nullptr;  // pinned mirror
+  void* G = nullptr;              // n * r_max storage
+  void* Rtmp = nullptr;           // n * r_max storage
+  void* R32 = nullptr;            // float factor, gradient and relayout scratch for
+  void* G32 = nullptr;            //   the BF16 -> float precision ladder
+  void* Rt32 = nullptr;
+  hipStream_t ss = nullptr;       // solve stream (non-blocking, default priority)
+  double* Av = nullptr;           // m
+  double* ybuf = nullptr;         // m
+  // Lanczos workspace
+  int kmax = 0;
+  int lnb = 0;
+  double* Q = nullptr;
+  double* lw = nullptr;
+  double* lh1 = nullptr;
+  double* lh2 = nullptr;
+  double* lalpha = nullptr;
+  double* lbeta = nullptr;
+  double* lpart = nullptr;
+  double* lpart2 = nullptr;
+  double* lv = nullptr;
+  double* ls = nullptr;
+  double* lscal = nullptr;
+  std::vector<void*> allocs;
+};
+
+static size_t esize(alm_bm_precision p) { return p == ALM_BM_F64 ? 8 : (p == ALM_BM_F32 ? 4 : 2); }
+
+static alm_bm_status dalloc(alm_bm_problem* p, void** out, size_t bytes) {
+  if (bytes == 0) bytes = 8;
+  hipError_t e = hipMalloc(out, bytes);
+  if (e != hipSuccess) return fail(ALM_BM_ERR_OOM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
+  p->allocs.push_back(*out);
+  return ALM_BM_OK;
+}
+template <typename X>
+static alm_bm_status dalloc_t(alm_bm_problem* p, X** out, size_t count) {
+  void* v = nullptr;
+  STCHK(dalloc(p, &v, count * sizeof(X)));
+  *out = static_cast<X*>(v);
+  return ALM_BM_OK;
+}
+
+static void free_all(alm_bm_problem* p) {
+  for (void* a : p->allocs) (void)hipFree(a);
+  p->allocs.clear();
+  if (p->ss) (void)hipStreamDestroy(p->ss);
+  p->ss = nullptr;
+  if (p->sc_host) (void)hipHostFree(p->sc_host);
+  p->sc_host = nullptr;
+}
+
+template <typename T> static const Cost<typename Acc<T>::type>& cost_of(const alm_bm_problem* p);
+template <> const Cost<double>& cost_of<double>(const alm_bm_problem* p) { return p->C64; }
+template <> const Cost<float>& cost_of<float>(const alm_bm_problem* p) { return p->C32; }
+template <> const Cost<float>& cost_of<bf16>(const alm_bm_problem* p) { return p->C32; }
+
+// Run f.template operator()<T>() for the storage type of precision `prec`.
+template <typename F>
+static auto with_storage(alm_bm_precision prec, F&& f) {
+  if (prec == ALM_BM_F64) return f.template operator()<double>();
+  if (prec == ALM_BM_F32) return f.template operator()<float>();
+  return f.template operator()<bf16>();
+}
+
+// --------------------------------------------------------------------- host helpers
+
+static bool check_csr(const std::vector<int32_t>& rp, const std::vector<int32_t>& ci, long n, long nnz,
+                      std::string& why) {
+  if (rp[0] != 0 || rp[n] != nnz) {
+    why = "row_ptr[0] must be 0 and row_ptr[n] must equal nnz";
+    return false;
+  }
+  for (long i = 0; i < n; ++i) {
+    if (rp[i + 1] < rp[i]) {
+      why = "row_ptr not monotone at row " + std::to_string(i);
+      return false;
+    }
+    for (int k = rp[i]; k < rp[i + 1]; ++k) {
+      if (ci[k] < 0 || ci[k] >= n) {
+        why = "col_idx out of range at entry " + std::to_string(k);
+        return false;
+      }
+      if (k > rp[i] && ci[k] < ci[k - 1]) {
+        why = "col_idx not ascending in row " + std::to_string(i);
+        return false;
+      }
+    }
+  }
+  return true;
+}
+
+extern "C" alm_bm_status alm_bm_maxcut_cost_host(int64_t n, int64_t m_edges, const int32_t* ei, const int32_t* ej,
+                                                 const double* w, int32_t* row_ptr, int32_t* col_idx, double* val,
+                                                 double* diag, int64_t* nnz_out) {
+  if (n <= 0 || m_edges < 0 || (m_edges > 0 && (!ei || !ej || !w)) || !row_ptr || !diag || !nnz_out)
+    return fail(ALM_BM_ERR_INVALID_ARG, "maxcut_cost_host: bad arguments");
+  if (2 * m_edges > INT32_MAX) return fail(ALM_BM_ERR_UNSUPPORTED, "maxcut_cost_host: more than 2^31 entries");
+  std::vector<int64_t> cnt(n + 1, 0);
+  for (int64_t e = 0; e < m_edges; ++e) {
+    const int32_t i = ei[e], j = ej[e];
+    if (i < 0 || j < 0 || i >= n || j >= n || i == j)
+      return fail(ALM_BM_ERR_INVALID_PATTERN, "maxcut_cost_host: edge " + std::to_string(e) + " invalid");
+    cnt[i + 1]++;
+    cnt[j + 1]++;
+  }
+  for (int64_t i = 0; i < n; ++i) cnt[i + 1] += cnt[i];
+  std::vector<int64_t> cur(cnt.begin(), cnt.end() - 1);
+  for (int64_t i = 0; i < n; ++i) diag[i] = 0.0;
+  // lower entries (row = larger endpoint) first, then upper: ascending columns
+  // within each row when the edge list is sorted by (min, max)
+  for (int64_t e = 0; e < m_edges; ++e) {
+    const int32_t i = std::min(ei[e], ej[e]), j = std::max(ei[e], ej[e]);
+    col_idx[cur[j]] = i;
+    val[cur[j]++] = 0.25 * w[e];
+  }
+  for (int64_t e = 0; e < m_edges; ++e) {
+    const int32_t i = std::min(ei[e], ej[e]), j = std::max(ei[e], ej[e]);
+    col_idx[cur[i]] = j;
+    val[cur[i]++] = 0.25 * w[e];
+    diag[i] -= 0.25 * w[e];
+    diag[j] -= 0.25 * w[e];
+  }
+  // sort rows that are not ascending, merge duplicates, compact
+  int64_t out = 0;
+  std::vector<std::pair<int32_t, double>> tmp;
+  row_ptr[0] = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    const int64_t a = cnt[i], b = cnt[i + 1];
+    bool sorted = true;
+    for (int64_t k = a + 1; k < b; ++k)
+      if (col_idx[k] <= col_idx[k - 1]) {
+        sorted = false;
+        break;
+      }
+    if (!sorted) {
+      tmp.clear();
+      for (int64_t k = a; k < b; ++k) tmp.emplace_back(col_idx[k], val[k]);
+      std::sort(tmp.begin(), tmp.end(), [](const auto& x, const auto& y) { return x.first < y.first; });
+      int64_t k = a;
+      for (size_t t = 0; t < tmp.size(); ++t) {
+        col_idx[k] = tmp[t].first;
+        val[k] = tmp[t].second;
+        ++k;
+      }
+    }
+    for (int64_t k = a; k < b; ++k) {
+      if (out > row_ptr[i] && col_idx[out - 1] == col_idx[k]) {
+        val[out - 1] += val[k];
+      } else {
+        col_idx[out] = col_idx[k];
+        val[out] = val[k];
+        ++out;
+      }
+    }
+    row_ptr[i + 1] = (int32_t)out;
+  }
+  *nnz_out = out;
+  return ALM_BM_OK;
+}
+
+extern "C" void alm_bm_default_options(alm_bm_options* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->eps_kkt = 1e-6;
+  o->sigma = 1.0;
+  o->max_outer = 1000;
+  o->max_inner = 500;
+  o->step_rule = ALM_BM_STEP_EXACT;
+  o->eta_fixed = 1e-3;
+  o->rank_policy = ALM_BM_RANK_ADAPT;
+  o->r_cap = 0;
+  o->tau_rank = 0.0;
+  o->expand_needs_inner = 1;
+  o->inner_tol_scale = 0.1;
+  o->inner_tol_decay = 0.7;
+  o->lanczos_kmax = 0;
+  o->lanczos_tol_rel = 0.1;
+  o->seed = 1;
+  o->graph_unroll = 8;
+  o->verbose = 0;
+  o->time_limit_s = 0.0;
+  o->bf16_promote = 1;
+}
+
+extern "C" const char* alm_bm_last_error(void) { return g_err.c_str(); }
+
+extern "C" void alm_bm_abi_sizes(int64_t* out) {
+  if (!out) return;
+  out[0] = (int64_t)sizeof(alm_bm_problem_desc);
+  out[1] = (int64_t)sizeof(alm_bm_options);
+  out[2] = (int64_t)sizeof(alm_bm_result);
+}
+
+// --------------------------------------------------------------------- create / destroy
+
+static int row_blocks(long n) {
+  long nb = (n + 63) / 64;
+  if (nb < 8) nb = 8;
+  if (nb > 4096) nb = 4096;
+  return (int)((nb + 7) / 8 * 8);
+}
+
+extern "C" alm_bm_status alm_bm_create(const alm_bm_problem_desc* desc, hipStream_t st, alm_bm_problem** out) {
+  if (!desc || !out) return fail(ALM_BM_ERR_INVALID_ARG, "create: null desc or out");
+  *out = nullptr;
+  const alm_bm_problem_desc& d = *desc;
+  if (d.n <= 0 || d.n > INT32_MAX) return fail(ALM_BM_ERR_INVALID_ARG, "create: n out of range");
+  if (d.r_max < 1 || d.r_max > kMaxR) return fail(ALM_BM_ERR_INVALID_ARG, "create: r_max must be in 1..128");
+  if (d.lanczos_kmax < 0 || d.lanczos_kmax > 512)
+    return fail(ALM_BM_ERR_INVALID_ARG, "create: lanczos_kmax must be in 0..512");
+  if (d.precision != ALM_BM_F64 && d.precision != ALM_BM_F32 && d.precision != ALM_BM_BF16)
+    return fail(ALM_BM_ERR_INVALID_ARG, "create: unknown precision");
+  if (!d.b) return fail(ALM_BM_ERR_INVALID_ARG, "create: b is null");
+  if (d.nnz < 0 || (d.nnz > 0 && (!d.col_idx || !d.val)))
+    return fail(ALM_BM_ERR_INVALID_ARG, "create: nnz > 0 needs col_idx and val");
+  if (d.nnz > INT32_MAX) return fail(ALM_BM_ERR_UNSUPPORTED, "create: nnz >= 2^31 needs 64-bit indices");
+  if (d.ell_width < 0) return fail(ALM_BM_ERR_INVALID_ARG, "create: ell_width < 0");
+  if (d.ell_width > 0 && d.nnz != d.n * (int64_t)d.ell_width)
+    return fail(ALM_BM_ERR_INVALID_ARG, "create: ELL needs nnz = n * ell_width");
+  if (d.ell_width == 0 && d.nnz > 0 && !d.row_ptr) return fail(ALM_BM_ERR_INVALID_ARG, "create: CSR needs row_ptr");
+  if (d.cons_kind == ALM_BM_CONS_DIAG) {
+    if (d.m != d.n) return fail(ALM_BM_ERR_INVALID_ARG, "create: DIAG needs m = n");
+    if (d.j_coef != 0.0) return fail(ALM_BM_ERR_UNSUPPORTED, "create: DIAG constraints with a -J cost term");
+  } else if (d.cons_kind == ALM_BM_CONS_TRACE_EDGES) {
+    if (d.n_edges < 0 || d.m != d.n_edges + 1) return fail(ALM_BM_ERR_INVALID_ARG, "create: TRACE_EDGES needs m = n_edges + 1");
+    if (d.n_edges > 0 && (!d.edge_i || !d.edge_j)) return fail(ALM_BM_ERR_INVALID_ARG, "create: edge arrays null");
+    if (2 * d.n_edges > INT32_MAX) return fail(ALM_BM_ERR_UNSUPPORTED, "create: too many edges");
+  } else {
+    return fail(ALM_BM_ERR_INVALID_ARG, "create: unknown constraint kind");
+  }
+  HIPCHK(hipStreamSynchronize(st));
+
+  alm_bm_problem* p = new alm_bm_problem();
+  p->d = d;
+  const long n = d.n;
+  auto bail = [&](alm_bm_status s) {
+    free_all(p);
+    delete p;
+    return s;
+  };
+#define CK(x)                          \
+  do {                                 \
+    alm_bm_status s_ = (x);            \
+    if (s_ < 0) return bail(s_);       \
+  } while (0)
+#define HK(x)                                                                                          \
+  do {                                                                                                 \
+    hipError_t e_ = (x);                                                                               \
+    if (e_ != hipSuccess) return bail(fail(ALM_BM_ERR_HIP, std::string(#x) + ": " + hipGetErrorString(e_))); \
+  } while (0)
+
+  // ---- host copies for validation, norms and the edge adjacency
+  std::vector<double> hval(d.nnz), hdg(d.diag ? n : 0), hb(d.m);
+  if (d.nnz) HK(hipMemcpy(hval.data(), d.val, d.nnz * sizeof(double), hipMemcpyDeviceToHost));
+  if (d.diag) HK(hipMemcpy(hdg.data(), d.diag, n * sizeof(double), hipMemcpyDeviceToHost));
+  HK(hipMemcpy(hb.data(), d.b, d.m * sizeof(double), hipMemcpyDeviceToHost));
+  if (d.validate && d.nnz) {
+    std::vector<int32_t> hci(d.nnz);
+    HK(hipMemcpy(hci.data(), d.col_idx, d.nnz * sizeof(int32_t), hipMemcpyDeviceToHost));
+    if (d.ell_width > 0) {
+      for (long k = 0; k < d.nnz; ++k)
+        if (hci[k] < 0 || hci[k] >= n) return bail(fail(ALM_BM_ERR_INVALID_PATTERN, "ELL col_idx out of range"));
+    } else {
+      std::vector<int32_t> hrp(n + 1);
+      HK(hipMemcpy(hrp.data(), d.row_ptr, (n + 1) * sizeof(int32_t), hipMemcpyDeviceToHost));
+      std::string why;
+      if (!check_csr(hrp, hci, n, d.nnz, why)) return bail(fail(ALM_BM_ERR_INVALID_PATTERN, "CSR: " + why));
+    }
+  }
+  for (double v : hval)
+    if (!std::isfinite(v)) return bail(fail(ALM_BM_ERR_NUMERIC, "create: non-finite cost value"));
+  for (double v : hb)
+    if (!std::isfinite(v)) return bail(fail(ALM_BM_ERR_NUMERIC, "create: non-finite b"));
+  // ||S + D - jJ||_F^2 = ||S + D||^2 - 2 j sum(S + D) + j^2 n^2
+  {
+    double s2 = 0.0, s1 = 0.0;
+    for (double v : hval) {
+      s2 += v * v;
+      s1 += v;
+    }
+    for (double v : hdg) {
+      s2 += v * v;
+      s1 += v;
+    }
+    const double j = d.j_coef;
+    p->cnorm = std::sqrt(std::max(0.0, s2 - 2.0 * j * s1 + j * j * (double)n * (double)n));
+    double b2 = 0.0;
+    for (double v : hb) b2 += v * v;
+    p->bnorm = std::sqrt(b2);
+  }
+  p->C64 = Cost<double>{n, d.ell_width > 0 ? nullptr : (d.nnz ? d.row_ptr : nullptr), d.col_idx, d.val, d.ell_width,
+                        d.diag};
+  if (d.nnz == 0) p->C64.rp = nullptr, p->C64.ell = 0;
+
+  // ---- float copies of the cost for the F32 / BF16 modes
+  if (d.precision != ALM_BM_F64) {
+    float* cv32 = nullptr;
+    float* dg32 = nullptr;
+    if (d.nnz) {
+      CK(dalloc_t(p, &cv32, d.nnz));
+      launch_convert<double, float>(d.nnz, d.val, cv32, st);
+    }
+    if (d.diag) {
+      CK(dalloc_t(p, &dg32, n));
+      launch_convert<double, float>(n, d.diag, dg32, st);
+    }
+    p->C32 = Cost<float>{n, p->C64.rp, d.col_idx, cv32, p->C64.ell, dg32};
+  }
+
+  // ---- edge adjacency (host build, one upload)
+  if (d.cons_kind == ALM_BM_CONS_TRACE_EDGES) {
+    const long E = d.n_edges;
+    std::vector<int32_t> ei(E), ej(E);
+    if (E) {
+      HK(hipMemcpy(ei.data(), d.edge_i, E * sizeof(int32_t), hipMemcpyDeviceToHost));
+      HK(hipMemcpy(ej.data(), d.edge_j, E * sizeof(int32_t), hipMemcpyDeviceToHost));
+    }
+    for (long e = 0; e < E; ++e) {
+      if (ei[e] < 0 || ej[e] >= n || ei[e] >= ej[e])
+        return bail(fail(ALM_BM_ERR_INVALID_PATTERN, "edge " + std::to_string(e) + ": need 0 <= i < j < n"));
+      if (e > 0 && (ei[e] < ei[e - 1] || (ei[e] == ei[e - 1] && ej[e] <= ej[e - 1])))
+        return bail(fail(ALM_BM_ERR_INVALID_PATTERN, "edges must be sorted by (i, j) without duplicates"));
+    }
+    std::vector<int32_t> urp(n + 1, 0), rp(n + 1, 0), ci(2 * E), eid(2 * E);
+    for (long e = 0; e < E; ++e) {
+      urp[ei[e] + 1]++;
+      rp[ei[e] + 1]++;
+      rp[ej[e] + 1]++;
+    }
+    for (long i = 0; i < n; ++i) {
+      urp[i + 1] += urp[i];
+      rp[i + 1] += rp[i];
+    }
+    std::vector<int32_t> cur(rp.begin(), rp.end() - 1);
+    for (long e = 0; e < E; ++e) {  // lower entries: row j, column i < j
+      ci[cur[ej[e]]] = ei[e];
+      eid[cur[ej[e]]++] = (int32_t)e;
+    }
+    for (long e = 0; e < E; ++e) {  // upper entries: row i, column j > i
+      ci[cur[ei[e]]] = ej[e];
+      eid[cur[ei[e]]++] = (int32_t)e;
+    }
+    int32_t *drp, *dci, *deid, *durp;
+    CK(dalloc_t(p, &drp, n + 1));
+    CK(dalloc_t(p, &durp, n + 1));
+    CK(dalloc_t(p, &dci, std::max<long>(1, 2 * E)));
+    CK(dalloc_t(p, &deid, std::max<long>(1, 2 * E)));
+    HK(hipMemcpy(drp, rp.data(), (n + 1) * sizeof(int32_t), hipMemcpyHostToDevice));
+    HK(hipMemcpy(durp, urp.data(), (n + 1) * sizeof(int32_t), hipMemcpyHostToDevice));
+    if (E) {
+      HK(hipMemcpy(dci, ci.data(), 2 * E * sizeof(int32_t), hipMemcpyHostToDevice));
+      HK(hipMemcpy(deid, eid.data(), 2 * E * sizeof(int32_t), hipMemcpyHostToDevice));
+    }
+    p->adj = EdgeAdj{drp, dci, deid, durp, d.edge_j};
+    CK(dalloc_t(p, &p->wE, std::max<long>(1, E)));
+  }
+
+  // ---- workspace
+  p->nblk = row_blocks(n);
+  const size_t es = esize(d.precision);
+  CK(dalloc_t(p, &p->part, (size_t)p->nblk * (NUM_P + kMaxR)));
+  CK(dalloc_t(p, &p->part_c2, (size_t)p->nblk));
+  CK(dalloc_t(p, &p->sc_api, 1));
+  CK(dalloc_t(p, &p->sc_solve, 1));
+  CK(dalloc(p, &p->G, (size_t)n * d.r_max * es));
+  CK(dalloc(p, &p->Rtmp, (size_t)n * d.r_max * es));
+  CK(dalloc_t(p, &p->Av, d.m));
+  CK(dalloc_t(p, &p->ybuf, d.m));
+  p->lnb = vec_blocks(n);
+  CK(dalloc_t(p, &p->part_vec, (size_t)std::max(p->lnb, dual_blocks(d.m)) * 2 + 16));
+  {
+    hipError_t e = hipHostMalloc((void**)&p->sc_host, sizeof(DevScalars), hipHostMallocDefault);
+    if (e != hipSuccess) return bail(fail(ALM_BM_ERR_OOM, "hipHostMalloc failed"));
+    std::memset(p->sc_host, 0, sizeof(DevScalars));
+  }
+  HK(hipMemcpy(p->sc_api, p->sc_host, sizeof(DevScalars), hipMemcpyHostToDevice));
+  HK(hipMemcpy(p->sc_solve, p->sc_host, sizeof(DevScalars), hipMemcpyHostToDevice));
+  p->kmax = d.lanczos_kmax;
+  if (p->kmax > 0) {
+    CK(dalloc_t(p, &p->Q, (size_t)n * (p->kmax + 1)));
+    CK(dalloc_t(p, &p->lw, n));
+    CK(dalloc_t(p, &p->lv, n));
+    CK(dalloc_t(p, &p->lh1, p->kmax + 1));
+    CK(dalloc_t(p, &p->lh2, p->kmax + 1));
+    CK(dalloc_t(p, &p->lalpha, p->kmax + 1));
+    CK(dalloc_t(p, &p->lbeta, p->kmax + 1));
+    CK(dalloc_t(p, &p->ls, p->kmax + 1));
+    CK(dalloc_t(p, &p->lscal, 8));
+    CK(dalloc_t(p, &p->lpart, (size_t)p->lnb * (p->kmax + 1)));
+    CK(dalloc_t(p, &p->lpart2, (size_t)p->lnb));
+  }
+  HK(hipStreamCreateWithFlags(&p->ss, hipStreamNonBlocking));
+  HK(hipStreamSynchronize(st));
+  HK(hipGetLastError());
+  *out = p;
+  return ALM_BM_OK;
+#undef CK
+#undef HK
+}
+
+extern "C" alm_bm_status alm_bm_destroy(alm_bm_problem* p) {
+  if (!p) return ALM_BM_OK;
+  (void)hipDeviceSynchronize();
+  free_all(p);
+  delete p;
+  return ALM_BM_OK;
+}
+
+// --------------------------------------------------------------------- enqueue helpers
+
+// f, G (nullable), Av (nullable) at (R, y): one objective/gradient evaluation.
+template <typename T>
+static void enqueue_objgrad(alm_bm_problem* p, int r, const T* R, const double* y, double sigma, T* G, double* Av,
+                            DevScalars* sc, int mode, double* f_out, hipStream_t st) {
+  const auto& d = p->d;
+  if (d.cons_kind == ALM_BM_CONS_DIAG) {
+    launch_objgrad_diag<T>(cost_of<T>(p), r, p->variant, R, y, d.b, sigma, G, Av, p->part, sc, p->nblk, st);
+    launch_fin_objgrad(p->part, p->nblk, sc, sigma, mode, f_out, st);
+  } else {
+    launch_edges_p1<T>(p->adj, d.n, r, p->variant, R, y, d.b, sigma, Av, p->wE, p->part, sc, p->nblk, st);
+    launch_fin_edges1(p->part, p->nblk, r, sc, y, d.b, sigma, d.trace_coef, Av, st);
+    launch_edges_p2<T>(cost_of<T>(p), p->adj, r, p->variant, R, p->wE, d.trace_coef, d.j_coef, nullptr, G, p->part,
+                       sc, p->nblk, st);
+    launch_fin_edges2(p->part, p->nblk, r, sc, sigma, mode, f_out, st);
+  }
+}
+
+// One inner gradient step (flag-guarded): objective/gradient, stop test,
+// exact line search, update.
+template <typename T>
+static void enqueue_inner_step(alm_bm_problem* p, int r, T* R, const double* y, double sigma, T* G, hipStream_t st) {
+  const auto& d = p->d;
+  DevScalars* sc = p->sc_solve;
+  enqueue_objgrad<T>(p, r, R, y, sigma, G, p->Av, sc, 1, nullptr, st);
+  if (d.cons_kind == ALM_BM_CONS_DIAG) {
+    launch_quad_diag<T>(cost_of<T>(p), r, p->variant, G, p->part_c2, sc, p->nblk, st);
+    launch_fin_step(p->part_c2, p->nblk, 1, sc, sigma, 0.0, 1, nullptr, nullptr, st);
+  } else {
+    launch_edges_p3<T>(cost_of<T>(p), p->adj, r, p->variant, R, G, y, d.b, p->Av, p->part, sc, p->nblk, st);
+    launch_fin_edges3(p->part, p->nblk, r, sc, y, d.b, sigma, d.trace_coef, d.j_coef, 1, nullptr, nullptr, st);
+  }
+  launch_update<T>((long)d.n * r, R, G, sc, 1, st);
+}
+
+static alm_bm_status check_r(const alm_bm_problem* p, int r) {
+  if (r < 1 || r > p->d.r_max) return fail(ALM_BM_ERR_INVALID_ARG, "r must be in 1..r_max");
+  return ALM_BM_OK;
+}
+
+// --------------------------------------------------------------------- API: per call
+
+extern "C" alm_bm_status alm_bm_objective_grad(alm_bm_problem* p, int32_t r, const void* R, const double* y,
+                                               double sigma, double* f, void* G, double* Av, hipStream_t st) {
+  if (!p || !R || !y || !f) return fail(ALM_BM_ERR_INVALID_ARG, "objective_grad: null argument");
+  STCHK(check_r(p, r));
+  with_storage(p->d.precision, [&]<typename T>() {
+    enqueue_objgrad<T>(p, r, static_cast<const T*>(R), y, sigma, static_cast<T*>(G), Av, p->sc_api, 0, f, st);
+    return 0;
+  });
+  HIPCHK(hipGetLastError());
+  return ALM_BM_OK;
+}
+
+extern "C" alm_bm_status alm_bm_line_search(alm_bm_problem* p, int32_t r, const void* R, const void* G,
+                                            const double* y, double sigma, double* coeffs, double* t_star,
+                                            hipStream_t st) {
+  if (!p || !R || !G || !y || !coeffs) return fail(ALM_BM_ERR_INVALID_ARG, "line_search: null argument");
+  STCHK(check_r(p, r));
+  const auto& d = p->d;
+  with_storage(d.precision, [&]<typename T>() {
+    const T* Rt = static_cast<const T*>(R);
+    const T* Gt = static_cast<const T*>(G);
+    if (d.cons_kind == ALM_BM_CONS_DIAG) {
+      launch_ls_diag<T>(cost_of<T>(p), r, p->variant, Rt, Gt, y, d.b, p->part, p->nblk, st);
+      launch_fin_ls(p->part, p->nblk, p->sc_api, sigma, coeffs, t_star, st);
+    } else {
+      DevScalars* sc = p->sc_api;
+      launch_edges_p1<T>(p->adj, d.n, r, p->variant, Rt, y, d.b, sigma, p->Av, p->wE, p->part, sc, p->nblk, st);
+      launch_fin_edges1(p->part, p->nblk, r, sc, y, d.b, sigma, d.trace_coef, p->Av, st);
+      launch_edges_p2<T>(cost_of<T>(p), p->adj, r, p->variant, Rt, p->wE, d.trace_coef, d.j_coef, Gt, nullptr,
+                         p->part, sc, p->nblk, st);
+      launch_fin_edges2(p->part, p->nblk, r, sc, sigma, 0, nullptr, st);
+      launch_edges_p3<T>(cost_of<T>(p), p->adj, r, p->variant, Rt, Gt, y, d.b, p->Av, p->part, sc, p->nblk, st);
+      launch_fin_edges3(p->part, p->nblk, r, sc, y, d.b, sigma, d.trace_coef, d.j_coef, 0, coeffs, t_star, st);
+    }
+    return 0;
+  });
+  HIPCHK(hipGetLastError());
+  return ALM_BM_OK;
+}
+
+extern "C" alm_bm_status alm_bm_gd_step(alm_bm_problem* p, int32_t r, void* R, const double* y, double sigma,
+                                        double* f, double* t, void* G, hipStream_t st) {
+  if (!p || !R || !y) return fail(ALM_BM_ERR_INVALID_ARG, "gd_step: null argument");
+  STCHK(check_r(p, r));
+  const auto& d = p->d;
+  with_storage(d.precision, [&]<typename T>() {
+    T* Rt = static_cast<T*>(R);
+    T* Gt = G ? static_cast<T*>(G) : static_cast<T*>(p->G);
+    DevScalars* sc = p->sc_api;
+    enqueue_objgrad<T>(p, r, Rt, y, sigma, Gt, p->Av, sc, 0, f, st);
+    if (d.cons_kind == ALM_BM_CONS_DIAG) {
+      launch_quad_diag<T>(cost_of<T>(p), r, p->variant, Gt, p->part_c2, sc, p->nblk, st);
+      launch_fin_step(p->part_c2, p->nblk, 1, sc, sigma, 0.0, 0, nullptr, t, st);
+    } else {
+      launch_edges_p3<T>(cost_of<T>(p), p->adj, r, p->variant, Rt, Gt, y, d.b, p->Av, p->part, sc, p->nblk, st);
+      launch_fin_edges3(p->part, p->nblk, r, sc, y, d.b, sigma, d.trace_coef, d.j_coef, 0, nullptr, t, st);
+    }
+    launch_update<T>((long)d.n * r, Rt, Gt, sc, 0, st);
+    return 0;
+  });
+  HIPCHK(hipGetLastError());
+  return ALM_BM_OK;
+}
+
+extern "C" alm_bm_status alm_bm_dual_update(alm_bm_problem* p, const double* Av, double sigma, double* y,
+                                            double* pinf, hipStream_t st) {
+  if (!p || !Av || !y) return fail(ALM_BM_ERR_INVALID_ARG, "dual_update: null argument");
+  launch_dual(p->d.m, Av, p->d.b, y, y, sigma, p->part_vec, p->sc_api, p->bnorm, pinf, st);
+  HIPCHK(hipGetLastError());
+  return ALM_BM_OK;
+}
+
+// --------------------------------------------------------------------- Lanczos
+
+static int sturm_count(const std::vector<double>& a, const std::vector<double>& b, int m, double x) {
+  double bmax = 0.0;
+  for (int i = 0; i + 1 < m; ++i) bmax = std::max(bmax, b[i] * b[i]);
+  const double pivmin = DBL_MIN * std::max(1.0, bmax);
+  int c = 0;
+  double q = a[0] - x;
+  if (std::fabs(q) < pivmin) q = -pivmin;
+  if (q < 0) ++c;
+  for (int i = 1; i < m; ++i) {
+    q = a[i] - x - b[i - 1] * b[i - 1] / q;
+    if (std::fabs(q) < pivmin) q = -pivmin;
+    if (q < 0) ++c;
+  }
+  return c;
+}
+
+// Smallest eigenvalue of the symmetric tridiagonal (a[0..m), b[0..m-1)) by
+// Sturm-sequence bisection.
+static double tri_min_eig(const std::vector<double>& a, const std::vector<double>& b, int m) {
+  if (m == 1) return a[0];
+  double lo = INFINITY, hi = -INFINITY;
+  for (int i = 0; i < m; ++i) {
+    const double rad = (i > 0 ? std::fabs(b[i - 1]) : 0.0) + (i + 1 < m ? std::fabs(b[i]) : 0.0);
+    lo = std::min(lo, a[i] - rad);
+    hi = std::max(hi, a[i] + rad);
+  }
+  const double scale = std::max(std::fabs(lo), std::fabs(hi));
+  for (int it = 0; it < 300; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (hi - lo <= 2.0 * DBL_EPSILON * scale || mid <= lo || mid >= hi) break;
+    if (sturm_count(a, b, m, mid) >= 1) hi = mid;
+    else lo = mid;
+  }
+  return 0.5 * (lo + hi);
+}
+
+// Eigenvector of the tridiagonal for eigenvalue theta by inverse iteration,
+// (T - theta I) factored by Gaussian elimination with partial pivoting.
+static void tri_eigvec(const std::vector<double>& a, const std::vector<double>& b, int m, double theta,
+                       std::vector<double>& z) {
+  z.assign(m, 0.0);
+  if (m == 1) {
+    z[0] = 1.0;
+    return;
+  }
+  double tnorm = 0.0;
+  for (int i = 0; i < m; ++i) tnorm = std::max(tnorm, std::fabs(a[i]) + (i + 1 < m ? std::fabs(b[i]) : 0.0));
+  const double tiny = std::max(tnorm, 1e-300) * DBL_EPSILON;
+  std::vector<double> dl(m - 1), dd(m), du(m - 1), du2(std::max(1, m - 2), 0.0);
+  std::vector<char> swp(m - 1, 0);
+  for (int i = 0; i < m; ++i) dd[i] = a[i] - theta;
+  for (int i = 0; i + 1 < m; ++i) dl[i] = du[i] = b[i];
+  for (int i = 0; i + 1 < m; ++i) {
+    if (std::fabs(dd[i]) >= std::fabs(dl[i])) {
+      if (dd[i] == 0.0) dd[i] = tiny;
+      const double fact = dl[i] / dd[i];
+      dl[i] = fact;
+      dd[i + 1] -= fact * du[i];
+      if (i + 2 < m) du2[i] = 0.0;
+    } else {
+      const double fact = dd[i] / dl[i];
+      dd[i] = dl[i];
+      dl[i] = fact;
+      const double temp = du[i];
+      du[i] = dd[i + 1];
+      dd[i + 1] = temp - fact * dd[i + 1];
+      if (i + 2 < m) {
+        du2[i] = du[i + 1];
+        du[i + 1] = -fact * du[i + 1];
+      }
+      swp[i] = 1;
+    }
+  }
+  if (dd[m - 1] == 0.0) dd[m - 1] = tiny;
+  for (int i = 0; i < m; ++i) z[i] = 1.0 + 0.01 * (double)((i * 7919) % 97) / 97.0;
+  for (int it = 0; it < 4; ++it) {
+    std::vector<double> x = z;
+    for (int i = 0; i + 1 < m; ++i) {
+      if (swp[i]) {
+        const double t = x[i];
+        x[i] = x[i + 1];
+        x[i + 1] = t - dl[i] * x[i];
+      } else {
+        x[i + 1] -= dl[i] * x[i];
+      }
+    }
+    x[m - 1] /= dd[m - 1];
+    x[m - 2] = (x[m - 2] - du[m - 2] * x[m - 1]) / dd[m - 2];
+    for (int i = m - 3; i >= 0; --i) x[i] = (x[i] - du[i] * x[i + 1] - du2[i] * x[i + 2]) / dd[i];
+    double nrm = 0.0;
+    for (double v : x) nrm += v * v;
+    nrm = std::sqrt(nrm);
+    if (!(nrm > 0.0) || !std::isfinite(nrm)) break;
+    for (int i = 0; i < m; ++i) z[i] = x[i] / nrm;
+  }
+}
+
+struct LanczosOut {
+  double theta = 0.0;
+  double resid = 0.0;
+  int iters = 0;
+};
+
+// Lanczos on Z(y) with two classical Gram-Schmidt passes per step; the Ritz
+// vector for the smallest Ritz value goes to v (device, n).
+static alm_bm_status lanczos_run(alm_bm_problem* p, const double* y, int kmax, double tol, uint64_t seed, double* v,
+                                 LanczosOut& out, hipStream_t st) {
+  const auto& d = p->d;
+  const long n = d.n;
+  const long ldq = n;
+  const int nb = p->lnb;
+  const int pstride = p->kmax + 1;
+  kmax = std::min(kmax, p->kmax);
+  if (kmax < 1) return fail(ALM_BM_ERR_INVALID_ARG, "lanczos: no Lanczos workspace (lanczos_kmax = 0)");
+  kmax = (int)std::min<long>(kmax, n);
+  double* qsum = (d.j_coef != 0.0) ? &p->sc_api->qsum : nullptr;
+  const int cons = d.cons_kind == ALM_BM_CONS_DIAG ? 0 : 1;
+  launch_rand(n, seed, p->lw, p->lpart2, nb, st);
+  launch_fin_sum(p->lpart2, nb, p->lscal, 1, st);
+  launch_scale(n, p->lw, p->lscal, p->Q, p->lpart2, nb, qsum, st);
+  std::vector<double> ha(kmax + 1), hb(kmax + 1), z;
+  int m = 0;
+  double theta = 0.0;
+  const int check_every = n <= 4096 ? 4 : 8;
+  for (int j = 0; j < kmax; ++j) {
+    const double* qj = p->Q + (long)j * ldq;
+    launch_slack_mv(p->C64, cons, p->adj, y, d.trace_coef, d.j_coef, p->sc_api, qj, p->lw, st);
+    launch_dots(n, j + 1, p->Q, ldq, p->lw, p->lpart, pstride, nb, p->lh1, st);
+    launch_sub(n, j + 1, p->Q, ldq, p->lh1, p->lw, p->lpart2, nb, st);
+    launch_dots(n, j + 1, p->Q, ldq, p->lw, p->lpart, pstride, nb, p->lh2, st);
+    launch_sub(n, j + 1, p->Q, ldq, p->lh2, p->lw, p->lpart2, nb, st);
+    launch_fin_ab(p->lpart2, nb, p->lh1, p->lh2, j, p->lalpha, p->lbeta, st);
+    launch_scale(n, p->lw, p->lbeta + j, p->Q + (long)(j + 1) * ldq, p->lpart2, nb, qsum, st);
+    const bool last = (j + 1 == kmax);
+    if (((j + 1) % check_every) == 0 || last) {
+      HIPCHK(hipMemcpyAsync(ha.data(), p->lalpha, (j + 1) * sizeof(double), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipMemcpyAsync(hb.data(), p->lbeta, (j + 1) * sizeof(double), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      double anorm = 0.0;
+      for (int i = 0; i <= j; ++i) anorm = std::max(anorm, std::fabs(ha[i]) + std::fabs(hb[i]));
+      for (int i = 0; i <= j; ++i)
+        if (!std::isfinite(ha[i]) || !std::isfinite(hb[i])) return fail(ALM_BM_ERR_NUMERIC, "lanczos: NaN/Inf");
+      // an (almost) invariant subspace ends the recurrence
+      int mm = j + 1;
+      bool breakdown = false;
+      for (int i = 0; i <= j; ++i)
+        if (hb[i] <= 1e-13 * std::max(anorm, 1e-300)) {
+          mm = i + 1;
+          breakdown = true;
+          break;
+        }
+      theta = tri_min_eig(ha, hb, mm);
+      tri_eigvec(ha, hb, mm, theta, z);
+      m = mm;
+      const double est = breakdown ? 0.0 : std::fabs(hb[mm - 1] * z[mm - 1]);
+      if (breakdown || est <= tol || last) break;
+    }
+  }
+  HIPCHK(hipMemcpyAsync(p->ls, z.data(), m * sizeof(double), hipMemcpyHostToDevice, st));
+  launch_combine(n, m, p->Q, ldq, p->ls, v, p->lpart2, nb, st);
+  launch_fin_sum(p->lpart2, nb, p->lscal + 1, 1, st);
+  launch_scale(n, v, p->lscal + 1, v, p->lpart2, nb, qsum, st);
+  launch_slack_mv(p->C64, cons, p->adj, y, d.trace_coef, d.j_coef, p->sc_api, v, p->lw, st);
+  launch_resid(n, p->lw, v, theta, p->lpart2, nb, st);
+  launch_fin_sum(p->lpart2, nb, p->lscal + 2, 1, st);
+  double hres = 0.0;
+  HIPCHK(hipMemcpyAsync(&hres, p->lscal + 2, sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  HIPCHK(hipGetLastError());
+  out.theta = theta;
+  out.resid = hres;
+  out.iters = m;
+  if (!std::isfinite(theta)) return fail(ALM_BM_ERR_NUMERIC, "lanczos: non-finite Ritz value");
+  return ALM_BM_OK;
+}
+
+extern "C" alm_bm_status alm_bm_lanczos_min_eig(alm_bm_problem* p, const double* y, int32_t max_iter, double tol,
+                                                uint64_t seed, double* theta, double* v, double* resid,
+                                                int32_t* iters, hipStream_t st) {
+  if (!p || !y || !theta) return fail(ALM_BM_ERR_INVALID_ARG, "lanczos_min_eig: null argument");
+  if (max_iter < 1) return fail(ALM_BM_ERR_INVALID_ARG, "lanczos_min_eig: max_iter < 1");
+  if (max_iter > p->kmax) return fail(ALM_BM_ERR_INVALID_ARG, "lanczos_min_eig: max_iter > lanczos_kmax");
+  LanczosOut o;
+  STCHK(lanczos_run(p, y, max_iter, tol, seed, v ? v : p->lv, o, st));
+  HIPCHK(hipMemcpyAsync(theta, &o.theta, sizeof(double), hipMemcpyHostToDevice, st));
+  if (resid) HIPCHK(hipMemcpyAsync(resid, &o.resid, sizeof(double), hipMemcpyHostToDevice, st));
+  if (iters) HIPCHK(hipMemcpyAsync(iters, &o.iters, sizeof(int32_t), hipMemcpyHostToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return ALM_BM_OK;
+}
+
+// --------------------------------------------------------------------- KKT
+
+struct KktVals {
+  double pinf, dinf, gap, kkt, pobj, dobj;
+};
+
+// pobj and pinf at R, dobj at y (device y), lambda_min given.
+template <typename T>
+static alm_bm_status kkt_eval(alm_bm_problem* p, int r, const T* R, const double* y, double lam, KktVals& k,
+                              hipStream_t st) {
+  enqueue_objgrad<T>(p, r, R, y, 0.0, nullptr, p->Av, p->sc_api, 0, nullptr, st);
+  launch_dual(p->d.m, p->Av, p->d.b, y, nullptr, 0.0, p->part_vec, p->sc_api, p->bnorm, nullptr, st);
+  HIPCHK(hipMemcpyAsync(p->sc_host, p->sc_api, sizeof(DevScalars), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  HIPCHK(hipGetLastError());
+  const DevScalars& s = *p->sc_host;
+  k.pobj = s.tot[P_C0];
+  k.dobj = s.dobj;
+  k.pinf = s.pinf;
+  k.dinf = std::fabs(std::min(0.0, lam)) / (1.0 + p->cnorm);
+  k.gap = std::fabs(k.pobj - k.dobj) / (1.0 + std::fabs(k.pobj) + std::fabs(k.dobj));
+  k.kkt = std::max(k.pinf, std::max(k.dinf, k.gap));
+  return ALM_BM_OK;
+}
+
+extern "C" alm_bm_status alm_bm_kkt(alm_bm_problem* p, int32_t r, const void* R, const double* y, double lam_min,
+                                    double* kkt_out, hipStream_t st) {
+  if (!p || !R || !y || !kkt_out) return fail(ALM_BM_ERR_INVALID_ARG, "kkt: null argument");
+  STCHK(check_r(p, r));
+  KktVals k{};
+  alm_bm_status s = with_storage(p->d.precision, [&]<typename T>() {
+    return kkt_eval<T>(p, r, static_cast<const T*>(R), y, lam_min, k, st);
+  });
+  if (s < 0) return s;
+  kkt_out[0] = k.pinf;
+  kkt_out[1] = k.dinf;
+  kkt_out[2] = k.gap;
+  kkt_out[3] = k.kkt;
+  kkt_out[4] = k.pobj;
+  kkt_out[5] = k.dobj;
+  return ALM_BM_OK;
+}
+
+// --------------------------------------------------------------------- solve
+
+namespace {
+
+struct GraphCache {
+  hipGraphExec_t exec = nullptr;
+  hipGraph_t graph = nullptr;
+  int r = -1;
+  const void* R = nullptr;
+  void reset() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+    r = -1;
+    R = nullptr;
+  }
+  ~GraphCache() { reset(); }
+};
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+int bp_rank_cap(long m) {
+  long r = (long)((std::sqrt(8.0 * (double)m + 1.0) - 1.0) / 2.0);
+  while ((r + 1) * (r + 2) / 2 <= m) ++r;
+  while (r > 0 && r * (r + 1) / 2 > m) --r;
+  return (int)r;
+}
+
+}  // namespace
+
+template <typename T>
+static alm_bm_status inner_solve(alm_bm_problem* p, int r, T* R, const double* y, double sigma, double tol,
+                                 const alm_bm_options& o, GraphCache& gc, hipStream_t st, int& iters, int& flag) {
+  T* G = static_cast<T*>(p->G);
+  launch_inner_reset(p->sc_solve, tol, o.max_inner, (int)o.step_rule, o.eta_fixed, st);
+  const int U = std::max(0, o.graph_unroll);
+  int32_t hflag = 0;
+  const int max_launch = o.max_inner + 2;
+  int launched = 0;
+  while (true) {
+    if (U > 0) {
+      if (gc.r != r || gc.R != (const void*)R) {
+        gc.reset();
+        HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        for (int u = 0; u < U; ++u) enqueue_inner_step<T>(p, r, R, y, sigma, G, st);
+        HIPCHK(hipStreamEndCapture(st, &gc.graph));
+        HIPCHK(hipGraphInstantiate(&gc.exec, gc.graph, nullptr, nullptr, 0));
+        gc.r = r;
+        gc.R = R;
+      }
+      HIPCHK(hipGraphLaunch(gc.exec, st));
+      launched += U;
+    } else {
+      enqueue_inner_step<T>(p, r, R, y, sigma, G, st);
+      launched += 1;
+    }
+    HIPCHK(hipMemcpyAsync(&p->sc_host->flag, &p->sc_solve->flag, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    hflag = p->sc_host->flag;
+    if (hflag != 0) break;
+    if (launched > max_launch + U) return fail(ALM_BM_ERR_HIP, "inner loop did not reach its stop flag");
+  }
+  HIPCHK(hipGetLastError());
+  iters = p->sc_host->iter;
+  flag = hflag;
+  return ALM_BM_OK;
+}
+
+template <typename T>
+static alm_bm_status solve_impl(alm_bm_problem* p, const alm_bm_options& o, T* R, double* y, hipStream_t st,
+                                int& r, int k_start, int& k_done,
+                                bool stop_on_stall, bool& stalled, double t0, double& pinf_prev, double& tol_prev,
+                                alm_bm_result& acc) {
+  const auto& d = p->d;
+  const long n = d.n;
+  const double sigma = o.sigma;
+  const double tau_rank = o.tau_rank > 0.0 ? o.tau_rank : o.eps_kkt * (1.0 + p->cnorm);
+  int r_cap = std::min<int>(d.r_max, bp_rank_cap(d.m));
+  if (o.r_cap > 0) r_cap = std::min(r_cap, o.r_cap);
+  const int kmax = o.lanczos_kmax > 0 ? std::min(o.lanczos_kmax, p->kmax) : p->kmax;
+  const double ltol = o.lanczos_tol_rel * o.eps_kkt * (1.0 + p->cnorm);
+  GraphCache gc;
+  stalled = false;
+  std::vector<double> pinf_hist;
+  for (int k = k_start; k < o.max_outer; ++k) {
+    const double tol = std::max(o.eps_kkt / 10.0, std::min(o.inner_tol_scale, std::min(pinf_prev, o.inner_tol_decay * tol_prev)));
+    tol_prev = tol;
+    int iters = 0, flag = 0;
+    STCHK(inner_solve<T>(p, r, R, y, sigma, tol, o, gc, st, iters, flag));
+    acc.inner_total += iters;
+    // w = y - sigma (A(RR^T) - b) into ybuf (Av is current: the last pass ran at the final R)
+    launch_dual(d.m, p->Av, d.b, y, p->ybuf, sigma, p->part_vec, p->sc_solve, p->bnorm, nullptr, st);
+    LanczosOut lo;
+    const double tl = now_s();
+    STCHK(lanczos_run(p, p->ybuf, kmax, ltol, o.seed * 1000003ull + (uint64_t)k, p->lv, lo, st));
+    acc.time_lanczos_s += now_s() - tl;
+    bool expanded = false;
+    const bool gate = (flag == 1) || !o.expand_needs_inner;
+    if (o.rank_policy == ALM_BM_RANK_ADAPT && gate && lo.theta < -tau_rank && r < r_cap) {
+      // ||A(v v^T)||^2 for the unit Ritz vector
+      launch_quartic_norm(n, d.cons_kind == ALM_BM_CONS_DIAG ? 0 : 1, p->adj, p->lv, p->lpart2, p->lnb, st);
+      launch_fin_sum(p->lpart2, p->lnb, p->lscal + 3, 0, st);
+      double q4 = 0.0;
+      HIPCHK(hipMemcpyAsync(&q4, p->lscal + 3, sizeof(double), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      if (d.cons_kind != ALM_BM_CONS_DIAG) q4 += d.trace_coef * d.trace_coef;
+      if (q4 > 0.0) {
+        const double s = std::max(0.0, -lo.theta / (sigma * q4));
+        T* Rt = static_cast<T*>(p->Rtmp);
+        launch_relayout<T>(n, r, r + 1, R, Rt, p->lv, std::sqrt(s), st);
+        HIPCHK(hipMemcpyAsync(R, Rt, (size_t)n * (r + 1) * sizeof(T), hipMemcpyDeviceToDevice, st));
+        r += 1;
+        gc.reset();
+        expanded = true;
+        acc.expansions += 1;
+        enqueue_objgrad<T>(p, r, R, y, sigma, nullptr, p->Av, p->sc_api, 0, nullptr, st);
+        launch_dual(d.m, p->Av, d.b, y, p->ybuf, sigma, p->part_vec, p->sc_solve, p->bnorm, nullptr, st);
+      }
+    }
+    HIPCHK(hipMemcpyAsync(y, p->ybuf, d.m * sizeof(double), hipMemcpyDeviceToDevice, st));
+    double lam = lo.theta;
+    if (expanded) {
+      LanczosOut l2;
+      const double tl2 = now_s();
+      STCHK(lanczos_run(p, y, kmax, ltol, o.seed * 1000003ull + (uint64_t)k + 7777777ull, p->lv, l2, st));
+      acc.time_lanczos_s += now_s() - tl2;
+      lam = l2.theta;
+    }
+    KktVals kv{};
+    STCHK(kkt_eval<T>(p, r, R, y, lam, kv, st));
+    if (p->sc_host->numeric_error) return fail(ALM_BM_ERR_NUMERIC, "solve: NaN/Inf in objective or step");
+    HIPCHK(hipMemcpyAsync(p->sc_host, p->sc_solve, sizeof(DevScalars), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (p->sc_host->numeric_error) return fail(ALM_BM_ERR_NUMERIC, "solve: NaN/Inf in objective or step");
+    if (!std::isfinite(kv.kkt)) return fail(ALM_BM_ERR_NUMERIC, "solve: non-finite KKT");
+    acc.outer = k + 1;
+    acc.rank = r;
+    acc.pobj = kv.pobj;
+    acc.dobj = kv.dobj;
+    acc.pinf = kv.pinf;
+    acc.dinf = kv.dinf;
+    acc.gap = kv.gap;
+    acc.kkt = kv.kkt;
+    acc.lam_min = lam;
+    pinf_prev = kv.pinf;
+    k_done = k + 1;
+    if (o.verbose)
+      std::fprintf(stderr,
+                   "[almbm] k=%d inner=%d flag=%d r=%d theta=%.3e pinf=%.3e dinf=%.3e gap=%.3e pobj=%.10e t=%.2fs\n",
+                   k, iters, flag, r, lo.theta, kv.pinf, kv.dinf, kv.gap, kv.pobj, now_s() - t0);
+    if (kv.kkt <= o.eps_kkt) return ALM_BM_OK;
+    if (o.time_limit_s > 0.0 && now_s() - t0 > o.time_limit_s) return ALM_BM_NOT_CONVERGED;
+    if (stop_on_stall) {
+      // storage-precision floor: primal infeasibility no longer falls by 2x over 3 outer iterations
+      pinf_hist.push_back(kv.pinf);
+      const size_t h = pinf_hist.size();
+      if (h >= 4 && pinf_hist[h - 1] > 0.5 * pinf_hist[h - 4] && kv.pinf > o.eps_kkt) {
+        stalled = true;
+        return ALM_BM_NOT_CONVERGED;
+      }
+    }
+  }
+  return ALM_BM_NOT_CONVERGED;
+}
+
+extern "C" alm_bm_status alm_bm_solve(alm_bm_problem* p, const alm_bm_options* opts, void* R, int32_t* r_io,
+                                      double* y, alm_bm_result* out, hipStream_t st_user) {
+  if (!p || !R || !r_io || !y) return fail(ALM_BM_ERR_INVALID_ARG, "solve: null argument");
+  STCHK(check_r(p, *r_io));
+  alm_bm_options o;
+  if (opts) o = *opts;
+  else alm_bm_default_options(&o);
+  if (!(o.sigma > 0.0) || !(o.eps_kkt > 0.0) || o.max_outer < 1 || o.max_inner < 1)
+    return fail(ALM_BM_ERR_INVALID_ARG, "solve: sigma, eps_kkt, max_outer and max_inner must be positive");
+  if (p->kmax < 1) return fail(ALM_BM_ERR_INVALID_ARG, "solve: the handle has no Lanczos workspace");
+  HIPCHK(hipStreamSynchronize(st_user));
+  hipStream_t st = p->ss;
+  const double t0 = now_s();
+  alm_bm_result acc{};
+  acc.promoted_at_outer = -1;
+  int r = *r_io;
+  int k_done = 0;
+  double pinf_prev = INFINITY, tol_prev = INFINITY;
+  bool stalled = false;
+  alm_bm_status s;
+  if (p->d.precision == ALM_BM_BF16 && o.bf16_promote) {
+    s = solve_impl<bf16>(p, o, static_cast<bf16*>(R), y, st, r, 0, k_done, true, stalled, t0, pinf_prev, tol_prev,
+                         acc);
+    if (s < 0) return s;
+    if (stalled) {
+      // precision ladder: continue with float storage (the float cost copy is resident)
+      const long n = p->d.n;
+      const size_t bytes = (size_t)n * p->d.r_max * sizeof(float);
+      if (!p->R32) {
+        STCHK(dalloc(p, &p->R32, bytes));
+        STCHK(dalloc(p, &p->G32, bytes));
+        STCHK(dalloc(p, &p->Rt32, bytes));
+      }
+      launch_convert<bf16, float>((long)n * r, static_cast<const bf16*>(R), static_cast<float*>(p->R32), st);
+      void* Gsave = p->G;
+      void* Rtsave = p->Rtmp;
+      p->G = p->G32;
+      p->Rtmp = p->Rt32;
+      const double tp = now_s();
+      acc.promoted_at_outer = k_done;
+      s = solve_impl<float>(p, o, static_cast<float*>(p->R32), y, st, r, k_done, k_done, false, stalled, t0,
+                            pinf_prev, tol_prev, acc);
+      p->G = Gsave;
+      p->Rtmp = Rtsave;
+      acc.time_promoted_s = now_s() - tp;
+      launch_convert<float, bf16>((long)n * r, static_cast<const float*>(p->R32), static_cast<bf16*>(R), st);
+      HIPCHK(hipStreamSynchronize(st));
+      if (s < 0) return s;
+    }
+  } else {
+    s = with_storage(p->d.precision, [&]<typename T>() {
+      return solve_impl<T>(p, o, static_cast<T*>(R), y, st, r, 0, k_done, false, stalled, t0, pinf_prev, tol_prev,
+                           acc);
+    });
+    if (s < 0) return s;
+  }
+  HIPCHK(hipStreamSynchronize(st));
+  *r_io = r;
+  acc.rank = r;
+  acc.time_s = now_s() - t0;
+  if (out) *out = acc;
+  return s;
+}

@@ -1,0 +1,470 @@
+// Row kernels for the TRACE_EDGES constraint family: A_0 = c_tr I and, per
+// edge e = {i, j}, A_{1+e} = (e_i e_j^T + e_j e_i^T)/2 (entry constraints as in
+// the examples of Sec. 3.3 / Sec. 4.3; with C = -J they give the Lovasz-theta
+// SDP).  Cost C = S + Diag(d) - j J.
+//
+// Pass 1 (SDDMM): a_{1+e} = <R_i, R_j> for every edge from the upper half of
+//   the pattern (each edge once, edge order = position), w_e = y_e - sigma
+//   (a_e - b_e), plus column sums 1^T R and ||R||^2 for the trace row and J.
+// Pass 2 (SpMM): G_i = 2 (P_i - c_tr w_0 R_i - 1/2 sum_{j~i} w_{e(ij)} R_j) with
+//   P_i = (S R)_i + d_i R_i - j (1^T R); the symmetric pattern carries edge ids.
+// Pass 3 (line search): a1_e = <R_i,G_j> + <G_i,R_j>, a2_e = <G_i,G_j> over the
+//   upper half and <G, (S + D) G>.
+#include "spmm_row.hpp"
+#include "quartic.hpp"
+
+namespace almbm {
+
+constexpr int kEdgePS = NUM_P + kMaxR;  // partial stride: scalars, then r column sums
+
+// Sum over the lanes of a block that share the same lane-in-row index (i.e.
+// over row groups) of a VEC-wide fragment, deterministic; thread t < LPR of the
+// first wave ends with the block totals for columns [t*VEC, t*VEC+VEC).
+template <int LPR, int VEC>
+__device__ __forceinline__ void block_colsum_store(double (&cs)[VEC], int r, double* __restrict__ out) {
+  __shared__ double red[kBlock / kWave][LPR * VEC];
+  const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+#pragma unroll
+  for (int v = 0; v < VEC; ++v) {
+    double x = cs[v];
+    for (int o = kWave / 2; o >= LPR; o >>= 1) x += __shfl_xor(x, o, kWave);
+    cs[v] = x;
+  }
+  if (lane < LPR) {
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) red[wave][lane * VEC + v] = cs[v];
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < LPR * VEC; c += kBlock) {
+    double t = 0.0;
+    for (int w = 0; w < kBlock / kWave; ++w) t += red[w][c];
+    if (c < r) out[c] = t;
+  }
+}
+
+template <typename T, int LPR, int VEC, bool FULL>
+__global__ void __launch_bounds__(kBlock)
+k_edges_p1(EdgeAdj A, long n, int r, const T* __restrict__ R, const double* __restrict__ y,
+           const double* __restrict__ b, double sigma, double* __restrict__ Av, double* __restrict__ wE,
+           double* __restrict__ part, const DevScalars* __restrict__ sc) {
+  using V = typename Acc<T>::type;
+  if (sc && sc->flag) return;
+  constexpr int RPB = kBlock / LPR;
+  const int lane = threadIdx.x % LPR;
+  const int slot = threadIdx.x / LPR;
+  double acc[NUM_P];
+#pragma unroll
+  for (int s = 0; s < NUM_P; ++s) acc[s] = 0.0;
+  double cs[VEC];
+#pragma unroll
+  for (int v = 0; v < VEC; ++v) cs[v] = 0.0;
+  const RowChunk ch = row_chunk(n);
+  for (long base = ch.lo; base < ch.hi; base += RPB) {
+    const long i = base + slot;
+    if (i >= ch.hi) break;
+    V ri[VEC];
+    load_frag<T, VEC, FULL>(R + i * r, lane, r, ri);
+    V rr = 0;
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) {
+      rr += ri[v] * ri[v];
+      cs[v] += (double)ri[v];
+    }
+    rr = group_sum<LPR>(rr);
+    const int k0 = A.urp[i], k1 = A.urp[i + 1];
+    for (int k = k0; k < k1; ++k) {
+      const int j = A.uci[k];
+      V rj[VEC];
+      load_frag<T, VEC, FULL>(R + (long)j * r, lane, r, rj);
+      V s = 0;
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) s += ri[v] * rj[v];
+      s = group_sum<LPR>(s);
+      if (lane == 0) {
+        const double a = s, be = b[1 + k], ye = y[1 + k];
+        const double e = a - be;
+        if (Av) Av[1 + k] = a;
+        wE[k] = ye - sigma * e;
+        acc[P_YBMA] += ye * (be - a);
+        acc[P_EE] += e * e;
+      }
+    }
+    if (lane == 0) acc[P_RR] += (double)rr;
+  }
+  block_sum_store<NUM_P>(acc, part + (long)blockIdx.x * kEdgePS);
+  block_colsum_store<LPR, VEC>(cs, r, part + (long)blockIdx.x * kEdgePS + NUM_P);
+}
+
+// Finalize of pass 1: trace row, w_0, column sums; writes Av[0].
+__global__ void __launch_bounds__(kBlock)
+k_fin_edges1(const double* __restrict__ part, int nb, int r, DevScalars* __restrict__ sc, const double* __restrict__ y,
+             const double* __restrict__ b, double sigma, double c_tr, double* __restrict__ Av) {
+  if (sc->flag) return;
+  // scalars
+  __shared__ double red[kBlock / kWave];
+  double tot3[3];
+  const int sl[3] = {P_YBMA, P_EE, P_RR};
+  for (int q = 0; q < 3; ++q) {
+    double a = 0.0;
+    for (int bi = threadIdx.x; bi < nb; bi += kBlock) a += part[(long)bi * kEdgePS + sl[q]];
+    a = wave_sum(a);
+    if (threadIdx.x % kWave == 0) red[threadIdx.x / kWave] = a;
+    __syncthreads();
+    double t = 0.0;
+    for (int w = 0; w < kBlock / kWave; ++w) t += red[w];
+    tot3[q] = t;
+    __syncthreads();
+  }
+  // column sums: one thread per column, blocks in order
+  for (int c = threadIdx.x; c < r; c += kBlock) {
+    double a = 0.0;
+    for (int bi = 0; bi < nb; ++bi) a += part[(long)bi * kEdgePS + NUM_P + c];
+    sc->colsum[c] = a;
+  }
+  if (threadIdx.x == 0) {
+    const double rr = tot3[2];
+    const double a0 = c_tr * rr;
+    const double e0 = a0 - b[0];
+    sc->a0 = a0;
+    sc->w0 = y[0] - sigma * e0;
+    if (Av) Av[0] = a0;
+    sc->tot[P_YBMA] = tot3[0] + y[0] * (b[0] - a0);
+    sc->tot[P_EE] = tot3[1] + e0 * e0;
+    sc->tot[P_RR] = rr;
+  }
+}
+
+// Pass 2: P = C R, gradient and its partials.  If G_in is given, the direction
+// is read instead of computed (line-search API) and nothing is written.
+template <typename T, int LPR, int VEC, bool FULL>
+__global__ void __launch_bounds__(kBlock)
+k_edges_p2(Cost<typename Acc<T>::type> C, EdgeAdj A, int r, const T* __restrict__ R,
+           const double* __restrict__ wE, double c_tr, double j_coef, const T* __restrict__ G_in,
+           T* __restrict__ G, double* __restrict__ part, const DevScalars* __restrict__ sc) {
+  using V = typename Acc<T>::type;
+  if (sc->flag) return;
+  constexpr int RPB = kBlock / LPR;
+  const int lane = threadIdx.x % LPR;
+  const int slot = threadIdx.x / LPR;
+  double acc[NUM_P];
+#pragma unroll
+  for (int s = 0; s < NUM_P; ++s) acc[s] = 0.0;
+  double gcs[VEC];
+  V jcs[VEC];
+#pragma unroll
+  for (int v = 0; v < VEC; ++v) {
+    gcs[v] = 0.0;
+    const int c = lane * VEC + v;
+    jcs[v] = (c < r && j_coef != 0.0) ? static_cast<V>(j_coef * sc->colsum[c]) : V(0);
+  }
+  const V cw0 = static_cast<V>(c_tr * sc->w0);
+  const RowChunk ch = row_chunk(C.n);
+  for (long base = ch.lo; base < ch.hi; base += RPB) {
+    const long i = base + slot;
+    if (i >= ch.hi) break;
+    V ri[VEC], p[VEC], ad[VEC];
+    load_frag<T, VEC, FULL>(R + i * r, lane, r, ri);
+    spmm_row<T, LPR, VEC, FULL>(C, i, lane, r, R, ri, p);
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) {
+      p[v] -= jcs[v];
+      ad[v] = cw0 * ri[v];
+    }
+    const int k0 = A.rp[i], k1 = A.rp[i + 1];
+    for (int k = k0; k < k1; ++k) {
+      const int j = A.ci[k];
+      const V we = static_cast<V>(0.5 * wE[A.eid[k]]);
+      V rj[VEC];
+      load_frag<T, VEC, FULL>(R + (long)j * r, lane, r, rj);
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) ad[v] += we * rj[v];
+    }
+    V g[VEC];
+    if (G_in) {
+      load_frag<T, VEC, FULL>(G_in + i * r, lane, r, g);
+    } else {
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) g[v] = round_st<T>(V(2) * (p[v] - ad[v]));
+      if (G) store_frag<T, VEC, FULL>(G + i * r, lane, r, g);
+    }
+    V rp = 0, gg = 0, gp = 0, rg = 0;
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) {
+      rp += ri[v] * p[v];
+      gg += g[v] * g[v];
+      gp += g[v] * p[v];
+      rg += ri[v] * g[v];
+      gcs[v] += (double)g[v];
+    }
+    rp = group_sum<LPR>(rp);
+    gg = group_sum<LPR>(gg);
+    gp = group_sum<LPR>(gp);
+    rg = group_sum<LPR>(rg);
+    if (lane == 0) {
+      acc[P_C0] += (double)rp;
+      acc[P_GG] += (double)gg;
+      acc[P_GP] += (double)gp;
+      acc[P_RG] += (double)rg;
+    }
+  }
+  block_sum_store<NUM_P>(acc, part + (long)blockIdx.x * kEdgePS);
+  block_colsum_store<LPR, VEC>(gcs, r, part + (long)blockIdx.x * kEdgePS + NUM_P);
+}
+
+// Finalize of pass 2: objective and (mode 1) the inner stop test.
+__global__ void __launch_bounds__(kBlock)
+k_fin_edges2(const double* __restrict__ part, int nb, int r, DevScalars* __restrict__ sc, double sigma, int mode,
+             double* __restrict__ f_out) {
+  if (sc->flag) return;
+  __shared__ double red[kBlock / kWave];
+  double tot4[4];
+  const int sl[4] = {P_C0, P_GG, P_GP, P_RG};
+  for (int q = 0; q < 4; ++q) {
+    double a = 0.0;
+    for (int bi = threadIdx.x; bi < nb; bi += kBlock) a += part[(long)bi * kEdgePS + sl[q]];
+    a = wave_sum(a);
+    if (threadIdx.x % kWave == 0) red[threadIdx.x / kWave] = a;
+    __syncthreads();
+    double t = 0.0;
+    for (int w = 0; w < kBlock / kWave; ++w) t += red[w];
+    tot4[q] = t;
+    __syncthreads();
+  }
+  for (int c = threadIdx.x; c < r; c += kBlock) {
+    double a = 0.0;
+    for (int bi = 0; bi < nb; ++bi) a += part[(long)bi * kEdgePS + NUM_P + c];
+    sc->gcolsum[c] = a;
+  }
+  if (threadIdx.x != 0) return;
+  sc->tot[P_C0] = tot4[0];
+  sc->tot[P_GG] = tot4[1];
+  sc->tot[P_GP] = tot4[2];
+  sc->tot[P_RG] = tot4[3];
+  const double f = tot4[0] + sc->tot[P_YBMA] + 0.5 * sigma * sc->tot[P_EE];
+  sc->f = f;
+  if (!isfinite(f) || !isfinite(tot4[1])) sc->numeric_error = 1;
+  if (f_out) *f_out = f;
+  if (mode == 1) {
+    const double lhs = sqrt(tot4[1]) * sqrt(sc->tot[P_RR]);
+    if (sc->iter >= sc->max_inner) sc->flag = 2;
+    else if (lhs <= sc->tol * (1.0 + fabs(tot4[0])) || !isfinite(lhs)) sc->flag = 1;
+    else sc->iter += 1;
+  }
+}
+
+// Pass 3: line-search partials over the edges and <G, (S + D) G>.
+template <typename T, int LPR, int VEC, bool FULL>
+__global__ void __launch_bounds__(kBlock)
+k_edges_p3(Cost<typename Acc<T>::type> C, EdgeAdj A, int r, const T* __restrict__ R, const T* __restrict__ G,
+           const double* __restrict__ y, const double* __restrict__ b, const double* __restrict__ Av,
+           double* __restrict__ part, const DevScalars* __restrict__ sc) {
+  using V = typename Acc<T>::type;
+  if (sc->flag) return;
+  constexpr int RPB = kBlock / LPR;
+  const int lane = threadIdx.x % LPR;
+  const int slot = threadIdx.x / LPR;
+  double acc[NUM_P];
+#pragma unroll
+  for (int s = 0; s < NUM_P; ++s) acc[s] = 0.0;
+  const RowChunk ch = row_chunk(C.n);
+  for (long base = ch.lo; base < ch.hi; base += RPB) {
+    const long i = base + slot;
+    if (i >= ch.hi) break;
+    V ri[VEC], gi[VEC], q[VEC];
+    load_frag<T, VEC, FULL>(R + i * r, lane, r, ri);
+    load_frag<T, VEC, FULL>(G + i * r, lane, r, gi);
+    spmm_row<T, LPR, VEC, FULL>(C, i, lane, r, G, gi, q);
+    V gq = 0;
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) gq += gi[v] * q[v];
+    gq = group_sum<LPR>(gq);
+    if (lane == 0) acc[P_C2] += (double)gq;
+    const int k0 = A.urp[i], k1 = A.urp[i + 1];
+    for (int k = k0; k < k1; ++k) {
+      const int j = A.uci[k];
+      V rj[VEC], gj[VEC];
+      load_frag<T, VEC, FULL>(R + (long)j * r, lane, r, rj);
+      load_frag<T, VEC, FULL>(G + (long)j * r, lane, r, gj);
+      V a1 = 0, a2 = 0;
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) {
+        a1 += ri[v] * gj[v] + gi[v] * rj[v];
+        a2 += gi[v] * gj[v];
+      }
+      a1 = group_sum<LPR>(a1);
+      a2 = group_sum<LPR>(a2);
+      if (lane == 0) {
+        const double ye = y[1 + k], e = Av[1 + k] - b[1 + k];
+        const double d1 = a1, d2 = a2;
+        acc[P_YA1] += ye * d1;
+        acc[P_YA2] += ye * d2;
+        acc[P_EA1] += e * d1;
+        acc[P_EA2] += e * d2;
+        acc[P_A1A1] += d1 * d1;
+        acc[P_A1A2] += d1 * d2;
+        acc[P_A2A2] += d2 * d2;
+      }
+    }
+  }
+  block_sum_store<NUM_P>(acc, part + (long)blockIdx.x * kEdgePS);
+}
+
+// Finalize of pass 3: add the trace row and the -jJ terms, then the step.
+
+__global__ void __launch_bounds__(kBlock)
+k_fin_edges3(const double* __restrict__ part, int nb, int r, DevScalars* __restrict__ sc, const double* __restrict__ y,
+             const double* __restrict__ b, double sigma, double c_tr, double j_coef, int mode,
+             double* __restrict__ coeffs_out, double* __restrict__ t_out) {
+  if (mode == 1 && sc->flag) return;
+  __shared__ double red[kBlock / kWave];
+  const int sl[8] = {P_C2, P_YA1, P_YA2, P_EA1, P_EA2, P_A1A1, P_A1A2, P_A2A2};
+  double tot8[8];
+  for (int q = 0; q < 8; ++q) {
+    double a = 0.0;
+    for (int bi = threadIdx.x; bi < nb; bi += kBlock) a += part[(long)bi * kEdgePS + sl[q]];
+    a = wave_sum(a);
+    if (threadIdx.x % kWave == 0) red[threadIdx.x / kWave] = a;
+    __syncthreads();
+    double t = 0.0;
+    for (int w = 0; w < kBlock / kWave; ++w) t += red[w];
+    tot8[q] = t;
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  double gj2 = 0.0;
+  for (int c = 0; c < r; ++c) gj2 += sc->gcolsum[c] * sc->gcolsum[c];
+  const double a1_0 = 2.0 * c_tr * sc->tot[P_RG];
+  const double a2_0 = c_tr * sc->tot[P_GG];
+  const double e0 = sc->a0 - b[0];
+  double* tot = sc->tot;
+  tot[P_C2] = tot8[0] - j_coef * gj2;
+  tot[P_YA1] = tot8[1] + y[0] * a1_0;
+  tot[P_YA2] = tot8[2] + y[0] * a2_0;
+  tot[P_EA1] = tot8[3] + e0 * a1_0;
+  tot[P_EA2] = tot8[4] + e0 * a2_0;
+  tot[P_A1A1] = tot8[5] + a1_0 * a1_0;
+  tot[P_A1A2] = tot8[6] + a1_0 * a2_0;
+  tot[P_A2A2] = tot8[7] + a2_0 * a2_0;
+  double k[5];
+  quartic_coeffs(tot, sigma, k);
+  for (int s = 0; s < 5; ++s) sc->coeffs[s] = k[s];
+  double t = (mode == 1 && sc->step_rule == 1) ? sc->eta_fixed : quartic_argmin(k);
+  if (!isfinite(t)) {
+    t = 0.0;
+    sc->numeric_error = 1;
+  }
+  sc->t = t;
+  if (coeffs_out)
+    for (int s = 0; s < 5; ++s) coeffs_out[s] = k[s];
+  if (t_out) *t_out = t;
+}
+
+// ---- launchers -----------------------------------------------------------------
+
+#define ALMBM_DISPATCH_EDGES(T, FN, ...)                                \
+  do {                                                                  \
+    if constexpr (sizeof(T) == 8) {                                     \
+      if (r <= 4) FN<T, 4, 1>(__VA_ARGS__);                             \
+      else if (r <= 8) FN<T, 8, 1>(__VA_ARGS__);                        \
+      else if (r <= 16) FN<T, 8, 2>(__VA_ARGS__);                       \
+      else if (r <= 32) FN<T, 8, 4>(__VA_ARGS__);                       \
+      else if (r <= 64) FN<T, 16, 4>(__VA_ARGS__);                      \
+      else FN<T, 32, 4>(__VA_ARGS__);                                   \
+    } else if constexpr (sizeof(T) == 4) {                              \
+      if (r <= 4) FN<T, 4, 1>(__VA_ARGS__);                             \
+      else if (r <= 8) FN<T, 4, 2>(__VA_ARGS__);                        \
+      else if (r <= 16) FN<T, 4, 4>(__VA_ARGS__);                       \
+      else if (r <= 32) { if (variant == 1) FN<T, 4, 8>(__VA_ARGS__); else FN<T, 8, 4>(__VA_ARGS__); } \
+      else if (r <= 64) FN<T, 16, 4>(__VA_ARGS__);                      \
+      else FN<T, 32, 4>(__VA_ARGS__);                                   \
+    } else {                                                            \
+      if (r <= 4) FN<T, 2, 2>(__VA_ARGS__);                             \
+      else if (r <= 8) FN<T, 2, 4>(__VA_ARGS__);                        \
+      else if (r <= 16) FN<T, 2, 8>(__VA_ARGS__);                       \
+      else if (r <= 32) FN<T, 4, 8>(__VA_ARGS__);                       \
+      else if (r <= 64) FN<T, 8, 8>(__VA_ARGS__);                       \
+      else FN<T, 16, 8>(__VA_ARGS__);                                   \
+    }                                                                   \
+  } while (0)
+
+template <typename T, int LPR, int VEC>
+static void p1_cfg(const EdgeAdj& A, long n, int r, const T* R, const double* y, const double* b, double sigma,
+                   double* Av, double* wE, double* part, const DevScalars* sc, int nblk, hipStream_t st) {
+  if (r == LPR * VEC)
+    hipLaunchKernelGGL((k_edges_p1<T, LPR, VEC, true>), dim3(nblk), dim3(kBlock), 0, st, A, n, r, R, y, b, sigma,
+                       Av, wE, part, sc);
+  else
+    hipLaunchKernelGGL((k_edges_p1<T, LPR, VEC, false>), dim3(nblk), dim3(kBlock), 0, st, A, n, r, R, y, b, sigma,
+                       Av, wE, part, sc);
+}
+template <typename T, int LPR, int VEC>
+static void p2_cfg(const Cost<typename Acc<T>::type>& C, const EdgeAdj& A, int r, const T* R, const double* wE,
+                   double c_tr, double j_coef, const T* G_in, T* G, double* part, const DevScalars* sc, int nblk,
+                   hipStream_t st) {
+  if (r == LPR * VEC)
+    hipLaunchKernelGGL((k_edges_p2<T, LPR, VEC, true>), dim3(nblk), dim3(kBlock), 0, st, C, A, r, R, wE, c_tr,
+                       j_coef, G_in, G, part, sc);
+  else
+    hipLaunchKernelGGL((k_edges_p2<T, LPR, VEC, false>), dim3(nblk), dim3(kBlock), 0, st, C, A, r, R, wE, c_tr,
+                       j_coef, G_in, G, part, sc);
+}
+template <typename T, int LPR, int VEC>
+static void p3_cfg(const Cost<typename Acc<T>::type>& C, const EdgeAdj& A, int r, const T* R, const T* G,
+                   const double* y, const double* b, const double* Av, double* part, const DevScalars* sc, int nblk,
+                   hipStream_t st) {
+  if (r == LPR * VEC)
+    hipLaunchKernelGGL((k_edges_p3<T, LPR, VEC, true>), dim3(nblk), dim3(kBlock), 0, st, C, A, r, R, G, y, b, Av,
+                       part, sc);
+  else
+    hipLaunchKernelGGL((k_edges_p3<T, LPR, VEC, false>), dim3(nblk), dim3(kBlock), 0, st, C, A, r, R, G, y, b, Av,
+                       part, sc);
+}
+
+template <typename T>
+void launch_edges_p1(const EdgeAdj& A, long n, int r, int variant, const T* R, const double* y, const double* b,
+                     double sigma, double* Av, double* wE, double* part, const DevScalars* sc, int nblk,
+                     hipStream_t st) {
+  ALMBM_DISPATCH_EDGES(T, p1_cfg, A, n, r, R, y, b, sigma, Av, wE, part, sc, nblk, st);
+}
+template <typename T>
+void launch_edges_p2(const Cost<typename Acc<T>::type>& C, const EdgeAdj& A, int r, int variant, const T* R,
+                     const double* wE, double c_tr, double j_coef, const T* G_in, T* G, double* part,
+                     const DevScalars* sc, int nblk, hipStream_t st) {
+  ALMBM_DISPATCH_EDGES(T, p2_cfg, C, A, r, R, wE, c_tr, j_coef, G_in, G, part, sc, nblk, st);
+}
+template <typename T>
+void launch_edges_p3(const Cost<typename Acc<T>::type>& C, const EdgeAdj& A, int r, int variant, const T* R,
+                     const T* G, const double* y, const double* b, const double* Av, double* part,
+                     const DevScalars* sc, int nblk, hipStream_t st) {
+  ALMBM_DISPATCH_EDGES(T, p3_cfg, C, A, r, R, G, y, b, Av, part, sc, nblk, st);
+}
+
+void launch_fin_edges1(const double* part, int nb, int r, DevScalars* sc, const double* y, const double* b,
+                       double sigma, double c_tr, double* Av, hipStream_t st) {
+  hipLaunchKernelGGL(k_fin_edges1, dim3(1), dim3(kBlock), 0, st, part, nb, r, sc, y, b, sigma, c_tr, Av);
+}
+void launch_fin_edges2(const double* part, int nb, int r, DevScalars* sc, double sigma, int mode, double* f_out,
+                       hipStream_t st) {
+  hipLaunchKernelGGL(k_fin_edges2, dim3(1), dim3(kBlock), 0, st, part, nb, r, sc, sigma, mode, f_out);
+}
+void launch_fin_edges3(const double* part, int nb, int r, DevScalars* sc, const double* y, const double* b,
+                       double sigma, double c_tr, double j_coef, int mode, double* coeffs_out, double* t_out,
+                       hipStream_t st) {
+  hipLaunchKernelGGL(k_fin_edges3, dim3(1), dim3(kBlock), 0, st, part, nb, r, sc, y, b, sigma, c_tr, j_coef, mode,
+                     coeffs_out, t_out);
+}
+
+#define ALMBM_INST_E(T)                                                                                        \
+  template void launch_edges_p1<T>(const EdgeAdj&, long, int, int, const T*, const double*, const double*, double, \
+                                   double*, double*, double*, const DevScalars*, int, hipStream_t);            \
+  template void launch_edges_p2<T>(const Cost<Acc<T>::type>&, const EdgeAdj&, int, int, const T*, const double*, \
+                                   double, double, const T*, T*, double*, const DevScalars*, int, hipStream_t); \
+  template void launch_edges_p3<T>(const Cost<Acc<T>::type>&, const EdgeAdj&, int, int, const T*, const T*,     \
+                                   const double*, const double*, const double*, double*, const DevScalars*, int, \
+                                   hipStream_t);
+
+ALMBM_INST_E(double)
+ALMBM_INST_E(float)
+ALMBM_INST_E(bf16)
+
+}  // namespace almbm

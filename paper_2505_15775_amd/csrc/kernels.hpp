@@ -1,0 +1,74 @@
+// Kernel argument structures, device scalar block and launcher declarations.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.hpp"
+
+namespace almbm {
+
+// Per-row partial sums produced by the objective/gradient pass.  Index names
+// follow the quartic line search: a1 = A(RG^T + GR^T), a2 = A(GG^T), e = A(RR^T) - b.
+enum PartialSlot {
+  P_C0 = 0,    // <C, RR^T> (cost part; the -j J part is added at finalize)
+  P_YBMA,      // <y, b - a>
+  P_EE,        // ||e||^2
+  P_GG,        // ||G||_F^2
+  P_GP,        // <G, CR>
+  P_YA1, P_YA2, P_EA1, P_EA2, P_A1A1, P_A1A2, P_A2A2,
+  P_RR,        // ||R||_F^2
+  P_RG,        // <R, G>      (edge family trace terms)
+  P_C2,        // <G, CG>     (cost part)
+  NUM_P
+};
+
+constexpr int kMaxR = 128;
+
+// Device-resident scalars of one handle.  Written by finalize kernels so that
+// the inner loop needs no host round trip; the host reads them after syncs.
+struct DevScalars {
+  double tot[NUM_P];
+  double f;               // objective at the current R
+  double coeffs[5];       // quartic phi(t) coefficients
+  double t;               // step chosen
+  double tol;             // inner stop tolerance (host sets per outer iteration)
+  double sigma;
+  double eta_fixed;
+  double pinf;
+  double dobj;
+  double res2;
+  double w0;              // edge family: trace-row multiplier y0 - sigma (a0 - b0)
+  double a0;              // edge family: trace_coef ||R||^2
+  double qsum;            // sum of a Lanczos vector (for the -j J term)
+  double colsum[kMaxR];   // edge family / J term: 1^T R
+  double gcolsum[kMaxR];  // 1^T G
+  int32_t flag;           // 0 running, 1 inner tolerance met, 2 max_inner reached
+  int32_t iter;           // inner iterations taken
+  int32_t max_inner;
+  int32_t step_rule;      // 0 exact, 1 fixed
+  int32_t numeric_error;  // set when a finalize sees NaN/Inf
+  int32_t pad;
+};
+
+// Sparse symmetric cost S (off-diagonal) + diagonal, in arithmetic type V.
+template <typename V> struct Cost {
+  long n;
+  const int32_t* rp;   // CSR row pointers (nullptr for ELL)
+  const int32_t* ci;
+  const V* cv;
+  int32_t ell;         // > 0: ELL width
+  const V* dg;         // nullable
+};
+
+// Edge family adjacency: symmetric pattern with edge ids, plus the upper
+// (i < j) half in edge order (edge e sits at position e of the upper arrays).
+struct EdgeAdj {
+  const int32_t* rp;    // n+1, symmetric
+  const int32_t* ci;    // 2E
+  const int32_t* eid;   // 2E
+  const int32_t* urp;   // n+1, upper half; urp[i]..urp[i+1] are edges with ei = i
+  const int32_t* uci;   // E, = edge_j in edge order
+};
+
+}  // namespace almbm

@@ -1,0 +1,256 @@
+// Lanczos for lambda_min of the dual slack Z(y) = C - A*(y) (Sec. 1.2), used
+// by the KKT measure of Sec. 6 and the rank test of Alg. 1.  Everything in FP64:
+// the matrix-free product, dot products and the full reorthogonalisation
+// (classical Gram-Schmidt applied twice) against the stored basis Q
+// (column-major, n x (k+1), leading dimension ldq).
+#include "kernels.hpp"
+
+namespace almbm {
+
+constexpr int kSpmvLpr = 4;  // lanes per row in the slack product (avg degree ~ 8)
+
+// out_i = (Z(y) x)_i.  DIAG: (d_i - y_i) x_i + sum_k S_ik x_k.
+// TRACE_EDGES: (S x)_i + d_i x_i - j (1^T x) - c_tr y_0 x_i - 1/2 sum_{k~i} y_{1+e(ik)} x_k.
+__global__ void __launch_bounds__(kBlock)
+k_slack_mv(Cost<double> C, int cons_kind, EdgeAdj A, const double* __restrict__ y, double c_tr, double j_coef,
+           const DevScalars* __restrict__ sc, const double* __restrict__ x, double* __restrict__ out) {
+  constexpr int L = kSpmvLpr;
+  const long i = ((long)blockIdx.x * kBlock + threadIdx.x) / L;
+  const int lane = threadIdx.x % L;
+  if (i >= C.n) return;
+  double acc = 0.0;
+  long k0 = 0, k1 = 0;
+  if (C.ell > 0) {
+    k0 = i * (long)C.ell;
+    k1 = k0 + C.ell;
+  } else if (C.rp) {
+    k0 = C.rp[i];
+    k1 = C.rp[i + 1];
+  }
+  for (long k = k0 + lane; k < k1; k += L) acc += C.cv[k] * x[C.ci[k]];
+  if (cons_kind == 1) {
+    const int a0 = A.rp[i], a1 = A.rp[i + 1];
+    for (int k = a0 + lane; k < a1; k += L) acc -= 0.5 * y[1 + A.eid[k]] * x[A.ci[k]];
+  }
+  acc = group_sum<L>(acc);
+  if (lane == 0) {
+    const double xi = x[i];
+    double d = C.dg ? C.dg[i] : 0.0;
+    if (cons_kind == 0) d -= y[i];
+    else d -= c_tr * y[0];
+    double v = acc + d * xi;
+    if (j_coef != 0.0) v -= j_coef * sc->qsum;
+    out[i] = v;
+  }
+}
+
+// partials[b][c] = sum over the block's rows of Q[c][i] * w[i], c < ncol.
+// Wave w of the block handles columns c = w, w+4, ...; lanes stride the rows.
+__global__ void __launch_bounds__(kBlock)
+k_dots(long n, int ncol, const double* __restrict__ Q, long ldq, const double* __restrict__ w,
+       double* __restrict__ part, int pstride) {
+  const RowChunk ch = row_chunk(n);
+  const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+  for (int c = wave; c < ncol; c += kBlock / kWave) {
+    const double* q = Q + (long)c * ldq;
+    double a = 0.0;
+    for (long i = ch.lo + lane; i < ch.hi; i += kWave) a += q[i] * w[i];
+    a = wave_sum(a);
+    if (lane == 0) part[(long)blockIdx.x * pstride + c] = a;
+  }
+}
+
+// h[c] = sum of partials over blocks (in block order); optionally accumulates
+// into alpha (alpha[j] += h[j]) for the Lanczos diagonal.
+__global__ void __launch_bounds__(kBlock)
+k_fin_dots(const double* __restrict__ part, int nb, int pstride, int ncol, double* __restrict__ h) {
+  for (int c = threadIdx.x; c < ncol; c += kBlock) {
+    double a = 0.0;
+    for (int b = 0; b < nb; ++b) a += part[(long)b * pstride + c];
+    h[c] = a;
+  }
+}
+
+// w_i -= sum_c Q[c][i] h[c]; partial ||w||^2 per block.
+__global__ void __launch_bounds__(kBlock)
+k_sub(long n, int ncol, const double* __restrict__ Q, long ldq, const double* __restrict__ h, double* __restrict__ w,
+      double* __restrict__ part) {
+  __shared__ double hs[512 + 1];
+  for (int c = threadIdx.x; c < ncol; c += kBlock) hs[c] = h[c];
+  __syncthreads();
+  const RowChunk ch = row_chunk(n);
+  double acc[1] = {0.0};
+  for (long i = ch.lo + threadIdx.x; i < ch.hi; i += kBlock) {
+    double v = w[i];
+    for (int c = 0; c < ncol; ++c) v -= Q[(long)c * ldq + i] * hs[c];
+    w[i] = v;
+    acc[0] += v * v;
+  }
+  block_sum_store<1>(acc, part + blockIdx.x);
+}
+
+// Tridiagonal entries after the two projections: alpha_j = h1[j] + h2[j],
+// beta_j = ||w||.
+__global__ void __launch_bounds__(kBlock)
+k_fin_ab(const double* __restrict__ part, int nb, const double* __restrict__ h1, const double* __restrict__ h2, int j,
+         double* __restrict__ alpha, double* __restrict__ beta) {
+  __shared__ double red[kBlock / kWave];
+  double a = 0.0;
+  for (int b = threadIdx.x; b < nb; b += kBlock) a += part[b];
+  a = wave_sum(a);
+  if (threadIdx.x % kWave == 0) red[threadIdx.x / kWave] = a;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < kBlock / kWave; ++w) t += red[w];
+    alpha[j] = h1[j] + h2[j];
+    beta[j] = sqrt(t);
+  }
+}
+
+// q = w / beta (beta > 0), partial sums of q for the -jJ term.
+__global__ void __launch_bounds__(kBlock)
+k_scale(long n, const double* __restrict__ w, const double* __restrict__ beta_ptr, double* __restrict__ q,
+        double* __restrict__ part) {
+  const double beta = *beta_ptr;
+  const double inv = beta > 0.0 ? 1.0 / beta : 0.0;
+  const RowChunk ch = row_chunk(n);
+  double acc[1] = {0.0};
+  for (long i = ch.lo + threadIdx.x; i < ch.hi; i += kBlock) {
+    const double v = w[i] * inv;
+    q[i] = v;
+    acc[0] += v;
+  }
+  block_sum_store<1>(acc, part + blockIdx.x);
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_fin_sum(const double* __restrict__ part, int nb, double* __restrict__ out, int do_sqrt) {
+  __shared__ double red[kBlock / kWave];
+  double a = 0.0;
+  for (int b = threadIdx.x; b < nb; b += kBlock) a += part[b];
+  a = wave_sum(a);
+  if (threadIdx.x % kWave == 0) red[threadIdx.x / kWave] = a;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < kBlock / kWave; ++w) t += red[w];
+    *out = do_sqrt ? sqrt(t) : t;
+  }
+}
+
+// Start vector: counter-based uniform entries, partial ||x||^2.
+__global__ void __launch_bounds__(kBlock)
+k_rand(long n, uint64_t seed, double* __restrict__ x, double* __restrict__ part) {
+  const RowChunk ch = row_chunk(n);
+  double acc[1] = {0.0};
+  for (long i = ch.lo + threadIdx.x; i < ch.hi; i += kBlock) {
+    const double v = counter_uniform(seed, (uint64_t)i);
+    x[i] = v;
+    acc[0] += v * v;
+  }
+  block_sum_store<1>(acc, part + blockIdx.x);
+}
+
+// v = sum_c Q[c] s[c]; partial ||v||^2.
+__global__ void __launch_bounds__(kBlock)
+k_combine(long n, int ncol, const double* __restrict__ Q, long ldq, const double* __restrict__ s,
+          double* __restrict__ v, double* __restrict__ part) {
+  __shared__ double ss[512 + 1];
+  for (int c = threadIdx.x; c < ncol; c += kBlock) ss[c] = s[c];
+  __syncthreads();
+  const RowChunk ch = row_chunk(n);
+  double acc[1] = {0.0};
+  for (long i = ch.lo + threadIdx.x; i < ch.hi; i += kBlock) {
+    double a = 0.0;
+    for (int c = 0; c < ncol; ++c) a += Q[(long)c * ldq + i] * ss[c];
+    v[i] = a;
+    acc[0] += a * a;
+  }
+  block_sum_store<1>(acc, part + blockIdx.x);
+}
+
+// partial ||z - theta v||^2 (residual of the Ritz pair).
+__global__ void __launch_bounds__(kBlock)
+k_resid(long n, const double* __restrict__ z, const double* __restrict__ v, double theta, double* __restrict__ part) {
+  const RowChunk ch = row_chunk(n);
+  double acc[1] = {0.0};
+  for (long i = ch.lo + threadIdx.x; i < ch.hi; i += kBlock) {
+    const double d = z[i] - theta * v[i];
+    acc[0] += d * d;
+  }
+  block_sum_store<1>(acc, part + blockIdx.x);
+}
+
+// sum_i x_i^4 (DIAG) or sum over edges of (x_i x_j)^2 (TRACE_EDGES): the
+// curvature ||A(v v^T)||^2 of the rank-one step, without the trace row.
+__global__ void __launch_bounds__(kBlock)
+k_quartic_norm(long n, int cons_kind, EdgeAdj A, const double* __restrict__ x, double* __restrict__ part) {
+  const RowChunk ch = row_chunk(n);
+  double acc[1] = {0.0};
+  for (long i = ch.lo + threadIdx.x; i < ch.hi; i += kBlock) {
+    const double xi = x[i];
+    if (cons_kind == 0) {
+      acc[0] += xi * xi * xi * xi;
+    } else {
+      for (int k = A.urp[i]; k < A.urp[i + 1]; ++k) {
+        const double p = xi * x[A.uci[k]];
+        acc[0] += p * p;
+      }
+    }
+  }
+  block_sum_store<1>(acc, part + blockIdx.x);
+}
+
+// ---- launchers -------------------------------------------------------------------
+
+int vec_blocks(long n) {
+  long nb = (n + kBlock * 16 - 1) / (kBlock * 16);
+  if (nb < 8) nb = 8;
+  if (nb > 1024) nb = 1024;
+  return (int)((nb + 7) / 8 * 8);
+}
+
+void launch_slack_mv(const Cost<double>& C, int cons_kind, const EdgeAdj& A, const double* y, double c_tr,
+                     double j_coef, const DevScalars* sc, const double* x, double* out, hipStream_t st) {
+  const long threads = C.n * kSpmvLpr;
+  const int nb = (int)((threads + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL(k_slack_mv, dim3(nb), dim3(kBlock), 0, st, C, cons_kind, A, y, c_tr, j_coef, sc, x, out);
+}
+void launch_dots(long n, int ncol, const double* Q, long ldq, const double* w, double* part, int pstride, int nb,
+                 double* h, hipStream_t st) {
+  hipLaunchKernelGGL(k_dots, dim3(nb), dim3(kBlock), 0, st, n, ncol, Q, ldq, w, part, pstride);
+  hipLaunchKernelGGL(k_fin_dots, dim3(1), dim3(kBlock), 0, st, part, nb, pstride, ncol, h);
+}
+void launch_sub(long n, int ncol, const double* Q, long ldq, const double* h, double* w, double* part, int nb,
+                hipStream_t st) {
+  hipLaunchKernelGGL(k_sub, dim3(nb), dim3(kBlock), 0, st, n, ncol, Q, ldq, h, w, part);
+}
+void launch_fin_ab(const double* part, int nb, const double* h1, const double* h2, int j, double* alpha, double* beta,
+                   hipStream_t st) {
+  hipLaunchKernelGGL(k_fin_ab, dim3(1), dim3(kBlock), 0, st, part, nb, h1, h2, j, alpha, beta);
+}
+void launch_scale(long n, const double* w, const double* beta, double* q, double* part, int nb, double* qsum,
+                  hipStream_t st) {
+  hipLaunchKernelGGL(k_scale, dim3(nb), dim3(kBlock), 0, st, n, w, beta, q, part);
+  if (qsum) hipLaunchKernelGGL(k_fin_sum, dim3(1), dim3(kBlock), 0, st, part, nb, qsum, 0);
+}
+void launch_fin_sum(const double* part, int nb, double* out, int do_sqrt, hipStream_t st) {
+  hipLaunchKernelGGL(k_fin_sum, dim3(1), dim3(kBlock), 0, st, part, nb, out, do_sqrt);
+}
+void launch_rand(long n, uint64_t seed, double* x, double* part, int nb, hipStream_t st) {
+  hipLaunchKernelGGL(k_rand, dim3(nb), dim3(kBlock), 0, st, n, seed, x, part);
+}
+void launch_combine(long n, int ncol, const double* Q, long ldq, const double* s, double* v, double* part, int nb,
+                    hipStream_t st) {
+  hipLaunchKernelGGL(k_combine, dim3(nb), dim3(kBlock), 0, st, n, ncol, Q, ldq, s, v, part);
+}
+void launch_resid(long n, const double* z, const double* v, double theta, double* part, int nb, hipStream_t st) {
+  hipLaunchKernelGGL(k_resid, dim3(nb), dim3(kBlock), 0, st, n, z, v, theta, part);
+}
+void launch_quartic_norm(long n, int cons_kind, const EdgeAdj& A, const double* x, double* part, int nb,
+                         hipStream_t st) {
+  hipLaunchKernelGGL(k_quartic_norm, dim3(nb), dim3(kBlock), 0, st, n, cons_kind, A, x, part);
+}
+
+}  // namespace almbm

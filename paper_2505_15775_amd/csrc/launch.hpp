@@ -1,0 +1,75 @@
+// Host-side declarations of the kernel launchers (defined in the .hip files).
+#pragma once
+
+#include "kernels.hpp"
+
+namespace almbm {
+
+template <typename T>
+void launch_objgrad_diag(const Cost<typename Acc<T>::type>& C, int r, int variant, const T* R, const double* y,
+                         const double* b, double sigma, T* G, double* Av, double* part, const DevScalars* sc,
+                         int nblk, hipStream_t st);
+template <typename T>
+void launch_quad_diag(const Cost<typename Acc<T>::type>& C, int r, int variant, const T* G, double* part,
+                      const DevScalars* sc, int nblk, hipStream_t st);
+template <typename T>
+void launch_ls_diag(const Cost<typename Acc<T>::type>& C, int r, int variant, const T* R, const T* G,
+                    const double* y, const double* b, double* part, int nblk, hipStream_t st);
+
+template <typename T>
+void launch_edges_p1(const EdgeAdj& A, long n, int r, int variant, const T* R, const double* y, const double* b,
+                     double sigma, double* Av, double* wE, double* part, const DevScalars* sc, int nblk,
+                     hipStream_t st);
+template <typename T>
+void launch_edges_p2(const Cost<typename Acc<T>::type>& C, const EdgeAdj& A, int r, int variant, const T* R,
+                     const double* wE, double c_tr, double j_coef, const T* G_in, T* G, double* part,
+                     const DevScalars* sc, int nblk, hipStream_t st);
+template <typename T>
+void launch_edges_p3(const Cost<typename Acc<T>::type>& C, const EdgeAdj& A, int r, int variant, const T* R,
+                     const T* G, const double* y, const double* b, const double* Av, double* part,
+                     const DevScalars* sc, int nblk, hipStream_t st);
+void launch_fin_edges1(const double* part, int nb, int r, DevScalars* sc, const double* y, const double* b,
+                       double sigma, double c_tr, double* Av, hipStream_t st);
+void launch_fin_edges2(const double* part, int nb, int r, DevScalars* sc, double sigma, int mode, double* f_out,
+                       hipStream_t st);
+void launch_fin_edges3(const double* part, int nb, int r, DevScalars* sc, const double* y, const double* b,
+                       double sigma, double c_tr, double j_coef, int mode, double* coeffs_out, double* t_out,
+                       hipStream_t st);
+
+void launch_fin_objgrad(const double* part, int nb, DevScalars* sc, double sigma, int mode, double* f_out,
+                        hipStream_t st);
+void launch_fin_step(const double* part_c2, int nb, int c2_stride, DevScalars* sc, double sigma, double j_extra,
+                     int mode, double* coeffs_out, double* t_out, hipStream_t st);
+void launch_fin_ls(const double* part, int nb, DevScalars* sc, double sigma, double* coeffs_out, double* t_out,
+                   hipStream_t st);
+template <typename T>
+void launch_update(long len, T* R, const T* G, const DevScalars* sc, int use_flag, hipStream_t st);
+int dual_blocks(long m);
+void launch_dual(long m, const double* Av, const double* b, const double* y_in, double* y_out, double sigma,
+                 double* part, DevScalars* sc, double bnorm, double* pinf_out, hipStream_t st);
+void launch_inner_reset(DevScalars* sc, double tol, int max_inner, int step_rule, double eta, hipStream_t st);
+template <typename T>
+void launch_relayout(long n, int rs, int rd, const T* src, T* dst, const double* v, double scale, hipStream_t st);
+template <typename S, typename D>
+void launch_convert(long len, const S* src, D* dst, hipStream_t st);
+
+int vec_blocks(long n);
+void launch_slack_mv(const Cost<double>& C, int cons_kind, const EdgeAdj& A, const double* y, double c_tr,
+                     double j_coef, const DevScalars* sc, const double* x, double* out, hipStream_t st);
+void launch_dots(long n, int ncol, const double* Q, long ldq, const double* w, double* part, int pstride, int nb,
+                 double* h, hipStream_t st);
+void launch_sub(long n, int ncol, const double* Q, long ldq, const double* h, double* w, double* part, int nb,
+                hipStream_t st);
+void launch_fin_ab(const double* part, int nb, const double* h1, const double* h2, int j, double* alpha, double* beta,
+                   hipStream_t st);
+void launch_scale(long n, const double* w, const double* beta, double* q, double* part, int nb, double* qsum,
+                  hipStream_t st);
+void launch_fin_sum(const double* part, int nb, double* out, int do_sqrt, hipStream_t st);
+void launch_rand(long n, uint64_t seed, double* x, double* part, int nb, hipStream_t st);
+void launch_combine(long n, int ncol, const double* Q, long ldq, const double* s, double* v, double* part, int nb,
+                    hipStream_t st);
+void launch_resid(long n, const double* z, const double* v, double theta, double* part, int nb, hipStream_t st);
+void launch_quartic_norm(long n, int cons_kind, const EdgeAdj& A, const double* x, double* part, int nb,
+                         hipStream_t st);
+
+}  // namespace almbm

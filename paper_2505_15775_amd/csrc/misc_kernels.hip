@@ -1,0 +1,245 @@
+// Scalar finalisation (deterministic fixed-order reductions), the quartic step
+// rule, the factor update and the FP64 dual update.
+#include <math.h>
+
+#include "kernels.hpp"
+#include "quartic.hpp"
+
+namespace almbm {
+
+// ---- deterministic reduction of per-block partials ---------------------------
+// part is [nb][NS]; thread t sums blocks t, t+256, ... in order, then the block
+// tree is fixed, so the total does not depend on timing.
+template <int NS>
+__device__ void reduce_partials(const double* __restrict__ part, int nb, int stride, double* __restrict__ out) {
+  double acc[NS];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) acc[s] = 0.0;
+  for (int bi = threadIdx.x; bi < nb; bi += kBlock) {
+#pragma unroll
+    for (int s = 0; s < NS; ++s) acc[s] += part[(long)bi * stride + s];
+  }
+  __shared__ double res[NS];
+  block_sum_store<NS>(acc, res);
+  __syncthreads();
+  if (threadIdx.x < NS) out[threadIdx.x] = res[threadIdx.x];
+  __syncthreads();
+}
+
+__device__ __forceinline__ bool finite(double x) { return isfinite(x); }
+
+// ---- finalize kernels (one block) ------------------------------------------------
+
+// Objective totals of the DIAG family.  mode 0: API call, writes *f_out.
+// mode 1: inner loop step 1 -- after max_inner steps stop (flag 2), else the
+// stop test ||G|| ||R|| <= tol (1 + |<C,RR^T>|) (flag 1), else count the step.
+__global__ void __launch_bounds__(kBlock)
+k_fin_objgrad(const double* __restrict__ part, int nb, DevScalars* __restrict__ sc, double sigma, int mode,
+              double* __restrict__ f_out) {
+  if (mode == 1 && sc->flag) return;
+  __shared__ double tot[NUM_P];
+  reduce_partials<NUM_P>(part, nb, NUM_P, tot);
+  if (threadIdx.x != 0) return;
+  for (int s = 0; s < NUM_P; ++s) sc->tot[s] = tot[s];
+  const double f = tot[P_C0] + tot[P_YBMA] + 0.5 * sigma * tot[P_EE];
+  sc->f = f;
+  if (!finite(f) || !finite(tot[P_GG])) sc->numeric_error = 1;
+  if (f_out) *f_out = f;
+  if (mode == 1) {
+    const double lhs = sqrt(tot[P_GG]) * sqrt(tot[P_RR]);
+    if (sc->iter >= sc->max_inner) {
+      sc->flag = 2;
+    } else if (lhs <= sc->tol * (1.0 + fabs(tot[P_C0])) || !finite(lhs)) {
+      sc->flag = 1;
+    } else {
+      sc->iter += 1;
+    }
+  }
+}
+
+// Step rule: reduce the <G, CG> partials into tot[P_C2], form the quartic and
+// pick t.  mode 0: API (coeffs/t to the given pointers).  mode 1: inner loop.
+__global__ void __launch_bounds__(kBlock)
+k_fin_step(const double* __restrict__ part_c2, int nb, int c2_stride, DevScalars* __restrict__ sc, double sigma,
+           double j_extra_c2, int mode, double* __restrict__ coeffs_out, double* __restrict__ t_out) {
+  if (mode == 1 && sc->flag) return;
+  __shared__ double c2[1];
+  if (part_c2) reduce_partials<1>(part_c2, nb, c2_stride, c2);
+  if (threadIdx.x != 0) return;
+  if (part_c2) sc->tot[P_C2] = c2[0] + j_extra_c2;
+  double k[5];
+  quartic_coeffs(sc->tot, sigma, k);
+  for (int s = 0; s < 5; ++s) sc->coeffs[s] = k[s];
+  double t = (sc->step_rule == 1 && mode == 1) ? sc->eta_fixed : quartic_argmin(k);
+  if (!finite(t)) {
+    t = 0.0;
+    sc->numeric_error = 1;
+  }
+  sc->t = t;
+  if (coeffs_out)
+    for (int s = 0; s < 5; ++s) coeffs_out[s] = k[s];
+  if (t_out) *t_out = t;
+}
+
+// Full reduction of all NUM_P partials (API line search), then the step.
+__global__ void __launch_bounds__(kBlock)
+k_fin_ls(const double* __restrict__ part, int nb, DevScalars* __restrict__ sc, double sigma,
+         double* __restrict__ coeffs_out, double* __restrict__ t_out) {
+  __shared__ double tot[NUM_P];
+  reduce_partials<NUM_P>(part, nb, NUM_P, tot);
+  if (threadIdx.x != 0) return;
+  for (int s = 0; s < NUM_P; ++s) sc->tot[s] = tot[s];
+  double k[5];
+  quartic_coeffs(sc->tot, sigma, k);
+  const double t = quartic_argmin(k);
+  for (int s = 0; s < 5; ++s) sc->coeffs[s] = k[s];
+  sc->t = t;
+  if (coeffs_out)
+    for (int s = 0; s < 5; ++s) coeffs_out[s] = k[s];
+  if (t_out) *t_out = t;
+}
+
+// R <- R - t G (elementwise, storage precision), skipped once the flag is set.
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_update(long len, T* __restrict__ R, const T* __restrict__ G, const DevScalars* __restrict__ sc, int use_flag) {
+  using V = typename Acc<T>::type;
+  if (use_flag && sc->flag) return;
+  const V t = static_cast<V>(sc->t);
+  const long stride = (long)gridDim.x * kBlock;
+  for (long idx = (long)blockIdx.x * kBlock + threadIdx.x; idx < len; idx += stride) {
+    R[idx] = from_acc<T>(to_acc<T>(R[idx]) - t * to_acc<T>(G[idx]));
+  }
+}
+
+// y_out = y_in - sigma (Av - b); partials {||Av - b||^2, b^T y_out}.
+__global__ void __launch_bounds__(kBlock)
+k_dual(long m, const double* __restrict__ Av, const double* __restrict__ b, const double* __restrict__ y_in,
+       double* __restrict__ y_out, double sigma, double* __restrict__ part) {
+  double acc[2] = {0.0, 0.0};
+  const long stride = (long)gridDim.x * kBlock;
+  for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < m; i += stride) {
+    const double e = Av[i] - b[i];
+    const double yn = y_in[i] - sigma * e;
+    if (y_out) y_out[i] = yn;
+    acc[0] += e * e;
+    acc[1] += b[i] * yn;
+  }
+  block_sum_store<2>(acc, part + (long)blockIdx.x * 2);
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_fin_dual(const double* __restrict__ part, int nb, DevScalars* __restrict__ sc, double bnorm,
+           double* __restrict__ pinf_out) {
+  __shared__ double tot[2];
+  reduce_partials<2>(part, nb, 2, tot);
+  if (threadIdx.x != 0) return;
+  sc->res2 = tot[0];
+  sc->pinf = sqrt(tot[0]) / (1.0 + bnorm);
+  sc->dobj = tot[1];
+  if (!finite(sc->pinf) || !finite(sc->dobj)) sc->numeric_error = 1;
+  if (pinf_out) *pinf_out = sc->pinf;
+}
+
+// Start of an inner solve: clear the flag and counters (a kernel, not a memset,
+// so that it can sit inside a captured graph).
+__global__ void k_inner_reset(DevScalars* sc, double tol, int max_inner, int step_rule, double eta) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    sc->flag = 0;
+    sc->iter = 0;
+    sc->tol = tol;
+    sc->max_inner = max_inner;
+    sc->step_rule = step_rule;
+    sc->eta_fixed = eta;
+  }
+}
+
+// Copy with change of row stride: dst (n x rd) <- src (n x rs) for the first
+// min(rs, rd) columns; column `rs` of dst (when rd > rs) gets scale * v[i].
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_relayout(long n, int rs, int rd, const T* __restrict__ src, T* __restrict__ dst, const double* __restrict__ v,
+           double scale) {
+  const long len = n * rd;
+  const long stride = (long)gridDim.x * kBlock;
+  for (long idx = (long)blockIdx.x * kBlock + threadIdx.x; idx < len; idx += stride) {
+    const long i = idx / rd;
+    const int c = (int)(idx - i * rd);
+    if (c < rs) dst[idx] = src[i * rs + c];
+    else if (c == rs && v) dst[idx] = from_acc<T>(static_cast<typename Acc<T>::type>(scale * v[i]));
+    else dst[idx] = from_acc<T>(typename Acc<T>::type(0));
+  }
+}
+
+// Precision conversion (storage), round to nearest even for bfloat16.
+template <typename S, typename D>
+__global__ void __launch_bounds__(kBlock) k_convert(long len, const S* __restrict__ src, D* __restrict__ dst) {
+  const long stride = (long)gridDim.x * kBlock;
+  for (long idx = (long)blockIdx.x * kBlock + threadIdx.x; idx < len; idx += stride)
+    dst[idx] = from_acc<D>(static_cast<typename Acc<D>::type>(to_acc<S>(src[idx])));
+}
+
+// ---- launch helpers ------------------------------------------------------------
+
+void launch_fin_objgrad(const double* part, int nb, DevScalars* sc, double sigma, int mode, double* f_out,
+                        hipStream_t st) {
+  hipLaunchKernelGGL(k_fin_objgrad, dim3(1), dim3(kBlock), 0, st, part, nb, sc, sigma, mode, f_out);
+}
+void launch_fin_step(const double* part_c2, int nb, int c2_stride, DevScalars* sc, double sigma, double j_extra,
+                     int mode, double* coeffs_out, double* t_out, hipStream_t st) {
+  hipLaunchKernelGGL(k_fin_step, dim3(1), dim3(kBlock), 0, st, part_c2, nb, c2_stride, sc, sigma, j_extra, mode,
+                     coeffs_out, t_out);
+}
+void launch_fin_ls(const double* part, int nb, DevScalars* sc, double sigma, double* coeffs_out, double* t_out,
+                   hipStream_t st) {
+  hipLaunchKernelGGL(k_fin_ls, dim3(1), dim3(kBlock), 0, st, part, nb, sc, sigma, coeffs_out, t_out);
+}
+static int elem_blocks(long len) {
+  long nb = (len + kBlock * 4 - 1) / (kBlock * 4);
+  if (nb < 1) nb = 1;
+  if (nb > 8192) nb = 8192;
+  return (int)nb;
+}
+template <typename T>
+void launch_update(long len, T* R, const T* G, const DevScalars* sc, int use_flag, hipStream_t st) {
+  hipLaunchKernelGGL((k_update<T>), dim3(elem_blocks(len)), dim3(kBlock), 0, st, len, R, G, sc, use_flag);
+}
+template void launch_update<double>(long, double*, const double*, const DevScalars*, int, hipStream_t);
+template void launch_update<float>(long, float*, const float*, const DevScalars*, int, hipStream_t);
+template void launch_update<bf16>(long, bf16*, const bf16*, const DevScalars*, int, hipStream_t);
+
+int dual_blocks(long m) {
+  long nb = (m + kBlock * 8 - 1) / (kBlock * 8);
+  if (nb < 1) nb = 1;
+  if (nb > 1024) nb = 1024;
+  return (int)nb;
+}
+void launch_dual(long m, const double* Av, const double* b, const double* y_in, double* y_out, double sigma,
+                 double* part, DevScalars* sc, double bnorm, double* pinf_out, hipStream_t st) {
+  const int nb = dual_blocks(m);
+  hipLaunchKernelGGL(k_dual, dim3(nb), dim3(kBlock), 0, st, m, Av, b, y_in, y_out, sigma, part);
+  hipLaunchKernelGGL(k_fin_dual, dim3(1), dim3(kBlock), 0, st, part, nb, sc, bnorm, pinf_out);
+}
+void launch_inner_reset(DevScalars* sc, double tol, int max_inner, int step_rule, double eta, hipStream_t st) {
+  hipLaunchKernelGGL(k_inner_reset, dim3(1), dim3(64), 0, st, sc, tol, max_inner, step_rule, eta);
+}
+template <typename T>
+void launch_relayout(long n, int rs, int rd, const T* src, T* dst, const double* v, double scale, hipStream_t st) {
+  hipLaunchKernelGGL((k_relayout<T>), dim3(elem_blocks(n * rd)), dim3(kBlock), 0, st, n, rs, rd, src, dst, v, scale);
+}
+template void launch_relayout<double>(long, int, int, const double*, double*, const double*, double, hipStream_t);
+template void launch_relayout<float>(long, int, int, const float*, float*, const double*, double, hipStream_t);
+template void launch_relayout<bf16>(long, int, int, const bf16*, bf16*, const double*, double, hipStream_t);
+
+template <typename S, typename D>
+void launch_convert(long len, const S* src, D* dst, hipStream_t st) {
+  hipLaunchKernelGGL((k_convert<S, D>), dim3(elem_blocks(len)), dim3(kBlock), 0, st, len, src, dst);
+}
+template void launch_convert<double, float>(long, const double*, float*, hipStream_t);
+template void launch_convert<double, bf16>(long, const double*, bf16*, hipStream_t);
+template void launch_convert<float, double>(long, const float*, double*, hipStream_t);
+template void launch_convert<bf16, double>(long, const bf16*, double*, hipStream_t);
+template void launch_convert<bf16, float>(long, const bf16*, float*, hipStream_t);
+template void launch_convert<float, bf16>(long, const float*, bf16*, hipStream_t);
+
+}  // namespace almbm

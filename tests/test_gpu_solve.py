@@ -1,0 +1,132 @@
+"""Solve-level checks of the HIP path (GPU only): closed-form SDP values, the
+stored oracle solve of the n = 2000 ER workload, KKT re-evaluated by the oracle
+at the GPU's final point, determinism, graph replay against eager launches,
+and the not-converged exit."""
+
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import gen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def almbm():
+    import paper_2505_15775_amd as m
+
+    return m
+
+
+def _maxcut(g, prec="f64", r_max=32, kmax=100):
+    return almbm().Problem.maxcut(g.n, g.ei, g.ej, g.w, precision=prec, r_max=r_max, lanczos_kmax=kmax, device=DEV)
+
+
+def _oracle_kkt(po, R, y):
+    lam = oracle.min_eig(po, y)
+    return oracle.kkt(po, R, y, lam_min=lam)
+
+
+@pytest.mark.parametrize("n", [10, 9, 64])
+def test_solve_cycles_closed_form(n):
+    g = gen.cycle_graph(n)
+    prob = _maxcut(g, r_max=8, kmax=min(n, 60))
+    st, res, R, y = prob.solve(gen.init_factor(n, 2, 1), eps_kkt=1e-8, max_outer=400, max_inner=2000)
+    val = -res["pobj"]
+    expect = n if n % 2 == 0 else n * (1 + math.cos(math.pi / n)) / 2
+    print(f"cycle {n}: status {st} value {val:.12f} expect {expect:.12f} outer {res['outer']} rank {res['rank']}")
+    assert st == 0
+    assert math.isclose(val, expect, rel_tol=1e-6)
+
+
+def test_solve_complete_graph_closed_form():
+    g = gen.complete_graph(8)
+    prob = _maxcut(g, r_max=8, kmax=8)
+    st, res, R, y = prob.solve(gen.init_factor(8, 3, 2), eps_kkt=1e-8, max_outer=400, max_inner=2000)
+    assert st == 0 and math.isclose(-res["pobj"], 16.0, rel_tol=1e-6)
+
+
+@pytest.mark.parametrize("n,expect", [(5, math.sqrt(5.0)), (6, 3.0)])
+def test_solve_lovasz_theta_cycles(n, expect):
+    g = gen.cycle_graph(n)
+    prob = almbm().Problem.lovasz(n, g.ei, g.ej, precision="f64", r_max=8, lanczos_kmax=n, device=DEV)
+    st, res, R, y = prob.solve(gen.init_factor(n, 3, 1), eps_kkt=1e-6, max_outer=400, max_inner=2000)
+    print(f"lovasz C{n}: status {st} theta {-res['pobj']:.10f} expect {expect:.10f}")
+    assert st == 0 and math.isclose(-res["pobj"], expect, rel_tol=1e-5)
+
+
+def test_solve_er2000_matches_stored_oracle_solve():
+    """The n = 2000 ER workload (unit weights, r0 = 8, sigma = 1, eps = 1e-6)
+    against the oracle's own solve (tests/golden/make_golden.py), and the KKT
+    measure re-evaluated by the oracle (exact lambda_min) at the GPU's (R, y)."""
+    gold = json.load(open(os.path.join(GOLDEN, "c1_maxcut_er2000.json")))
+    g = gen.er_graph(2000, 10000, 1, "unit")
+    prob = _maxcut(g, r_max=64, kmax=100)
+    st, res, R, y = prob.solve(gen.init_factor(2000, 8, 1), eps_kkt=1e-6, sigma=1.0)
+    print(f"er2000: status {st} outer {res['outer']} inner {res['inner_total']} rank {res['rank']} "
+          f"pobj {res['pobj']:.10f} (oracle {gold['pobj']:.10f}) kkt {res['kkt']:.2e} time {res['time_s']:.2f}s")
+    assert st == 0
+    assert abs(res["pobj"] - gold["pobj"]) <= 1e-5 * abs(gold["pobj"])
+    po = oracle.maxcut_sdp(g)
+    k = _oracle_kkt(po, R.cpu().numpy(), y.cpu().numpy())
+    print(f"oracle KKT at GPU point: {k}")
+    assert k["pinf"] <= 1e-6 and k["gap"] <= 1e-6 and k["dinf"] <= 2e-6
+
+
+def test_solve_deterministic_and_graph_matches_eager():
+    g = gen.er_graph(700, 4000, 21, "gauss")
+    outs = []
+    for unroll in (8, 8, 0, 3):
+        prob = _maxcut(g, r_max=32, kmax=80)
+        st, res, R, y = prob.solve(gen.init_factor(700, 4, 3), eps_kkt=1e-5, graph_unroll=unroll, max_outer=300)
+        outs.append((st, res["outer"], res["rank"], R.cpu().numpy().copy(), y.cpu().numpy().copy()))
+        prob.close()
+    for o in outs[1:]:
+        assert o[0] == outs[0][0] and o[1] == outs[0][1] and o[2] == outs[0][2]
+        assert np.array_equal(o[3], outs[0][3]) and np.array_equal(o[4], outs[0][4])
+
+
+def test_solve_max_outer_exit_returns_valid_outputs():
+    g = gen.er_graph(500, 2500, 5, "unit")
+    prob = _maxcut(g, r_max=16, kmax=50)
+    st, res, R, y = prob.solve(gen.init_factor(500, 4, 1), eps_kkt=1e-9, max_outer=2, max_inner=5)
+    assert st == 1  # NOT_CONVERGED
+    assert res["outer"] == 2 and np.all(np.isfinite(R.cpu().numpy())) and np.all(np.isfinite(y.cpu().numpy()))
+
+
+def test_solve_gpu_matches_oracle_trajectory_short():
+    """Same start, same options, a few outer iterations: final objective and
+    dual agree with the oracle's run (discrete decisions coincide on this case)."""
+    g = gen.er_graph(400, 2000, 8, "gauss")
+    po = oracle.maxcut_sdp(g)
+    R0 = gen.init_factor(400, 6, 2)
+    opts = dict(eps_kkt=1e-12, max_outer=3, max_inner=40, rank_policy=1)
+    prob = _maxcut(g, r_max=16, kmax=100)
+    st, res, R, y = prob.solve(R0, **opts)
+    out = oracle.solve(po, R0, opts=oracle.SolveOptions(eps_kkt=1e-12, max_outer=3, max_inner=40,
+                                                        rank_policy="fixed", r_max=16))
+    Ro, yo = out["R"], out["y"]
+    assert abs(res["pobj"] - out["kkt"]["pobj"]) <= 1e-9 * abs(out["kkt"]["pobj"])
+    assert np.linalg.norm(y.cpu().numpy() - yo) <= 1e-8 * np.linalg.norm(yo)
+    Xg = R.cpu().numpy() @ R.cpu().numpy().T
+    assert np.linalg.norm(Xg - Ro @ Ro.T) <= 1e-8 * np.linalg.norm(Ro @ Ro.T)
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+def test_solve_mixed_precision_reports_error(prec):
+    g = gen.er_graph(2000, 10000, 1, "unit")
+    gold = json.load(open(os.path.join(GOLDEN, "c1_maxcut_er2000.json")))
+    prob = _maxcut(g, prec=prec, r_max=64, kmax=100)
+    st, res, R, y = prob.solve(gen.init_factor(2000, 8, 1), eps_kkt=1e-4, sigma=1.0)
+    err = abs(res["pobj"] - gold["pobj"]) / abs(gold["pobj"])
+    print(f"{prec}: status {st} outer {res['outer']} kkt {res['kkt']:.2e} rel obj err vs FP64 oracle {err:.2e} "
+          f"promoted_at {res['promoted_at_outer']}")
+    assert st == 0 and err <= 2e-4
