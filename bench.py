@@ -1,0 +1,288 @@
+"""Benchmark of the ALM-BM hot path on one MI355X.
+
+Workload (default): MaxCut SDP relaxation on an Erdos-Renyi graph with
+n = 10,000,000 vertices and M = 40,000,000 edges (average degree 8), N(0,1)
+edge weights, rank r = 16, factor stored in BF16 with FP32 arithmetic; inputs
+synthetic and resident in HBM before timing.
+
+A step is one inner iteration of the method as run inside the solve: the fused
+objective + gradient pass (C R, A(RR^T), adjoint, objective terms), the exact
+line search (the product C G and the quartic's roots) and the update R <- R - tG.
+Each step is one gradient evaluation, so steps/s = gradient evaluations/s.
+The rows evaluated once per outer iteration (dual update, Lanczos matvec and
+reorthogonalisation) are timed separately and reported under "per_outer".
+
+Usage: python bench.py [--steps K] [--warmup W] [--precision bf16|f32|f64]
+                       [--n N] [--deg D] [--rank R] [--modes] [--solve]
+                       [--no-cpu-baseline]
+"""
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+LANCZOS_STEPS = 20
+METRIC = "ALM-BM grad evals/sec + HBM GB/s, n=10M MaxCut; wall time to 1e-4 rel KKT"
+COUNTERS = os.path.join(ROOT, "profiles", "objgrad_counters.json")
+KERNEL_SOURCES = ["paper_2505_15775_amd/csrc/diag_kernels.hip", "paper_2505_15775_amd/csrc/spmm_row.hpp",
+                  "paper_2505_15775_amd/csrc/common.hpp", "paper_2505_15775_amd/csrc/kernels.hpp"]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def objgrad_bytes(n, nnz, r, prec):
+    """Compulsory HBM bytes of one objective/gradient pass (DIAG family):
+    CSR row_ptr + col_idx + values, diagonal, read R once, y, b, write G and A(RR^T)."""
+    vb = 8 if prec == "f64" else 4
+    rb = {"f64": 8, "f32": 4, "bf16": 2}[prec]
+    return (n + 1) * 4 + nnz * (4 + vb) + n * vb + 2 * n * r * rb + 3 * n * 8
+
+
+def time_events(fn, iters):
+    import torch
+
+    s = torch.cuda.Event(enable_timing=True)
+    e = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    s.record()
+    for _ in range(iters):
+        fn()
+    e.record()
+    e.synchronize()
+    return s.elapsed_time(e) / 1000.0
+
+
+def bench_mode(g, prec, r, steps, warmup, seed):
+    import torch
+
+    import gen
+    import paper_2505_15775_amd as almbm
+
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    prob = almbm.Problem.maxcut(g.n, g.ei, g.ej, g.w, precision=prec, r_max=r, lanczos_kmax=LANCZOS_STEPS,
+                                device=dev, validate=False)
+    log(f"[bench] {prec}: problem resident in {time.time() - t0:.1f}s (nnz {prob.desc.nnz})")
+    R = prob.factor(torch.from_numpy(gen.init_factor(g.n, r, seed)))
+    y = torch.zeros(g.n, dtype=torch.float64, device=dev)
+    f = torch.empty(1, dtype=torch.float64, device=dev)
+    t = torch.empty(1, dtype=torch.float64, device=dev)
+    G = torch.empty_like(R)
+    Av = torch.empty(g.n, dtype=torch.float64, device=dev)
+    sigma = 1.0
+
+    # the solve's inner loop (graph-captured, one sparse product per step between
+    # refreshes), run for a fixed number of steps (tolerance 0: never stops early)
+    prob.inner_solve(R, y, 0.0, warmup, sigma=sigma)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    done, flag, f_last = prob.inner_solve(R, y, 0.0, steps, sigma=sigma)
+    el = time.perf_counter() - t1
+    assert done == steps and flag == 2, (done, flag)
+    log(f"[bench] {prec}: {steps} inner steps in {el:.3f}s, f={f_last:.6e}")
+
+    # the dominant kernel alone (objective/gradient pass + its one-block finalize)
+    from paper_2505_15775_amd import _lib, _ptr, _stream  # noqa: F401
+
+    def og():
+        _lib.check(_lib.lib.alm_bm_objective_grad(prob._h, r, _ptr(R), _ptr(y), sigma, _ptr(f), _ptr(G), _ptr(Av),
+                                                  _stream()), "objective_grad")
+
+    for _ in range(max(2, warmup)):
+        og()
+    n_og = max(steps, 10)
+    el_og = time_events(og, n_og)
+    per_og = el_og / n_og
+    out = {"steps_per_s": steps / el, "ms_per_step": 1000.0 * el / steps,
+           "objgrad_ms": 1000.0 * per_og, "objgrad_evals_per_s": 1.0 / per_og,
+           "objgrad_bytes": objgrad_bytes(g.n, int(prob.desc.nnz), r, prec)}
+    out["objgrad_gbs"] = out["objgrad_bytes"] / per_og / 1e9
+    return prob, R, y, out
+
+
+def per_outer_rows(prob, y, steps):
+    """Dual update and Lanczos (slack matvec + two Gram-Schmidt passes per step,
+    host tridiagonal solve every few steps) at full size, FP64."""
+    import torch
+
+    Av = torch.ones(prob.n, dtype=torch.float64, device=y.device)
+    yy = y.clone()
+    el = time_events(lambda: prob.dual_update(Av, 1.0, yy), steps)
+    yl = -torch.ones(prob.n, dtype=torch.float64, device=y.device)
+    prob.lanczos_min_eig(yl, max_iter=4, tol=0.0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, _, _, iters = prob.lanczos_min_eig(yl, max_iter=LANCZOS_STEPS, tol=0.0)
+    tl = time.perf_counter() - t0
+    return {"dual_update_ms": 1000.0 * el / steps, "lanczos_steps": iters,
+            "lanczos_ms_total": 1000.0 * tl, "lanczos_ms_per_step": 1000.0 * tl / max(1, iters)}
+
+
+def calibrate_copy(nbytes=1 << 30):
+    """A plain elementwise copy of known size (read nbytes, write nbytes), for
+    scaling the HBM byte counters of a profiled run."""
+    import torch
+
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.mul(src, 1.0, out=dst)
+    torch.cuda.synchronize()
+    log(f"[bench] calibration copy: {nbytes} bytes read, {nbytes} bytes written")
+    del src, dst
+    torch.cuda.empty_cache()
+
+
+def cpu_baseline(n_full, deg, r, seed, evals=2):
+    """The FP64 oracle's objective/gradient on a bounded sample of the same
+    workload family: an ER graph with n/10 vertices and the same average degree
+    and weight law, scaled to the full size by the row count."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    import gen
+    import oracle
+
+    n_s = max(1000, n_full // 10)
+    g = gen.er_graph(n_s, int(n_s * deg / 2), seed + 100, "gauss")
+    p = oracle.maxcut_sdp(g)
+    R = gen.init_factor(n_s, r, seed)
+    y = np.zeros(n_s)
+    with threadpool_limits(limits=1):
+        oracle.objective_grad(p, R, y, 1.0)
+        t0 = time.perf_counter()
+        for _ in range(evals):
+            oracle.objective_grad(p, R, y, 1.0)
+        dt = (time.perf_counter() - t0) / evals
+    scale = n_full / n_s
+    return {"value": 1.0 / (dt * scale), "unit": "grad_evals/s", "cores": 1, "kind": "oracle",
+            "sample": f"oracle.objective_grad (FP64, NumPy/SciPy, 1 thread) on ER n={n_s} M={g.m_edges} "
+                      f"N(0,1) weights r={r}, {evals} timed evals of {dt:.2f}s each, scaled by n ratio {scale:.1f}"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--precision", default="bf16", choices=["bf16", "f32", "f64"])
+    ap.add_argument("--n", type=int, default=10_000_000)
+    ap.add_argument("--deg", type=float, default=8.0)
+    ap.add_argument("--rank", type=int, default=16)
+    ap.add_argument("--seed", type=int, default=5)
+    ap.add_argument("--modes", action="store_true", help="also time the other two precisions")
+    ap.add_argument("--solve", action="store_true", help="also run the full solve to 1e-4 relative KKT")
+    ap.add_argument("--solve-time-limit", type=float, default=600.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true", help="run a 1 GiB copy kernel first (profiling)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import gen
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.calibrate_copy:
+        calibrate_copy()
+    t0 = time.time()
+    M = int(args.n * args.deg / 2)
+    g = gen.er_graph(args.n, M, args.seed, "gauss")
+    log(f"[bench] graph n={g.n} M={g.m_edges} generated in {time.time() - t0:.1f}s")
+
+    prob, R, y, main_out = bench_mode(g, args.precision, args.rank, args.steps, args.warmup, args.seed)
+    per_outer = per_outer_rows(prob, y, 20)
+    modes = {}
+    if args.modes:
+        for pm in ("f64", "f32", "bf16"):
+            if pm == args.precision:
+                continue
+            p2, _, _, o2 = bench_mode(g, pm, args.rank, max(10, args.steps // 2), 2, args.seed)
+            modes[pm] = o2
+            p2.close()
+            torch.cuda.empty_cache()
+
+    # traffic from the committed rocprofv3 counter summary, if it is for this kernel source
+    traffic = None
+    if os.path.exists(COUNTERS):
+        c = json.load(open(COUNTERS))
+        key = f"{args.precision}_n{args.n}_r{args.rank}"
+        if c.get("kernel_source_hash") == kernel_source_hash() and key in c.get("runs", {}):
+            traffic = c["runs"][key]["hbm_bytes_per_launch"]
+
+    ach = main_out["objgrad_gbs"]
+    roofline = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": "k_objgrad_diag (fused objective/gradient pass)",
+                "algorithmic_bytes_per_launch": main_out["objgrad_bytes"],
+                "launch_ms": round(main_out["objgrad_ms"], 4)}
+
+    solve = None
+    if args.solve:
+        prob.close()
+        del prob
+        torch.cuda.empty_cache()
+        import paper_2505_15775_amd as almbm
+
+        ps = almbm.Problem.maxcut(g.n, g.ei, g.ej, g.w, precision=args.precision, r_max=48, lanczos_kmax=60,
+                                  device="cuda:0", validate=False)
+        st, res, Rf, yf = ps.solve(gen.init_factor(g.n, args.rank, args.seed), eps_kkt=1e-4,
+                                   time_limit_s=args.solve_time_limit, verbose=1)
+        solve = {"status": int(st), **{k: res[k] for k in ("outer", "inner_total", "rank", "kkt", "pobj", "time_s",
+                                                          "time_lanczos_s", "promoted_at_outer")}}
+        ps.close()
+
+    cpu = None if args.no_cpu_baseline else cpu_baseline(args.n, args.deg, args.rank, args.seed)
+
+    line = {
+        "metric": METRIC,
+        "value": round(main_out["steps_per_s"], 3),
+        "unit": "grad_evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(main_out["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.precision,
+        "data": "synthetic",
+        "config": {"workload": f"MaxCut SDP (C=-L/4, X_ii=1), Erdos-Renyi n={args.n} M={M} (avg degree "
+                               f"{args.deg:g}), N(0,1) weights, r={args.rank}, "
+                               f"{'BF16 R storage, FP32 arithmetic' if args.precision == 'bf16' else args.precision}",
+                   "n": args.n, "nnz": int(2 * M), "r": args.rank, "precision": args.precision},
+        "objgrad_evals_per_s": round(main_out["objgrad_evals_per_s"], 3),
+        "per_outer": per_outer,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    if modes:
+        line["modes"] = {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
+                         for k, v in modes.items()}
+    if solve is not None:
+        line["solve"] = solve
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -118,7 +118,7 @@ typedef struct {
   int32_t max_inner;         /* 500    gradient steps per subproblem                  */
   alm_bm_step_rule step_rule;/* EXACT  exact minimiser of the quartic Lbar(R - tG)    */
   double eta_fixed;          /* 1e-3   step for ALM_BM_STEP_FIXED                     */
-  alm_bm_rank_policy rank_policy; /* ADAPT p = 1 expansion of Alg. 1 lines 5-9       */
+  alm_bm_rank_policy rank_policy; /* ADAPT p = 1 rank step of Alg. 1                 */
   int32_t r_cap;             /* 0 -> min(r_max, floor((sqrt(8m+1)-1)/2))              */
   double tau_rank;           /* <= 0 -> eps_kkt (1 + ||C||_F)                        */
   int32_t expand_needs_inner;/* 1      expand only after an inner solve converged     */
@@ -131,6 +131,9 @@ typedef struct {
   int32_t verbose;           /* 0      1: one line per outer iteration on stderr      */
   double time_limit_s;       /* 0      > 0: stop (NOT_CONVERGED) after this wall time  */
   int32_t bf16_promote;      /* 1      BF16 handle: ladder to float storage when stalled */
+  int32_t refresh_every;     /* 0 -> 32 (F64), 16 (F32), 4 (BF16): inner steps between
+                                full sparse evaluations of C R; in between, C R is
+                                carried as C R - t C G (1 = always recompute)      */
 } alm_bm_options;
 
 typedef struct {
@@ -201,6 +204,16 @@ alm_bm_status alm_bm_lanczos_min_eig(alm_bm_problem* prob, const double* y, int3
                                      double tol, uint64_t seed, double* theta, double* v,
                                      double* resid, int32_t* iters, hipStream_t stream);
 
+/* The inner loop of alm_bm_solve on its own: gradient descent with exact line
+ * search on eq. (AL-BM) at fixed y from R (in place, device n x r), until
+ * ||G||_F ||R||_F <= tol (1 + |<C, RR^T>|) or max_steps steps.  opts (host,
+ * nullable): sigma, step_rule, eta_fixed, graph_unroll, refresh_every are used.
+ * steps_done, stop_flag (1 tolerance met, 2 step limit), f_last (objective at
+ * the final R): host, nullable.  Synchronous.                                  */
+alm_bm_status alm_bm_inner_solve(alm_bm_problem* prob, const alm_bm_options* opts, int32_t r, void* R,
+                                 const double* y, double tol, int32_t max_steps, int32_t* steps_done,
+                                 int32_t* stop_flag, double* f_last, hipStream_t stream);
+
 /* Full ALM-BM solve (Alg. 1, ALORA, with p = 1 rank adaptation).
  * R: device buffer of n x r_max elements; its first n*(*r) elements hold the
  * starting factor (row stride *r) and on return the final factor (row stride
@@ -210,6 +223,20 @@ alm_bm_status alm_bm_lanczos_min_eig(alm_bm_problem* prob, const double* y, int3
  * max_outer or the time limit ran out (outputs still valid).                   */
 alm_bm_status alm_bm_solve(alm_bm_problem* prob, const alm_bm_options* opts, void* R,
                            int32_t* r, double* y, alm_bm_result* out, hipStream_t stream);
+
+/* Kernel tiling of this handle's row kernels.  variant picks an alternative
+ * (lanes per row, columns per lane) tile for the same rank, 0..2 (0 = default);
+ * row_blocks is the grid of the row kernels, a multiple of 8 in
+ * [8, max_row_blocks] (0 = default).  Results stay deterministic for a fixed
+ * choice; different choices sum in different orders.                          */
+alm_bm_status alm_bm_set_tiles(alm_bm_problem* prob, int32_t variant, int32_t row_blocks);
+
+/* Autotuner: times reps objective/gradient passes at rank r for every
+ * (variant, row_blocks) candidate with HIP events on `stream`, keeps the
+ * fastest in the handle and returns it (host int32 each, nullable).  Uses the
+ * handle's workspace as input (values do not affect the timing).              */
+alm_bm_status alm_bm_autotune(alm_bm_problem* prob, int32_t r, int32_t reps, int32_t* variant,
+                              int32_t* row_blocks, hipStream_t stream);
 
 /* Relative KKT measure of Sec. 6 at (RR^T, y) with lambda_min supplied by the
  * caller (host double); kkt_out: host array of 6 doubles

@@ -5,7 +5,7 @@ y0 (zero by default, as Alg. 1 initialises it); each outer iteration
 approximately minimises the BM subproblem eq. (AL-BM) by gradient descent
 (eq. GD, Sec. 4.2), then looks at the smallest eigenpair of
 grad_X L = C - A*(y + sigma (b - A(RR^T))), expands the factor by one column
-when that eigenvalue is sufficiently negative (p = 1 case of Alg. 1 lines 5-9),
+when that eigenvalue is sufficiently negative (p = 1 case of the rank step of Alg. 1),
 then updates y (eq. ALM) and tests the relative KKT measure of Sec. 6.
 
 Readings where the paper is silent (shared with the HIP path through the

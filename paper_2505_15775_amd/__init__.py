@@ -225,12 +225,37 @@ class Problem:
                                          _ptr(rs), _ptr(it), _stream(stream)), "lanczos_min_eig")
         return float(th.item()), v, float(rs.item()), int(it.item())
 
+    def set_tiles(self, variant=0, row_blocks=0):
+        check(lib.alm_bm_set_tiles(self._h, int(variant), int(row_blocks)), "set_tiles")
+
+    def autotune(self, r, reps=5, stream=None):
+        """Pick the fastest (tile variant, row-kernel grid) for rank r; returns it."""
+        v = C.c_int32(0)
+        nb = C.c_int32(0)
+        check(lib.alm_bm_autotune(self._h, int(r), int(reps), C.byref(v), C.byref(nb), _stream(stream)), "autotune")
+        return v.value, nb.value
+
     def kkt(self, R, y, lam_min, stream=None):
         self._check_R(R)
         self._check_y(y)
         out = (C.c_double * 6)()
         check(lib.alm_bm_kkt(self._h, R.shape[1], _ptr(R), _ptr(y), float(lam_min), out, _stream(stream)), "kkt")
         return dict(zip(["pinf", "dinf", "gap", "kkt", "pobj", "dobj"], list(out)))
+
+    def inner_solve(self, R, y, tol, max_steps, stream=None, **opts):
+        """Inner gradient loop at fixed y, R (device, handle precision) in place.
+        Returns (steps_done, stop_flag, f_last)."""
+        self._check_R(R)
+        self._check_y(y)
+        o = default_options()
+        for k, v in opts.items():
+            if not hasattr(o, k):
+                raise KeyError(f"unknown option {k!r}")
+            setattr(o, k, v)
+        sd, fl, fv = C.c_int32(0), C.c_int32(0), C.c_double(0.0)
+        check(lib.alm_bm_inner_solve(self._h, C.byref(o), R.shape[1], _ptr(R), _ptr(y), float(tol), int(max_steps),
+                                     C.byref(sd), C.byref(fl), C.byref(fv), _stream(stream)), "inner_solve")
+        return sd.value, fl.value, fv.value
 
     def solve(self, R0, y0=None, stream=None, **opts):
         """Full ALM-BM solve.  R0: n x r0 factor (any device/dtype), y0: m vector or

@@ -75,6 +75,7 @@ class Options(C.Structure):
         ("verbose", C.c_int32),
         ("time_limit_s", C.c_double),
         ("bf16_promote", C.c_int32),
+        ("refresh_every", C.c_int32),
     ]
 
 
@@ -104,7 +105,8 @@ class Result(C.Structure):
 EXPORTS = [
     "alm_bm_create", "alm_bm_destroy", "alm_bm_objective_grad", "alm_bm_line_search", "alm_bm_dual_update",
     "alm_bm_lanczos_min_eig", "alm_bm_solve", "alm_bm_kkt", "alm_bm_default_options", "alm_bm_last_error",
-    "alm_bm_maxcut_cost_host", "alm_bm_abi_sizes", "alm_bm_gd_step",
+    "alm_bm_maxcut_cost_host", "alm_bm_abi_sizes", "alm_bm_gd_step", "alm_bm_set_tiles", "alm_bm_autotune",
+    "alm_bm_inner_solve",
 ]
 
 vp = C.c_void_p
@@ -132,6 +134,10 @@ def _load():
         "alm_bm_last_error": (C.c_char_p, []),
         "alm_bm_maxcut_cost_host": (i32, [i64, i64, vp, vp, vp, vp, vp, vp, vp, C.POINTER(i64)]),
         "alm_bm_abi_sizes": (None, [C.POINTER(i64)]),
+        "alm_bm_set_tiles": (i32, [vp, i32, i32]),
+        "alm_bm_inner_solve": (i32, [vp, C.POINTER(Options), i32, vp, vp, f64, i32, C.POINTER(i32), C.POINTER(i32),
+                                     C.POINTER(f64), vp]),
+        "alm_bm_autotune": (i32, [vp, i32, i32, C.POINTER(i32), C.POINTER(i32), vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

@@ -48,6 +48,7 @@ struct alm_bm_problem {
   EdgeAdj adj{};
   double* wE = nullptr;
   int nblk = 0;
+  int max_blocks = 0;
   int variant = 0;
   double* part = nullptr;     // nblk * (NUM_P + kMaxR)
   double* part_c2 = nullptr;  // nblk
@@ -57,6 +58,7 @@ struct alm_bm_problem {
   DevScalars* sc_host = nullptr;  // pinned mirror
   void* G = nullptr;              // n * r_max storage
   void* Rtmp = nullptr;           // n * r_max storage
+  void* Qbuf = nullptr;           // n * r_max arithmetic type: C G of the inner loop
   void* R32 = nullptr;            // float factor, gradient and relayout scratch for
   void* G32 = nullptr;            //   the BF16 -> float precision ladder
   void* Rt32 = nullptr;
@@ -237,6 +239,7 @@ extern "C" void alm_bm_default_options(alm_bm_options* o) {
   o->verbose = 0;
   o->time_limit_s = 0.0;
   o->bf16_promote = 1;
+  o->refresh_every = 0;
 }
 
 extern "C" const char* alm_bm_last_error(void) { return g_err.c_str(); }
@@ -254,6 +257,14 @@ static int row_blocks(long n) {
   long nb = (n + 63) / 64;
   if (nb < 8) nb = 8;
   if (nb > 4096) nb = 4096;
+  return (int)((nb + 7) / 8 * 8);
+}
+
+// Largest grid a handle supports (blocks of fewer than 8 rows are pointless).
+static int max_row_blocks(long n) {
+  long nb = (n + 7) / 8;
+  if (nb < 8) nb = 8;
+  if (nb > 16384) nb = 16384;
   return (int)((nb + 7) / 8 * 8);
 }
 
@@ -414,13 +425,15 @@ extern "C" alm_bm_status alm_bm_create(const alm_bm_problem_desc* desc, hipStrea
 
   // ---- workspace
   p->nblk = row_blocks(n);
+  p->max_blocks = std::max(p->nblk, max_row_blocks(n));
   const size_t es = esize(d.precision);
-  CK(dalloc_t(p, &p->part, (size_t)p->nblk * (NUM_P + kMaxR)));
-  CK(dalloc_t(p, &p->part_c2, (size_t)p->nblk));
+  CK(dalloc_t(p, &p->part, (size_t)p->max_blocks * (NUM_P + kMaxR)));
+  CK(dalloc_t(p, &p->part_c2, (size_t)p->max_blocks));
   CK(dalloc_t(p, &p->sc_api, 1));
   CK(dalloc_t(p, &p->sc_solve, 1));
   CK(dalloc(p, &p->G, (size_t)n * d.r_max * es));
   CK(dalloc(p, &p->Rtmp, (size_t)n * d.r_max * es));
+  CK(dalloc(p, &p->Qbuf, (size_t)n * d.r_max * (d.precision == ALM_BM_F64 ? 8 : 4)));
   CK(dalloc_t(p, &p->Av, d.m));
   CK(dalloc_t(p, &p->ybuf, d.m));
   p->lnb = vec_blocks(n);
@@ -471,7 +484,7 @@ static void enqueue_objgrad(alm_bm_problem* p, int r, const T* R, const double* 
                             DevScalars* sc, int mode, double* f_out, hipStream_t st) {
   const auto& d = p->d;
   if (d.cons_kind == ALM_BM_CONS_DIAG) {
-    launch_objgrad_diag<T>(cost_of<T>(p), r, p->variant, R, y, d.b, sigma, G, Av, p->part, sc, p->nblk, st);
+    launch_objgrad_diag<T>(cost_of<T>(p), r, p->variant, R, y, d.b, sigma, G, Av, p->part, sc, 0, p->nblk, st);
     launch_fin_objgrad(p->part, p->nblk, sc, sigma, mode, f_out, st);
   } else {
     launch_edges_p1<T>(p->adj, d.n, r, p->variant, R, y, d.b, sigma, Av, p->wE, p->part, sc, p->nblk, st);
@@ -482,21 +495,36 @@ static void enqueue_objgrad(alm_bm_problem* p, int r, const T* R, const double* 
   }
 }
 
-// One inner gradient step (flag-guarded): objective/gradient, stop test,
-// exact line search, update.
+// One inner gradient step (flag-guarded, decisions taken on the device):
+// DIAG family: apply the pending step and evaluate the new gradient from the
+// carried cost product (or, every `refresh` steps, with the full sparse pass),
+// stop test, line-search product Q = C G, step choice.  One sparse product per
+// step except on refresh steps.
+// TRACE_EDGES family: full evaluation, stop test, line search, update.
 template <typename T>
-static void enqueue_inner_step(alm_bm_problem* p, int r, T* R, const double* y, double sigma, T* G, hipStream_t st) {
+static void enqueue_inner_step(alm_bm_problem* p, int r, T* R, const double* y, double sigma, T* G, int refresh,
+                               hipStream_t st) {
+  using V = typename Acc<T>::type;
   const auto& d = p->d;
   DevScalars* sc = p->sc_solve;
-  enqueue_objgrad<T>(p, r, R, y, sigma, G, p->Av, sc, 1, nullptr, st);
   if (d.cons_kind == ALM_BM_CONS_DIAG) {
-    launch_quad_diag<T>(cost_of<T>(p), r, p->variant, G, p->part_c2, sc, p->nblk, st);
+    V* Q = static_cast<V*>(p->Qbuf);
+    launch_upd_eval_diag<T>(d.n, r, p->variant, R, G, Q, y, d.b, sigma, p->Av, p->part, sc, refresh, p->nblk, st);
+    launch_objgrad_diag<T>(cost_of<T>(p), r, p->variant, R, y, d.b, sigma, G, p->Av, p->part, sc, refresh, p->nblk,
+                           st);
+    launch_fin_objgrad(p->part, p->nblk, sc, sigma, 1, nullptr, st);
+    launch_quadq_diag<T>(cost_of<T>(p), r, p->variant, G, Q, p->part_c2, sc, p->nblk, st);
     launch_fin_step(p->part_c2, p->nblk, 1, sc, sigma, 0.0, 1, nullptr, nullptr, st);
   } else {
+    enqueue_objgrad<T>(p, r, R, y, sigma, G, p->Av, sc, 1, nullptr, st);
     launch_edges_p3<T>(cost_of<T>(p), p->adj, r, p->variant, R, G, y, d.b, p->Av, p->part, sc, p->nblk, st);
     launch_fin_edges3(p->part, p->nblk, r, sc, y, d.b, sigma, d.trace_coef, d.j_coef, 1, nullptr, nullptr, st);
+    launch_update<T>((long)d.n * r, R, G, sc, 1, st);
   }
-  launch_update<T>((long)d.n * r, R, G, sc, 1, st);
+}
+
+static int default_refresh(alm_bm_precision prec) {
+  return prec == ALM_BM_F64 ? 32 : (prec == ALM_BM_F32 ? 16 : 4);
 }
 
 static alm_bm_status check_r(const alm_bm_problem* p, int r) {
@@ -574,6 +602,73 @@ extern "C" alm_bm_status alm_bm_dual_update(alm_bm_problem* p, const double* Av,
                                             double* pinf, hipStream_t st) {
   if (!p || !Av || !y) return fail(ALM_BM_ERR_INVALID_ARG, "dual_update: null argument");
   launch_dual(p->d.m, Av, p->d.b, y, y, sigma, p->part_vec, p->sc_api, p->bnorm, pinf, st);
+  HIPCHK(hipGetLastError());
+  return ALM_BM_OK;
+}
+
+// --------------------------------------------------------------------- tiling
+
+extern "C" alm_bm_status alm_bm_set_tiles(alm_bm_problem* p, int32_t variant, int32_t row_blocks_) {
+  if (!p) return fail(ALM_BM_ERR_INVALID_ARG, "set_tiles: null handle");
+  if (variant < 0 || variant > 2) return fail(ALM_BM_ERR_INVALID_ARG, "set_tiles: variant must be 0..2");
+  int nb = row_blocks_ == 0 ? row_blocks(p->d.n) : row_blocks_;
+  if (nb < 8 || nb % 8 != 0 || nb > p->max_blocks)
+    return fail(ALM_BM_ERR_INVALID_ARG, "set_tiles: row_blocks must be a multiple of 8 in [8, " +
+                                            std::to_string(p->max_blocks) + "]");
+  p->variant = variant;
+  p->nblk = nb;
+  return ALM_BM_OK;
+}
+
+extern "C" alm_bm_status alm_bm_autotune(alm_bm_problem* p, int32_t r, int32_t reps, int32_t* variant_out,
+                                         int32_t* blocks_out, hipStream_t st) {
+  if (!p) return fail(ALM_BM_ERR_INVALID_ARG, "autotune: null handle");
+  STCHK(check_r(p, r));
+  if (reps < 1) return fail(ALM_BM_ERR_INVALID_ARG, "autotune: reps < 1");
+  const auto& d = p->d;
+  HIPCHK(hipMemsetAsync(p->Rtmp, 0, (size_t)d.n * r * esize(d.precision), st));
+  HIPCHK(hipMemsetAsync(p->ybuf, 0, (size_t)d.m * sizeof(double), st));
+  std::vector<int> cands;
+  for (int nb : {row_blocks(d.n), 1024, 2048, 4096, 8192, 16384})
+    if (nb >= 8 && nb % 8 == 0 && nb <= p->max_blocks &&
+        std::find(cands.begin(), cands.end(), nb) == cands.end())
+      cands.push_back(nb);
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  float best = INFINITY;
+  int bv = p->variant, bb = p->nblk;
+  for (int v = 0; v <= 2; ++v) {
+    for (int nb : cands) {
+      p->variant = v;
+      p->nblk = nb;
+      auto run = [&]() {
+        with_storage(d.precision, [&]<typename T>() {
+          enqueue_objgrad<T>(p, r, static_cast<const T*>(p->Rtmp), p->ybuf, 1.0, static_cast<T*>(p->G), p->Av,
+                             p->sc_api, 0, nullptr, st);
+          return 0;
+        });
+      };
+      run();  // warm
+      HIPCHK(hipEventRecord(e0, st));
+      for (int k = 0; k < reps; ++k) run();
+      HIPCHK(hipEventRecord(e1, st));
+      HIPCHK(hipEventSynchronize(e1));
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+      if (ms < best) {
+        best = ms;
+        bv = v;
+        bb = nb;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  p->variant = bv;
+  p->nblk = bb;
+  if (variant_out) *variant_out = bv;
+  if (blocks_out) *blocks_out = bb;
   HIPCHK(hipGetLastError());
   return ALM_BM_OK;
 }
@@ -822,6 +917,7 @@ struct GraphCache {
   hipGraphExec_t exec = nullptr;
   hipGraph_t graph = nullptr;
   int r = -1;
+  int refresh = -1;
   const void* R = nullptr;
   void reset() {
     if (exec) (void)hipGraphExecDestroy(exec);
@@ -851,6 +947,8 @@ template <typename T>
 static alm_bm_status inner_solve(alm_bm_problem* p, int r, T* R, const double* y, double sigma, double tol,
                                  const alm_bm_options& o, GraphCache& gc, hipStream_t st, int& iters, int& flag) {
   T* G = static_cast<T*>(p->G);
+  const int refresh = o.refresh_every > 0 ? o.refresh_every : default_refresh(sizeof(T) == 8 ? ALM_BM_F64
+                                                                  : (sizeof(T) == 4 ? ALM_BM_F32 : ALM_BM_BF16));
   launch_inner_reset(p->sc_solve, tol, o.max_inner, (int)o.step_rule, o.eta_fixed, st);
   const int U = std::max(0, o.graph_unroll);
   int32_t hflag = 0;
@@ -858,19 +956,20 @@ static alm_bm_status inner_solve(alm_bm_problem* p, int r, T* R, const double* y
   int launched = 0;
   while (true) {
     if (U > 0) {
-      if (gc.r != r || gc.R != (const void*)R) {
+      if (gc.r != r || gc.R != (const void*)R || gc.refresh != refresh) {
         gc.reset();
         HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-        for (int u = 0; u < U; ++u) enqueue_inner_step<T>(p, r, R, y, sigma, G, st);
+        for (int u = 0; u < U; ++u) enqueue_inner_step<T>(p, r, R, y, sigma, G, refresh, st);
         HIPCHK(hipStreamEndCapture(st, &gc.graph));
         HIPCHK(hipGraphInstantiate(&gc.exec, gc.graph, nullptr, nullptr, 0));
         gc.r = r;
         gc.R = R;
+        gc.refresh = refresh;
       }
       HIPCHK(hipGraphLaunch(gc.exec, st));
       launched += U;
     } else {
-      enqueue_inner_step<T>(p, r, R, y, sigma, G, st);
+      enqueue_inner_step<T>(p, r, R, y, sigma, G, refresh, st);
       launched += 1;
     }
     HIPCHK(hipMemcpyAsync(&p->sc_host->flag, &p->sc_solve->flag, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
@@ -980,6 +1079,34 @@ static alm_bm_status solve_impl(alm_bm_problem* p, const alm_bm_options& o, T* R
     }
   }
   return ALM_BM_NOT_CONVERGED;
+}
+
+extern "C" alm_bm_status alm_bm_inner_solve(alm_bm_problem* p, const alm_bm_options* opts, int32_t r, void* R,
+                                            const double* y, double tol, int32_t max_steps, int32_t* steps_done,
+                                            int32_t* stop_flag, double* f_last, hipStream_t st_user) {
+  if (!p || !R || !y) return fail(ALM_BM_ERR_INVALID_ARG, "inner_solve: null argument");
+  STCHK(check_r(p, r));
+  if (max_steps < 0) return fail(ALM_BM_ERR_INVALID_ARG, "inner_solve: max_steps < 0");
+  alm_bm_options o;
+  if (opts) o = *opts;
+  else alm_bm_default_options(&o);
+  if (!(o.sigma > 0.0)) return fail(ALM_BM_ERR_INVALID_ARG, "inner_solve: sigma must be positive");
+  o.max_inner = max_steps;
+  HIPCHK(hipStreamSynchronize(st_user));
+  hipStream_t st = p->ss;
+  int iters = 0, flag = 0;
+  GraphCache gc;
+  alm_bm_status s = with_storage(p->d.precision, [&]<typename T>() {
+    return inner_solve<T>(p, r, static_cast<T*>(R), y, o.sigma, tol, o, gc, st, iters, flag);
+  });
+  if (s < 0) return s;
+  HIPCHK(hipMemcpyAsync(p->sc_host, p->sc_solve, sizeof(DevScalars), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (steps_done) *steps_done = iters;
+  if (stop_flag) *stop_flag = flag;
+  if (f_last) *f_last = p->sc_host->f;
+  if (p->sc_host->numeric_error) return fail(ALM_BM_ERR_NUMERIC, "inner_solve: NaN/Inf");
+  return ALM_BM_OK;
 }
 
 extern "C" alm_bm_status alm_bm_solve(alm_bm_problem* p, const alm_bm_options* opts, void* R, int32_t* r_io,

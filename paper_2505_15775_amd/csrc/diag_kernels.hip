@@ -20,15 +20,16 @@ __global__ void __launch_bounds__(kBlock)
 k_objgrad_diag(Cost<typename Acc<T>::type> C, int r, const T* __restrict__ R,
                const double* __restrict__ y, const double* __restrict__ b, double sigma,
                T* __restrict__ G, double* __restrict__ Av, double* __restrict__ part,
-               const DevScalars* __restrict__ sc) {
+               const DevScalars* __restrict__ sc, int refresh_every) {
   using V = typename Acc<T>::type;
   if (sc && sc->flag) return;
+  // inside the inner loop this full pass runs only on refresh iterations
+  if (sc && refresh_every > 1 && (sc->iter % refresh_every) != 0) return;
   constexpr int RPB = kBlock / LPR;
   const int lane = threadIdx.x % LPR;
   const int slot = threadIdx.x / LPR;
-  double acc[NUM_P];
-#pragma unroll
-  for (int s = 0; s < NUM_P; ++s) acc[s] = 0.0;
+  SplitAcc<NUM_P, LPR> acc;
+  acc.zero();
   const RowChunk ch = row_chunk(C.n);
   for (long base = ch.lo; base < ch.hi; base += RPB) {
     const long i = base + slot;
@@ -63,26 +64,26 @@ k_objgrad_diag(Cost<typename Acc<T>::type> C, int r, const T* __restrict__ R,
     gg = group_sum<LPR>(gg);
     gp = group_sum<LPR>(gp);
     rg = group_sum<LPR>(rg);
-    if (lane == 0) {
-      if (Av) Av[i] = ai;
+    if (lane == 0 && Av) Av[i] = ai;
+    {
       const double a1 = 2.0 * (double)rg, a2 = (double)gg;
-      acc[P_C0] += (double)rp;
-      acc[P_YBMA] += yi * (b[i] - ai);
-      acc[P_EE] += ei * ei;
-      acc[P_GG] += a2;
-      acc[P_GP] += (double)gp;
-      acc[P_YA1] += yi * a1;
-      acc[P_YA2] += yi * a2;
-      acc[P_EA1] += ei * a1;
-      acc[P_EA2] += ei * a2;
-      acc[P_A1A1] += a1 * a1;
-      acc[P_A1A2] += a1 * a2;
-      acc[P_A2A2] += a2 * a2;
-      acc[P_RR] += ai;
-      acc[P_RG] += (double)rg;
+      acc.add(lane, P_C0, (double)rp);
+      acc.add(lane, P_YBMA, yi * (b[i] - ai));
+      acc.add(lane, P_EE, ei * ei);
+      acc.add(lane, P_GG, a2);
+      acc.add(lane, P_GP, (double)gp);
+      acc.add(lane, P_YA1, yi * a1);
+      acc.add(lane, P_YA2, yi * a2);
+      acc.add(lane, P_EA1, ei * a1);
+      acc.add(lane, P_EA2, ei * a2);
+      acc.add(lane, P_A1A1, a1 * a1);
+      acc.add(lane, P_A1A2, a1 * a2);
+      acc.add(lane, P_A2A2, a2 * a2);
+      acc.add(lane, P_RR, ai);
+      acc.add(lane, P_RG, (double)rg);
     }
   }
-  block_sum_store<NUM_P>(acc, part + (long)blockIdx.x * NUM_P);
+  acc.block_store(lane, part + (long)blockIdx.x * NUM_P);
 }
 
 // c2 = <G, C G> for the quartic line search (sparse product of the direction).
@@ -112,6 +113,125 @@ k_quad_diag(Cost<typename Acc<T>::type> C, int r, const T* __restrict__ G,
   block_sum_store<1>(acc, part + blockIdx.x);
 }
 
+
+// Line-search product of the inner loop: Q = C G stored (arithmetic type) for
+// the next step's cost product, and the partial sums of <G, C G>.
+template <typename T, int LPR, int VEC, bool FULL>
+__global__ void __launch_bounds__(kBlock)
+k_quadq_diag(Cost<typename Acc<T>::type> C, int r, const T* __restrict__ G, typename Acc<T>::type* __restrict__ Q,
+             double* __restrict__ part, const DevScalars* __restrict__ sc) {
+  using V = typename Acc<T>::type;
+  if (sc->flag) return;
+  constexpr int RPB = kBlock / LPR;
+  const int lane = threadIdx.x % LPR;
+  const int slot = threadIdx.x / LPR;
+  double acc[1] = {0.0};
+  const RowChunk ch = row_chunk(C.n);
+  for (long base = ch.lo; base < ch.hi; base += RPB) {
+    const long i = base + slot;
+    if (i >= ch.hi) break;
+    V gi[VEC], q[VEC];
+    load_frag<T, VEC, FULL>(G + i * r, lane, r, gi);
+    spmm_row<T, LPR, VEC, FULL>(C, i, lane, r, G, gi, q);
+    store_frag<V, VEC, FULL>(Q + i * r, lane, r, q);
+    V gq = 0;
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) gq += gi[v] * q[v];
+    gq = group_sum<LPR>(gq);
+    if (lane == 0) acc[0] += (double)gq;
+  }
+  block_sum_store<1>(acc, part + blockIdx.x);
+}
+
+// Start of an inner iteration: apply the pending step R <- R - t G and, except
+// on refresh iterations, evaluate the new gradient without a sparse product.
+// The cost product is carried implicitly: before the step P = C R = G/2 + w R
+// (w from the stored A(RR^T)), and C (R - t G) = P - t Q with Q = C G from the
+// line search, so G_new = 2 (P - t Q - w_new R_new).  Refresh iterations
+// (every refresh_every steps) recompute C R with the full sparse pass instead,
+// which bounds the drift of the recurrence in reduced precision.
+template <typename T, int LPR, int VEC, bool FULL>
+__global__ void __launch_bounds__(kBlock)
+k_upd_eval_diag(long n, int r, T* __restrict__ R, T* __restrict__ G, const typename Acc<T>::type* __restrict__ Q,
+                const double* __restrict__ y, const double* __restrict__ b, double sigma, double* __restrict__ Av,
+                double* __restrict__ part, const DevScalars* __restrict__ sc, int refresh_every) {
+  using V = typename Acc<T>::type;
+  if (sc->flag) return;
+  const int e = sc->iter;
+  if (e == 0) return;
+  const bool update_only = refresh_every <= 1 || (e % refresh_every) == 0;
+  const V t = static_cast<V>(sc->t);
+  constexpr int RPB = kBlock / LPR;
+  const int lane = threadIdx.x % LPR;
+  const int slot = threadIdx.x / LPR;
+  SplitAcc<NUM_P, LPR> acc;
+  acc.zero();
+  const RowChunk ch = row_chunk(n);
+  for (long base = ch.lo; base < ch.hi; base += RPB) {
+    const long i = base + slot;
+    if (i >= ch.hi) break;
+    V ri[VEC], gi[VEC];
+    load_frag<T, VEC, FULL>(R + i * r, lane, r, ri);
+    load_frag<T, VEC, FULL>(G + i * r, lane, r, gi);
+    V rn[VEC];
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) rn[v] = round_st<T>(ri[v] - t * gi[v]);
+    store_frag<T, VEC, FULL>(R + i * r, lane, r, rn);
+    if (update_only) continue;
+    V qi[VEC];
+    load_frag<V, VEC, FULL>(Q + i * r, lane, r, qi);
+    const double yi = y[i], bi = b[i];
+    const V w_old = static_cast<V>(yi - sigma * (Av[i] - bi));
+    V p[VEC];
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) p[v] = V(0.5) * gi[v] + w_old * ri[v] - t * qi[v];
+    V rr = 0, rp = 0;
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) {
+      rr += rn[v] * rn[v];
+      rp += rn[v] * p[v];
+    }
+    rr = group_sum<LPR>(rr);
+    rp = group_sum<LPR>(rp);
+    const double ai = rr;
+    const double ei = ai - bi;
+    const V wv = static_cast<V>(yi - sigma * ei);
+    V g[VEC];
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) g[v] = round_st<T>(V(2) * (p[v] - wv * rn[v]));
+    store_frag<T, VEC, FULL>(G + i * r, lane, r, g);
+    V gg = 0, gp = 0, rg = 0;
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) {
+      gg += g[v] * g[v];
+      gp += g[v] * p[v];
+      rg += rn[v] * g[v];
+    }
+    gg = group_sum<LPR>(gg);
+    gp = group_sum<LPR>(gp);
+    rg = group_sum<LPR>(rg);
+    if (lane == 0) Av[i] = ai;
+    {
+      const double a1 = 2.0 * (double)rg, a2 = (double)gg;
+      acc.add(lane, P_C0, (double)rp);
+      acc.add(lane, P_YBMA, yi * (bi - ai));
+      acc.add(lane, P_EE, ei * ei);
+      acc.add(lane, P_GG, a2);
+      acc.add(lane, P_GP, (double)gp);
+      acc.add(lane, P_YA1, yi * a1);
+      acc.add(lane, P_YA2, yi * a2);
+      acc.add(lane, P_EA1, ei * a1);
+      acc.add(lane, P_EA2, ei * a2);
+      acc.add(lane, P_A1A1, a1 * a1);
+      acc.add(lane, P_A1A2, a1 * a2);
+      acc.add(lane, P_A2A2, a2 * a2);
+      acc.add(lane, P_RR, ai);
+      acc.add(lane, P_RG, (double)rg);
+    }
+  }
+  if (!update_only) acc.block_store(lane, part + (long)blockIdx.x * NUM_P);
+}
+
 // All line-search partials for an arbitrary direction G (API entry point).
 template <typename T, int LPR, int VEC, bool FULL>
 __global__ void __launch_bounds__(kBlock)
@@ -122,9 +242,8 @@ k_ls_diag(Cost<typename Acc<T>::type> C, int r, const T* __restrict__ R, const T
   constexpr int RPB = kBlock / LPR;
   const int lane = threadIdx.x % LPR;
   const int slot = threadIdx.x / LPR;
-  double acc[NUM_P];
-#pragma unroll
-  for (int s = 0; s < NUM_P; ++s) acc[s] = 0.0;
+  SplitAcc<NUM_P, LPR> acc;
+  acc.zero();
   const RowChunk ch = row_chunk(C.n);
   for (long base = ch.lo; base < ch.hi; base += RPB) {
     const long i = base + slot;
@@ -150,27 +269,27 @@ k_ls_diag(Cost<typename Acc<T>::type> C, int r, const T* __restrict__ R, const T
     gp = group_sum<LPR>(gp);
     rg = group_sum<LPR>(rg);
     gq = group_sum<LPR>(gq);
-    if (lane == 0) {
+    {
       const double ai = rr, yi = y[i], ei = ai - b[i];
       const double a1 = 2.0 * (double)rg, a2 = (double)gg;
-      acc[P_C0] += (double)rp;
-      acc[P_YBMA] += yi * (b[i] - ai);
-      acc[P_EE] += ei * ei;
-      acc[P_GG] += a2;
-      acc[P_GP] += (double)gp;
-      acc[P_YA1] += yi * a1;
-      acc[P_YA2] += yi * a2;
-      acc[P_EA1] += ei * a1;
-      acc[P_EA2] += ei * a2;
-      acc[P_A1A1] += a1 * a1;
-      acc[P_A1A2] += a1 * a2;
-      acc[P_A2A2] += a2 * a2;
-      acc[P_RR] += ai;
-      acc[P_RG] += (double)rg;
-      acc[P_C2] += (double)gq;
+      acc.add(lane, P_C0, (double)rp);
+      acc.add(lane, P_YBMA, yi * (b[i] - ai));
+      acc.add(lane, P_EE, ei * ei);
+      acc.add(lane, P_GG, a2);
+      acc.add(lane, P_GP, (double)gp);
+      acc.add(lane, P_YA1, yi * a1);
+      acc.add(lane, P_YA2, yi * a2);
+      acc.add(lane, P_EA1, ei * a1);
+      acc.add(lane, P_EA2, ei * a2);
+      acc.add(lane, P_A1A1, a1 * a1);
+      acc.add(lane, P_A1A2, a1 * a2);
+      acc.add(lane, P_A2A2, a2 * a2);
+      acc.add(lane, P_RR, ai);
+      acc.add(lane, P_RG, (double)rg);
+      acc.add(lane, P_C2, (double)gq);
     }
   }
-  block_sum_store<NUM_P>(acc, part + (long)blockIdx.x * NUM_P);
+  acc.block_store(lane, part + (long)blockIdx.x * NUM_P);
 }
 
 // ---- launchers -----------------------------------------------------------------
@@ -178,13 +297,34 @@ k_ls_diag(Cost<typename Acc<T>::type> C, int r, const T* __restrict__ R, const T
 template <typename T, int LPR, int VEC>
 static void launch_objgrad_cfg(const Cost<typename Acc<T>::type>& C, int r, const T* R, const double* y,
                                const double* b, double sigma, T* G, double* Av, double* part,
-                               const DevScalars* sc, int nblk, hipStream_t st) {
+                               const DevScalars* sc, int refresh_every, int nblk, hipStream_t st) {
   if (r == LPR * VEC)
     hipLaunchKernelGGL((k_objgrad_diag<T, LPR, VEC, true>), dim3(nblk), dim3(kBlock), 0, st, C, r, R, y, b,
-                       sigma, G, Av, part, sc);
+                       sigma, G, Av, part, sc, refresh_every);
   else
     hipLaunchKernelGGL((k_objgrad_diag<T, LPR, VEC, false>), dim3(nblk), dim3(kBlock), 0, st, C, r, R, y, b,
-                       sigma, G, Av, part, sc);
+                       sigma, G, Av, part, sc, refresh_every);
+}
+
+template <typename T, int LPR, int VEC>
+static void launch_quadq_cfg(const Cost<typename Acc<T>::type>& C, int r, const T* G, typename Acc<T>::type* Q,
+                             double* part, const DevScalars* sc, int nblk, hipStream_t st) {
+  if (r == LPR * VEC)
+    hipLaunchKernelGGL((k_quadq_diag<T, LPR, VEC, true>), dim3(nblk), dim3(kBlock), 0, st, C, r, G, Q, part, sc);
+  else
+    hipLaunchKernelGGL((k_quadq_diag<T, LPR, VEC, false>), dim3(nblk), dim3(kBlock), 0, st, C, r, G, Q, part, sc);
+}
+
+template <typename T, int LPR, int VEC>
+static void launch_upd_eval_cfg(long n, int r, T* R, T* G, const typename Acc<T>::type* Q, const double* y,
+                                const double* b, double sigma, double* Av, double* part, const DevScalars* sc,
+                                int refresh_every, int nblk, hipStream_t st) {
+  if (r == LPR * VEC)
+    hipLaunchKernelGGL((k_upd_eval_diag<T, LPR, VEC, true>), dim3(nblk), dim3(kBlock), 0, st, n, r, R, G, Q, y, b,
+                       sigma, Av, part, sc, refresh_every);
+  else
+    hipLaunchKernelGGL((k_upd_eval_diag<T, LPR, VEC, false>), dim3(nblk), dim3(kBlock), 0, st, n, r, R, G, Q, y, b,
+                       sigma, Av, part, sc, refresh_every);
 }
 
 template <typename T, int LPR, int VEC>
@@ -245,8 +385,21 @@ static void launch_ls_cfg(const Cost<typename Acc<T>::type>& C, int r, const T* 
 template <typename T>
 void launch_objgrad_diag(const Cost<typename Acc<T>::type>& C, int r, int variant, const T* R, const double* y,
                          const double* b, double sigma, T* G, double* Av, double* part, const DevScalars* sc,
-                         int nblk, hipStream_t st) {
-  ALMBM_DISPATCH_DIAG(T, launch_objgrad_cfg, C, r, R, y, b, sigma, G, Av, part, sc, nblk, st);
+                         int refresh_every, int nblk, hipStream_t st) {
+  ALMBM_DISPATCH_DIAG(T, launch_objgrad_cfg, C, r, R, y, b, sigma, G, Av, part, sc, refresh_every, nblk, st);
+}
+
+template <typename T>
+void launch_quadq_diag(const Cost<typename Acc<T>::type>& C, int r, int variant, const T* G,
+                       typename Acc<T>::type* Q, double* part, const DevScalars* sc, int nblk, hipStream_t st) {
+  ALMBM_DISPATCH_DIAG(T, launch_quadq_cfg, C, r, G, Q, part, sc, nblk, st);
+}
+
+template <typename T>
+void launch_upd_eval_diag(long n, int r, int variant, T* R, T* G, const typename Acc<T>::type* Q, const double* y,
+                          const double* b, double sigma, double* Av, double* part, const DevScalars* sc,
+                          int refresh_every, int nblk, hipStream_t st) {
+  ALMBM_DISPATCH_DIAG(T, launch_upd_eval_cfg, n, r, R, G, Q, y, b, sigma, Av, part, sc, refresh_every, nblk, st);
 }
 
 template <typename T>
@@ -264,7 +417,12 @@ void launch_ls_diag(const Cost<typename Acc<T>::type>& C, int r, int variant, co
 #define ALMBM_INST(T)                                                                                     \
   template void launch_objgrad_diag<T>(const Cost<Acc<T>::type>&, int, int, const T*, const double*,      \
                                        const double*, double, T*, double*, double*, const DevScalars*, int, \
-                                       hipStream_t);                                                      \
+                                       int, hipStream_t);                                                 \
+  template void launch_quadq_diag<T>(const Cost<Acc<T>::type>&, int, int, const T*, Acc<T>::type*, double*, \
+                                     const DevScalars*, int, hipStream_t);                                 \
+  template void launch_upd_eval_diag<T>(long, int, int, T*, T*, const Acc<T>::type*, const double*,          \
+                                        const double*, double, double*, double*, const DevScalars*, int, int, \
+                                        hipStream_t);                                                      \
   template void launch_quad_diag<T>(const Cost<Acc<T>::type>&, int, int, const T*, double*,               \
                                     const DevScalars*, int, hipStream_t);                                 \
   template void launch_ls_diag<T>(const Cost<Acc<T>::type>&, int, int, const T*, const T*, const double*,  \

@@ -52,9 +52,8 @@ k_edges_p1(EdgeAdj A, long n, int r, const T* __restrict__ R, const double* __re
   constexpr int RPB = kBlock / LPR;
   const int lane = threadIdx.x % LPR;
   const int slot = threadIdx.x / LPR;
-  double acc[NUM_P];
-#pragma unroll
-  for (int s = 0; s < NUM_P; ++s) acc[s] = 0.0;
+  SplitAcc<NUM_P, LPR> acc;
+  acc.zero();
   double cs[VEC];
 #pragma unroll
   for (int v = 0; v < VEC; ++v) cs[v] = 0.0;
@@ -80,18 +79,18 @@ k_edges_p1(EdgeAdj A, long n, int r, const T* __restrict__ R, const double* __re
 #pragma unroll
       for (int v = 0; v < VEC; ++v) s += ri[v] * rj[v];
       s = group_sum<LPR>(s);
+      const double a = s, be = b[1 + k], ye = y[1 + k];
+      const double e = a - be;
       if (lane == 0) {
-        const double a = s, be = b[1 + k], ye = y[1 + k];
-        const double e = a - be;
         if (Av) Av[1 + k] = a;
         wE[k] = ye - sigma * e;
-        acc[P_YBMA] += ye * (be - a);
-        acc[P_EE] += e * e;
       }
+      acc.add(lane, P_YBMA, ye * (be - a));
+      acc.add(lane, P_EE, e * e);
     }
-    if (lane == 0) acc[P_RR] += (double)rr;
+    acc.add(lane, P_RR, (double)rr);
   }
-  block_sum_store<NUM_P>(acc, part + (long)blockIdx.x * kEdgePS);
+  acc.block_store(lane, part + (long)blockIdx.x * kEdgePS);
   block_colsum_store<LPR, VEC>(cs, r, part + (long)blockIdx.x * kEdgePS + NUM_P);
 }
 
@@ -146,9 +145,8 @@ k_edges_p2(Cost<typename Acc<T>::type> C, EdgeAdj A, int r, const T* __restrict_
   constexpr int RPB = kBlock / LPR;
   const int lane = threadIdx.x % LPR;
   const int slot = threadIdx.x / LPR;
-  double acc[NUM_P];
-#pragma unroll
-  for (int s = 0; s < NUM_P; ++s) acc[s] = 0.0;
+  SplitAcc<NUM_P, LPR> acc;
+  acc.zero();
   double gcs[VEC];
   V jcs[VEC];
 #pragma unroll
@@ -200,14 +198,12 @@ k_edges_p2(Cost<typename Acc<T>::type> C, EdgeAdj A, int r, const T* __restrict_
     gg = group_sum<LPR>(gg);
     gp = group_sum<LPR>(gp);
     rg = group_sum<LPR>(rg);
-    if (lane == 0) {
-      acc[P_C0] += (double)rp;
-      acc[P_GG] += (double)gg;
-      acc[P_GP] += (double)gp;
-      acc[P_RG] += (double)rg;
-    }
+    acc.add(lane, P_C0, (double)rp);
+    acc.add(lane, P_GG, (double)gg);
+    acc.add(lane, P_GP, (double)gp);
+    acc.add(lane, P_RG, (double)rg);
   }
-  block_sum_store<NUM_P>(acc, part + (long)blockIdx.x * kEdgePS);
+  acc.block_store(lane, part + (long)blockIdx.x * kEdgePS);
   block_colsum_store<LPR, VEC>(gcs, r, part + (long)blockIdx.x * kEdgePS + NUM_P);
 }
 
@@ -263,9 +259,8 @@ k_edges_p3(Cost<typename Acc<T>::type> C, EdgeAdj A, int r, const T* __restrict_
   constexpr int RPB = kBlock / LPR;
   const int lane = threadIdx.x % LPR;
   const int slot = threadIdx.x / LPR;
-  double acc[NUM_P];
-#pragma unroll
-  for (int s = 0; s < NUM_P; ++s) acc[s] = 0.0;
+  SplitAcc<NUM_P, LPR> acc;
+  acc.zero();
   const RowChunk ch = row_chunk(C.n);
   for (long base = ch.lo; base < ch.hi; base += RPB) {
     const long i = base + slot;
@@ -278,7 +273,7 @@ k_edges_p3(Cost<typename Acc<T>::type> C, EdgeAdj A, int r, const T* __restrict_
 #pragma unroll
     for (int v = 0; v < VEC; ++v) gq += gi[v] * q[v];
     gq = group_sum<LPR>(gq);
-    if (lane == 0) acc[P_C2] += (double)gq;
+    acc.add(lane, P_C2, (double)gq);
     const int k0 = A.urp[i], k1 = A.urp[i + 1];
     for (int k = k0; k < k1; ++k) {
       const int j = A.uci[k];
@@ -293,20 +288,18 @@ k_edges_p3(Cost<typename Acc<T>::type> C, EdgeAdj A, int r, const T* __restrict_
       }
       a1 = group_sum<LPR>(a1);
       a2 = group_sum<LPR>(a2);
-      if (lane == 0) {
-        const double ye = y[1 + k], e = Av[1 + k] - b[1 + k];
-        const double d1 = a1, d2 = a2;
-        acc[P_YA1] += ye * d1;
-        acc[P_YA2] += ye * d2;
-        acc[P_EA1] += e * d1;
-        acc[P_EA2] += e * d2;
-        acc[P_A1A1] += d1 * d1;
-        acc[P_A1A2] += d1 * d2;
-        acc[P_A2A2] += d2 * d2;
-      }
+      const double ye = y[1 + k], e = Av[1 + k] - b[1 + k];
+      const double d1 = a1, d2 = a2;
+      acc.add(lane, P_YA1, ye * d1);
+      acc.add(lane, P_YA2, ye * d2);
+      acc.add(lane, P_EA1, e * d1);
+      acc.add(lane, P_EA2, e * d2);
+      acc.add(lane, P_A1A1, d1 * d1);
+      acc.add(lane, P_A1A2, d1 * d2);
+      acc.add(lane, P_A2A2, d2 * d2);
     }
   }
-  block_sum_store<NUM_P>(acc, part + (long)blockIdx.x * kEdgePS);
+  acc.block_store(lane, part + (long)blockIdx.x * kEdgePS);
 }
 
 // Finalize of pass 3: add the trace row and the -jJ terms, then the step.

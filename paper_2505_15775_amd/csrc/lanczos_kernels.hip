@@ -53,22 +53,28 @@ k_dots(long n, int ncol, const double* __restrict__ Q, long ldq, const double* _
   const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
   for (int c = wave; c < ncol; c += kBlock / kWave) {
     const double* q = Q + (long)c * ldq;
-    double a = 0.0;
-    for (long i = ch.lo + lane; i < ch.hi; i += kWave) a += q[i] * w[i];
-    a = wave_sum(a);
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    long i = ch.lo + lane;
+    for (; i + 3 * kWave < ch.hi; i += 4 * kWave) {
+      a0 += q[i] * w[i];
+      a1 += q[i + kWave] * w[i + kWave];
+      a2 += q[i + 2 * kWave] * w[i + 2 * kWave];
+      a3 += q[i + 3 * kWave] * w[i + 3 * kWave];
+    }
+    for (; i < ch.hi; i += kWave) a0 += q[i] * w[i];
+    double a = wave_sum((a0 + a1) + (a2 + a3));
     if (lane == 0) part[(long)blockIdx.x * pstride + c] = a;
   }
 }
 
-// h[c] = sum of partials over blocks (in block order); optionally accumulates
-// into alpha (alpha[j] += h[j]) for the Lanczos diagonal.
+// h[c] = sum of the block partials of column c (one block per column, fixed order).
 __global__ void __launch_bounds__(kBlock)
 k_fin_dots(const double* __restrict__ part, int nb, int pstride, int ncol, double* __restrict__ h) {
-  for (int c = threadIdx.x; c < ncol; c += kBlock) {
-    double a = 0.0;
-    for (int b = 0; b < nb; ++b) a += part[(long)b * pstride + c];
-    h[c] = a;
-  }
+  const int c = blockIdx.x;
+  if (c >= ncol) return;
+  double acc[1] = {0.0};
+  for (int b = threadIdx.x; b < nb; b += kBlock) acc[0] += part[(long)b * pstride + c];
+  block_sum_store<1>(acc, h + c);
 }
 
 // w_i -= sum_c Q[c][i] h[c]; partial ||w||^2 per block.
@@ -220,7 +226,7 @@ void launch_slack_mv(const Cost<double>& C, int cons_kind, const EdgeAdj& A, con
 void launch_dots(long n, int ncol, const double* Q, long ldq, const double* w, double* part, int pstride, int nb,
                  double* h, hipStream_t st) {
   hipLaunchKernelGGL(k_dots, dim3(nb), dim3(kBlock), 0, st, n, ncol, Q, ldq, w, part, pstride);
-  hipLaunchKernelGGL(k_fin_dots, dim3(1), dim3(kBlock), 0, st, part, nb, pstride, ncol, h);
+  hipLaunchKernelGGL(k_fin_dots, dim3(ncol), dim3(kBlock), 0, st, part, nb, pstride, ncol, h);
 }
 void launch_sub(long n, int ncol, const double* Q, long ldq, const double* h, double* w, double* part, int nb,
                 hipStream_t st) {

@@ -8,7 +8,14 @@ namespace almbm {
 template <typename T>
 void launch_objgrad_diag(const Cost<typename Acc<T>::type>& C, int r, int variant, const T* R, const double* y,
                          const double* b, double sigma, T* G, double* Av, double* part, const DevScalars* sc,
-                         int nblk, hipStream_t st);
+                         int refresh_every, int nblk, hipStream_t st);
+template <typename T>
+void launch_quadq_diag(const Cost<typename Acc<T>::type>& C, int r, int variant, const T* G,
+                       typename Acc<T>::type* Q, double* part, const DevScalars* sc, int nblk, hipStream_t st);
+template <typename T>
+void launch_upd_eval_diag(long n, int r, int variant, T* R, T* G, const typename Acc<T>::type* Q, const double* y,
+                          const double* b, double sigma, double* Av, double* part, const DevScalars* sc,
+                          int refresh_every, int nblk, hipStream_t st);
 template <typename T>
 void launch_quad_diag(const Cost<typename Acc<T>::type>& C, int r, int variant, const T* G, double* part,
                       const DevScalars* sc, int nblk, hipStream_t st);

@@ -5,15 +5,20 @@
 
 namespace almbm {
 
+constexpr int kUnroll = 4;  // neighbour rows gathered together per step
+
 // p = d_i x_i + sum_k S_ik x_{col k} for the row group's slice of columns;
-// X rows have stride r.  Two neighbours per step so that both row gathers are
-// in flight together.
+// X rows have stride r.  The neighbour loop issues kUnroll row gathers before
+// consuming any of them and fetches the next indices while they are in flight,
+// so that each wave keeps several independent HBM/Infinity-Cache requests
+// outstanding (the kernel is bound by gather latency, not by arithmetic).
 template <typename T, int LPR, int VEC, bool FULL>
 __device__ __forceinline__ void spmm_row(const Cost<typename Acc<T>::type>& C, long i, int lane, int r,
                                          const T* __restrict__ X,
                                          const typename Acc<T>::type (&xi)[VEC],
                                          typename Acc<T>::type (&p)[VEC]) {
   using V = typename Acc<T>::type;
+  constexpr int U = kUnroll;
   const V di = C.dg ? C.dg[i] : V(0);
 #pragma unroll
   for (int v = 0; v < VEC; ++v) p[v] = di * xi[v];
@@ -25,27 +30,73 @@ __device__ __forceinline__ void spmm_row(const Cost<typename Acc<T>::type>& C, l
     k0 = C.rp[i];
     k1 = C.rp[i + 1];
   } else {
-    k0 = k1 = 0;
+    return;
   }
-  long k = k0;
-  // two neighbours per step: both gathers are issued before either is used
-  for (; k + 1 < k1; k += 2) {
-    const int j0 = C.ci[k], j1 = C.ci[k + 1];
-    const V c0 = C.cv[k], c1 = C.cv[k + 1];
-    V x0[VEC], x1[VEC];
-    load_frag<T, VEC, FULL>(X + (long)j0 * r, lane, r, x0);
-    load_frag<T, VEC, FULL>(X + (long)j1 * r, lane, r, x1);
+  if (k0 >= k1) return;
+  // indices and values of the first chunk; entries past the row end point at
+  // row i itself with weight 0 (in bounds, no branch in the gather)
+  int j[U];
+  V c[U];
 #pragma unroll
-    for (int v = 0; v < VEC; ++v) p[v] += c0 * x0[v] + c1 * x1[v];
+  for (int u = 0; u < U; ++u) {
+    const long k = k0 + u;
+    j[u] = (k < k1) ? C.ci[k] : (int)i;
+    c[u] = (k < k1) ? C.cv[k] : V(0);
   }
-  if (k < k1) {
-    const int j0 = C.ci[k];
-    const V c0 = C.cv[k];
-    V x0[VEC];
-    load_frag<T, VEC, FULL>(X + (long)j0 * r, lane, r, x0);
+  for (long k = k0; k < k1; k += U) {
+    V x[U][VEC];
 #pragma unroll
-    for (int v = 0; v < VEC; ++v) p[v] += c0 * x0[v];
+    for (int u = 0; u < U; ++u) load_frag<T, VEC, FULL>(X + (long)j[u] * r, lane, r, x[u]);
+    V cc[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) cc[u] = c[u];
+    // next chunk's indices while the gathers are outstanding
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const long kn = k + U + u;
+      j[u] = (kn < k1) ? C.ci[kn] : (int)i;
+      c[u] = (kn < k1) ? C.cv[kn] : V(0);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) p[v] += cc[u] * x[u][v];
   }
 }
+
+// Row-partial accumulators spread over the LPR lanes of a row group: lane l
+// keeps the slots s with s % LPR == l, so each lane holds ceil(NS/LPR) doubles
+// instead of NS.  add() takes a value every lane of the group agrees on.
+template <int NS, int LPR>
+struct SplitAcc {
+  static constexpr int K = (NS + LPR - 1) / LPR;
+  double a[K];
+  __device__ __forceinline__ void zero() {
+#pragma unroll
+    for (int q = 0; q < K; ++q) a[q] = 0.0;
+  }
+  __device__ __forceinline__ void add(int lane, int s, double v) {
+    if (LPR == 1) {
+      a[s] += v;
+    } else {
+      a[s / LPR] += (lane == s % LPR) ? v : 0.0;
+    }
+  }
+  // Deterministic block total of every slot into out[0..NS): per-thread slots
+  // to LDS, then slot s summed over threads t = s % LPR, s % LPR + LPR, ... in order.
+  __device__ __forceinline__ void block_store(int lane, double* __restrict__ out) {
+    __shared__ double buf[kBlock][K];
+#pragma unroll
+    for (int q = 0; q < K; ++q) buf[threadIdx.x][q] = a[q];
+    __syncthreads();
+    if (threadIdx.x < NS) {
+      const int s = threadIdx.x;
+      const int l = s % LPR, q = s / LPR;
+      double t = 0.0;
+      for (int th = l; th < kBlock; th += LPR) t += buf[th][q];
+      out[s] = t;
+    }
+  }
+};
 
 }  // namespace almbm

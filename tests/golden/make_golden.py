@@ -1,7 +1,7 @@
 """Writes the stored expected values under tests/golden/ by calling only the
 FP64 oracle (oracle/) on seeded generator inputs (gen/).
 
-c1_maxcut_er2000.json: ALM-BM solve of the MaxCut SDP (Sec. 6.1 form, C = -L/4,
+maxcut_er2000_solve.json: ALM-BM solve of the MaxCut SDP (Sec. 6.1 form, C = -L/4,
 X_ii = 1) on the Erdos-Renyi graph n = 2000, M = 10000 (average degree 10),
 unit weights, seed 1; starting factor rank 8 (gen.init_factor seed 1), y0 = 0,
 sigma = 1, exact line search, p = 1 rank adaptation, stop at relative KKT 1e-6
@@ -19,7 +19,7 @@ import gen  # noqa: E402
 import oracle  # noqa: E402
 
 
-def c1():
+def maxcut_er2000():
     g = gen.er_graph(2000, 10000, 1, "unit")
     p = oracle.maxcut_sdp(g)
     R0 = gen.init_factor(2000, 8, 1)
@@ -34,7 +34,7 @@ def c1():
 
 
 if __name__ == "__main__":
-    res = c1()
-    with open(os.path.join(HERE, "c1_maxcut_er2000.json"), "w") as fh:
+    res = maxcut_er2000()
+    with open(os.path.join(HERE, "maxcut_er2000_solve.json"), "w") as fh:
         json.dump(res, fh, indent=1)
     print(res)

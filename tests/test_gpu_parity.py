@@ -231,3 +231,64 @@ def test_precision_modes_error_vs_f64_oracle(prec, bound, name, r):
     ea = rel(Av.cpu(), a_o)
     print(f"precision {prec} {name}: rel err f {ef:.2e} G {eg:.2e} A(RR^T) {ea:.2e}")
     assert ef <= bound and eg <= 5 * bound and ea <= bound
+
+
+# ----------------------------------------------------------------- inner loop
+
+
+@pytest.mark.parametrize("name,r,refresh", [("er2000", 8, 0), ("er3001g", 16, 1), ("torus", 7, 5)])
+def test_inner_solve_matches_oracle_gradient_descent(name, r, refresh):
+    """30 steps of the graph-captured inner loop (carried cost product, refresh
+    schedule) against 30 steps of the oracle's gradient descent with exact line
+    search from the same start: same iterate up to rounding."""
+    g = _case_graph(name)
+    prob = almbm().Problem.maxcut(g.n, g.ei, g.ej, g.w, precision="f64", r_max=32, lanczos_kmax=0, device=DEV)
+    po = oracle.maxcut_sdp(g)
+    rng = np.random.default_rng(3)
+    R0 = gen.init_factor(g.n, r, 6)
+    y = -0.5 + 0.2 * rng.standard_normal(g.n)
+    Rt = prob.factor(R0)
+    done, flag, f_last = prob.inner_solve(Rt, torch.from_numpy(y).to(DEV), 0.0, 30, sigma=1.0,
+                                          refresh_every=refresh, graph_unroll=8)
+    assert done == 30 and flag == 2
+    Ro, info = oracle.inner_gd(po, R0, y, 1.0, 0.0, 30)
+    Rg = Rt.cpu().numpy()
+    print(f"inner {name} r={r} refresh={refresh}: rel diff R {rel(Rg, Ro):.2e}")
+    assert rel(Rg, Ro) <= 1e-9
+    assert abs(f_last - oracle.objective(po, Ro, y, 1.0)) <= 1e-9 * abs(f_last)
+
+
+def test_inner_solve_stops_at_tolerance_like_oracle():
+    g = _case_graph("er2000")
+    prob = almbm().Problem.maxcut(g.n, g.ei, g.ej, g.w, precision="f64", r_max=32, lanczos_kmax=0, device=DEV)
+    po = oracle.maxcut_sdp(g)
+    R0 = gen.init_factor(g.n, 8, 2)
+    y = np.full(g.n, -1.5)
+    for tol, max_steps in [(1e-2, 500), (3e-3, 400)]:
+        Rt = prob.factor(R0)
+        done, flag, _ = prob.inner_solve(Rt, torch.from_numpy(y).to(DEV), tol, max_steps, sigma=1.0)
+        Ro, info = oracle.inner_gd(po, R0, y, 1.0, tol, max_steps)
+        print(f"tol {tol}: gpu steps {done} flag {flag}; oracle steps {info['iters']} converged {info['converged']}")
+        assert (flag == 1) == info["converged"] and done == info["iters"]
+        assert rel(Rt.cpu().numpy(), Ro) <= 1e-8
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
+def test_tile_variants_and_grids_agree(prec):
+    g = _case_graph("er3001g")
+    prob = almbm().Problem.maxcut(g.n, g.ei, g.ej, g.w, precision=prec, r_max=16, lanczos_kmax=0, device=DEV)
+    R = prob.factor(gen.init_factor(g.n, 16, 1))
+    y = torch.full((g.n,), -0.7, dtype=torch.float64, device=DEV)
+    ref = None
+    for v in (0, 1, 2):
+        for nb in (8, 64, 384):
+            prob.set_tiles(v, nb)
+            f, G, Av = prob.objective_grad(R, y, 1.0)
+            out = (f.item(), G.double().cpu().numpy(), Av.cpu().numpy())
+            if ref is None:
+                ref = out
+            tol = 1e-13 if prec == "f64" else 1e-5
+            assert abs(out[0] - ref[0]) <= tol * abs(ref[0])
+            assert rel(out[1], ref[1]) <= (tol if prec != "bf16" else 1e-2)
+    v, nb = prob.autotune(16, reps=2)
+    assert 0 <= v <= 2 and nb % 8 == 0

@@ -67,7 +67,7 @@ def test_solve_er2000_matches_stored_oracle_solve():
     """The n = 2000 ER workload (unit weights, r0 = 8, sigma = 1, eps = 1e-6)
     against the oracle's own solve (tests/golden/make_golden.py), and the KKT
     measure re-evaluated by the oracle (exact lambda_min) at the GPU's (R, y)."""
-    gold = json.load(open(os.path.join(GOLDEN, "c1_maxcut_er2000.json")))
+    gold = json.load(open(os.path.join(GOLDEN, "maxcut_er2000_solve.json")))
     g = gen.er_graph(2000, 10000, 1, "unit")
     prob = _maxcut(g, r_max=64, kmax=100)
     st, res, R, y = prob.solve(gen.init_factor(2000, 8, 1), eps_kkt=1e-6, sigma=1.0)
@@ -123,7 +123,7 @@ def test_solve_gpu_matches_oracle_trajectory_short():
 @pytest.mark.parametrize("prec", ["f32", "bf16"])
 def test_solve_mixed_precision_reports_error(prec):
     g = gen.er_graph(2000, 10000, 1, "unit")
-    gold = json.load(open(os.path.join(GOLDEN, "c1_maxcut_er2000.json")))
+    gold = json.load(open(os.path.join(GOLDEN, "maxcut_er2000_solve.json")))
     prob = _maxcut(g, prec=prec, r_max=64, kmax=100)
     st, res, R, y = prob.solve(gen.init_factor(2000, 8, 1), eps_kkt=1e-4, sigma=1.0)
     err = abs(res["pobj"] - gold["pobj"]) / abs(gold["pobj"])

@@ -107,3 +107,9 @@ def test_create_rejects_bad_arguments_before_any_launch():
     assert st == -1 and b"b is null" in _lib.lib.alm_bm_last_error()
     st = _lib.lib.alm_bm_objective_grad(None, 4, None, None, 1.0, None, None, None, None)
     assert st == -1
+
+
+def test_set_tiles_rejects_bad_values_without_device():
+    from paper_2505_15775_amd import _lib
+
+    assert _lib.lib.alm_bm_set_tiles(None, 0, 0) == -1

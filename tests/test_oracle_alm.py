@@ -172,7 +172,7 @@ def test_alm_proximity_and_nonexpansiveness_on_even_cycle():
 
 
 def test_rank_expansion_step_is_exact_minimiser():
-    """p = 1 case of Alg. 1 line 7: L(X + s v v^T) = L(X) + s theta + (sigma/2) s^2 ||A(vv^T)||^2,
+    """p = 1 case of the small SDP of Alg. 1: L(X + s v v^T) = L(X) + s theta + (sigma/2) s^2 ||A(vv^T)||^2,
     minimised over s >= 0 at s* = max(0, -theta / (sigma ||A(vv^T)||^2))."""
     g = gen.er_graph(30, 80, 6, "gauss")
     p = oracle.maxcut_sdp(g)
