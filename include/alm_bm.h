@@ -244,6 +244,50 @@ alm_bm_status alm_bm_autotune(alm_bm_problem* prob, int32_t r, int32_t reps, int
 alm_bm_status alm_bm_kkt(alm_bm_problem* prob, int32_t r, const void* R, const double* y,
                          double lam_min, double* kkt_out, hipStream_t stream);
 
+/* ---- learned warm start (MaxCut-type problems, DIAG family) -----------------
+ * A per-vertex model proposes the initial dual y0 and a pooled-feature ridge
+ * model the initial rank r0 (Alg. 1 starts from y = 0; the warm start is an
+ * addition).  Features of vertex i, from the cost C = S + Diag(d):
+ *   0 log(1 + deg_i)   1 sum_j |S_ij|   2 sum_j S_ij   3 d_i
+ *   4 d_i - sum_j |S_ij| (Gershgorin bound of a dual-feasible y_i)
+ *   5 mean and 6 max of log(1 + deg_j) over the neighbours j, 7 mean of their
+ *   feature 1.
+ * MLP: n_in -> h -> h -> 1, ReLU, FP32, inputs standardised inside the
+ * kernels as (x - mu) * inv_sd; parameters flattened as W1[n_in][h], b1[h],
+ * W2[h][h], b2[h], W3[h], b3 (alm_bm_ws_param_count floats).  h in {16,32,64},
+ * n_in <= 8.                                                                    */
+#define ALM_BM_WS_NFEAT 8
+/* feats: device n x 8 float (row-major); scratch: device n floats.  Handle must
+ * be DIAG family.                                                               */
+alm_bm_status alm_bm_ws_features(alm_bm_problem* prob, float* feats, float* scratch, hipStream_t stream);
+/* out[k] = mean over rows of feats[:, k] (device 8 doubles); n rows; work:
+ * device 512 doubles.                                                           */
+alm_bm_status alm_bm_ws_pool(const float* feats, int64_t n, double* out, double* work, hipStream_t stream);
+int64_t alm_bm_ws_param_count(int32_t n_in, int32_t h);
+/* Floats of workspace alm_bm_ws_loss_grad needs for `nblocks` blocks.          */
+int64_t alm_bm_ws_work_size(int32_t n_in, int32_t h, int32_t nblocks);
+/* out (device n doubles) = MLP(X) for X device n x n_in float.                 */
+alm_bm_status alm_bm_ws_forward(const float* params, int32_t n_in, int32_t h, const float* mu,
+                                const float* inv_sd, int64_t n, const float* X, double* out,
+                                hipStream_t stream);
+/* Mean squared error (1/n) sum (MLP(x_v) - t_v)^2 into *loss (device double)
+ * and its gradient into grad (device, param_count floats), deterministic for a
+ * fixed nblocks (1..4096).  work: device, alm_bm_ws_work_size floats.          */
+alm_bm_status alm_bm_ws_loss_grad(const float* params, int32_t n_in, int32_t h, const float* mu,
+                                  const float* inv_sd, int64_t n, const float* X, const float* target,
+                                  float* grad, double* loss, float* work, int32_t nblocks,
+                                  hipStream_t stream);
+/* Adam (Kingma & Ba 2015) on count parameters, bias corrections for `step` >= 1.
+ * params, grad, m, v: device floats.                                             */
+alm_bm_status alm_bm_ws_adam(float* params, const float* grad, float* m, float* v, int32_t count,
+                             float lr, float beta1, float beta2, float eps, int32_t step,
+                             hipStream_t stream);
+/* Ridge regression on the host: coef (p+1 doubles, last = intercept) minimising
+ * sum_k (x_k . coef[0:p] + coef[p] - t_k)^2 + lambda ||coef[0:p]||^2 for the
+ * rows x_k of X (host k x p, row-major), by the normal equations.              */
+alm_bm_status alm_bm_ws_ridge_fit(const double* X, const double* t, int32_t k, int32_t p, double lambda,
+                                  double* coef);
+
 void alm_bm_default_options(alm_bm_options* opts);
 const char* alm_bm_last_error(void);
 

@@ -44,3 +44,4 @@ from .alm import (  # noqa: F401
     solve,
 )
 from .dense_alm import dense_alm  # noqa: F401
+from . import warmstart  # noqa: F401

@@ -106,7 +106,8 @@ EXPORTS = [
     "alm_bm_create", "alm_bm_destroy", "alm_bm_objective_grad", "alm_bm_line_search", "alm_bm_dual_update",
     "alm_bm_lanczos_min_eig", "alm_bm_solve", "alm_bm_kkt", "alm_bm_default_options", "alm_bm_last_error",
     "alm_bm_maxcut_cost_host", "alm_bm_abi_sizes", "alm_bm_gd_step", "alm_bm_set_tiles", "alm_bm_autotune",
-    "alm_bm_inner_solve",
+    "alm_bm_inner_solve", "alm_bm_ws_features", "alm_bm_ws_pool", "alm_bm_ws_param_count", "alm_bm_ws_work_size",
+    "alm_bm_ws_forward", "alm_bm_ws_loss_grad", "alm_bm_ws_adam", "alm_bm_ws_ridge_fit",
 ]
 
 vp = C.c_void_p
@@ -135,6 +136,14 @@ def _load():
         "alm_bm_maxcut_cost_host": (i32, [i64, i64, vp, vp, vp, vp, vp, vp, vp, C.POINTER(i64)]),
         "alm_bm_abi_sizes": (None, [C.POINTER(i64)]),
         "alm_bm_set_tiles": (i32, [vp, i32, i32]),
+        "alm_bm_ws_features": (i32, [vp, vp, vp, vp]),
+        "alm_bm_ws_pool": (i32, [vp, i64, vp, vp, vp]),
+        "alm_bm_ws_param_count": (i64, [i32, i32]),
+        "alm_bm_ws_work_size": (i64, [i32, i32, i32]),
+        "alm_bm_ws_forward": (i32, [vp, i32, i32, vp, vp, i64, vp, vp, vp]),
+        "alm_bm_ws_loss_grad": (i32, [vp, i32, i32, vp, vp, i64, vp, vp, vp, vp, vp, i32, vp]),
+        "alm_bm_ws_adam": (i32, [vp, vp, vp, vp, i32, C.c_float, C.c_float, C.c_float, C.c_float, i32, vp]),
+        "alm_bm_ws_ridge_fit": (i32, [vp, vp, i32, i32, f64, vp]),
         "alm_bm_inner_solve": (i32, [vp, C.POINTER(Options), i32, vp, vp, f64, i32, C.POINTER(i32), C.POINTER(i32),
                                      C.POINTER(f64), vp]),
         "alm_bm_autotune": (i32, [vp, i32, i32, C.POINTER(i32), C.POINTER(i32), vp]),

@@ -606,6 +606,110 @@ extern "C" alm_bm_status alm_bm_dual_update(alm_bm_problem* p, const double* Av,
   return ALM_BM_OK;
 }
 
+// --------------------------------------------------------------------- warm start
+
+extern "C" alm_bm_status alm_bm_ws_features(alm_bm_problem* p, float* feats, float* scratch, hipStream_t st) {
+  if (!p || !feats || !scratch) return fail(ALM_BM_ERR_INVALID_ARG, "ws_features: null argument");
+  if (p->d.cons_kind != ALM_BM_CONS_DIAG) return fail(ALM_BM_ERR_UNSUPPORTED, "ws_features: DIAG family only");
+  launch_ws_features(p->C64, feats, scratch, st);
+  HIPCHK(hipGetLastError());
+  return ALM_BM_OK;
+}
+
+extern "C" alm_bm_status alm_bm_ws_pool(const float* feats, int64_t n, double* out, double* work, hipStream_t st) {
+  if (!feats || !out || !work || n < 1) return fail(ALM_BM_ERR_INVALID_ARG, "ws_pool: bad argument");
+  launch_ws_pool(feats, n, work, 64, out, st);  // 64 blocks x 8 partials
+  HIPCHK(hipGetLastError());
+  return ALM_BM_OK;
+}
+
+extern "C" int64_t alm_bm_ws_param_count(int32_t n_in, int32_t h) { return ws_param_count(n_in, h); }
+
+extern "C" int64_t alm_bm_ws_work_size(int32_t n_in, int32_t h, int32_t nblocks) {
+  // per-block gradient partials, then per-block losses as doubles (2 floats each)
+  return (int64_t)nblocks * ws_param_count(n_in, h) + 2 * (int64_t)nblocks + 2;
+}
+
+static bool ws_shape_ok(int32_t n_in, int32_t h) {
+  return n_in >= 1 && n_in <= ALM_BM_WS_NFEAT && (h == 16 || h == 32 || h == 64);
+}
+
+extern "C" alm_bm_status alm_bm_ws_forward(const float* params, int32_t n_in, int32_t h, const float* mu,
+                                           const float* inv_sd, int64_t n, const float* X, double* out,
+                                           hipStream_t st) {
+  if (!params || !mu || !inv_sd || !X || !out || n < 0) return fail(ALM_BM_ERR_INVALID_ARG, "ws_forward: bad argument");
+  if (!ws_shape_ok(n_in, h)) return fail(ALM_BM_ERR_INVALID_ARG, "ws_forward: n_in <= 8 and h in {16,32,64}");
+  if (n == 0) return ALM_BM_OK;
+  launch_ws_forward(params, n_in, h, mu, inv_sd, n, X, out, st);
+  HIPCHK(hipGetLastError());
+  return ALM_BM_OK;
+}
+
+extern "C" alm_bm_status alm_bm_ws_loss_grad(const float* params, int32_t n_in, int32_t h, const float* mu,
+                                             const float* inv_sd, int64_t n, const float* X, const float* target,
+                                             float* grad, double* loss, float* work, int32_t nblocks,
+                                             hipStream_t st) {
+  if (!params || !mu || !inv_sd || !X || !target || !grad || !work || n < 1)
+    return fail(ALM_BM_ERR_INVALID_ARG, "ws_loss_grad: bad argument");
+  if (!ws_shape_ok(n_in, h)) return fail(ALM_BM_ERR_INVALID_ARG, "ws_loss_grad: n_in <= 8 and h in {16,32,64}");
+  if (nblocks < 1 || nblocks > 4096) return fail(ALM_BM_ERR_INVALID_ARG, "ws_loss_grad: nblocks in 1..4096");
+  const int np = ws_param_count(n_in, h);
+  float* gpart = work;
+  // doubles after the float partials, 8-byte aligned
+  size_t off = (size_t)nblocks * np;
+  off = (off + 1) & ~(size_t)1;
+  double* lpart = reinterpret_cast<double*>(work + off);
+  launch_ws_backward(params, n_in, h, mu, inv_sd, n, X, target, gpart, lpart, nblocks, grad, loss, st);
+  HIPCHK(hipGetLastError());
+  return ALM_BM_OK;
+}
+
+extern "C" alm_bm_status alm_bm_ws_adam(float* params, const float* grad, float* m, float* v, int32_t count, float lr,
+                                        float beta1, float beta2, float eps, int32_t step, hipStream_t st) {
+  if (!params || !grad || !m || !v || count < 1 || step < 1) return fail(ALM_BM_ERR_INVALID_ARG, "ws_adam: bad argument");
+  launch_ws_adam(params, grad, m, v, count, lr, beta1, beta2, eps, step, st);
+  HIPCHK(hipGetLastError());
+  return ALM_BM_OK;
+}
+
+extern "C" alm_bm_status alm_bm_ws_ridge_fit(const double* X, const double* t, int32_t k, int32_t p, double lambda,
+                                             double* coef) {
+  if (!X || !t || !coef || k < 1 || p < 0 || p > 64 || lambda < 0.0)
+    return fail(ALM_BM_ERR_INVALID_ARG, "ws_ridge_fit: bad argument");
+  const int q = p + 1;  // with intercept (not penalised)
+  std::vector<double> A(q * q, 0.0), rhs(q, 0.0);
+  for (int r = 0; r < k; ++r) {
+    for (int i = 0; i < q; ++i) {
+      const double xi = i < p ? X[(long)r * p + i] : 1.0;
+      rhs[i] += xi * t[r];
+      for (int j = 0; j < q; ++j) A[i * q + j] += xi * (j < p ? X[(long)r * p + j] : 1.0);
+    }
+  }
+  for (int i = 0; i < p; ++i) A[i * q + i] += lambda;
+  // Gaussian elimination with partial pivoting
+  for (int c = 0; c < q; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < q; ++r)
+      if (std::fabs(A[r * q + c]) > std::fabs(A[piv * q + c])) piv = r;
+    if (std::fabs(A[piv * q + c]) < 1e-300) return fail(ALM_BM_ERR_NUMERIC, "ws_ridge_fit: singular system");
+    if (piv != c) {
+      for (int j = 0; j < q; ++j) std::swap(A[c * q + j], A[piv * q + j]);
+      std::swap(rhs[c], rhs[piv]);
+    }
+    for (int r = c + 1; r < q; ++r) {
+      const double f = A[r * q + c] / A[c * q + c];
+      for (int j = c; j < q; ++j) A[r * q + j] -= f * A[c * q + j];
+      rhs[r] -= f * rhs[c];
+    }
+  }
+  for (int c = q - 1; c >= 0; --c) {
+    double s = rhs[c];
+    for (int j = c + 1; j < q; ++j) s -= A[c * q + j] * coef[j];
+    coef[c] = s / A[c * q + c];
+  }
+  return ALM_BM_OK;
+}
+
 // --------------------------------------------------------------------- tiling
 
 extern "C" alm_bm_status alm_bm_set_tiles(alm_bm_problem* p, int32_t variant, int32_t row_blocks_) {

@@ -79,4 +79,15 @@ void launch_resid(long n, const double* z, const double* v, double theta, double
 void launch_quartic_norm(long n, int cons_kind, const EdgeAdj& A, const double* x, double* part, int nb,
                          hipStream_t st);
 
+void launch_ws_features(const Cost<double>& C, float* F, float* ldeg, hipStream_t st);
+int ws_param_count(int nin, int h);
+bool launch_ws_forward(const float* P, int nin, int h, const float* mu, const float* isd, long n, const float* X,
+                       double* out, hipStream_t st);
+void launch_ws_pool(const float* F, long n, double* part, int nb, double* out, hipStream_t st);
+bool launch_ws_backward(const float* P, int nin, int h, const float* mu, const float* isd, long n, const float* X,
+                        const float* T, float* gpart, double* lpart, int nb, float* grad, double* loss,
+                        hipStream_t st);
+void launch_ws_adam(float* P, const float* g, float* m, float* v, int np, float lr, float b1, float b2, float eps,
+                    int step, hipStream_t st);
+
 }  // namespace almbm
