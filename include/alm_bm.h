@@ -134,6 +134,8 @@ typedef struct {
   int32_t refresh_every;     /* 0 -> 32 (F64), 16 (F32), 4 (BF16): inner steps between
                                 full sparse evaluations of C R; in between, C R is
                                 carried as C R - t C G (1 = always recompute)      */
+  int32_t lanczos_restarts;  /* 3      restarts from the Ritz vector while the Ritz
+                                residual exceeds its tolerance                    */
 } alm_bm_options;
 
 typedef struct {
@@ -196,9 +198,12 @@ alm_bm_status alm_bm_dual_update(alm_bm_problem* prob, const double* Av, double 
 /* Smallest eigenvalue of the dual slack Z(y) = C - A*(y) (Sec. 1.2) by Lanczos
  * with full FP64 reorthogonalisation (two classical Gram-Schmidt passes),
  * start vector drawn from `seed` by a counter-based generator.  Stops when the
- * Ritz residual ||Z v - theta v|| <= tol or after max_iter (<= lanczos_kmax) steps.
- * theta, resid: device 1 double each; iters: device 1 int32 (all nullable except
- * theta); v: device n doubles, unit Ritz vector (nullable).  Synchronises stream.
+ * Ritz residual ||Z v - theta v|| <= tol or after max_iter (<= lanczos_kmax)
+ * steps; then restarts from the Ritz vector (up to 3 times) while the residual
+ * exceeds tol.
+ * theta, resid: device 1 double each; iters: device 1 int32, Lanczos steps summed
+ * over restarts (all nullable except theta); v: device n doubles, unit Ritz
+ * vector (nullable).  Synchronises stream.
  * theta is a Ritz value, hence an upper bound on lambda_min.                    */
 alm_bm_status alm_bm_lanczos_min_eig(alm_bm_problem* prob, const double* y, int32_t max_iter,
                                      double tol, uint64_t seed, double* theta, double* v,
@@ -237,6 +242,33 @@ alm_bm_status alm_bm_set_tiles(alm_bm_problem* prob, int32_t variant, int32_t ro
  * handle's workspace as input (values do not affect the timing).              */
 alm_bm_status alm_bm_autotune(alm_bm_problem* prob, int32_t r, int32_t reps, int32_t* variant,
                               int32_t* row_blocks, hipStream_t stream);
+
+/* ---- batched solves ----------------------------------------------------------
+ * Many independent problems (DIAG family, one storage precision) solved
+ * together: the instances are concatenated block-diagonally on the device and
+ * every kernel launch of the method covers all of them (per-instance step
+ * sizes, tolerances, stop flags, duals, Lanczos recurrences and ranks; the
+ * inner loop of all instances is one captured HIP graph per chunk of steps).
+ * Factors share one row width, rank_stride: instance q's rows sit at rows
+ * [off_q, off_q + n_q) of one (sum n) x rank_stride array, its first r_q columns
+ * used and the rest zero (zero columns stay exactly zero under the gradient
+ * step, so the padded problem is the rank-r_q problem).  Rank expansion fills
+ * the next zero column, up to rank_stride.                                      */
+typedef struct alm_bm_batch alm_bm_batch;
+
+/* descs: host array of count descriptors (device arrays as for alm_bm_create,
+ * copied into the batch, so they may be freed afterwards).  1 <= count <= 4096. */
+alm_bm_status alm_bm_batch_create(int32_t count, const alm_bm_problem_desc* descs, int32_t rank_stride,
+                                  hipStream_t stream, alm_bm_batch** out);
+alm_bm_status alm_bm_batch_destroy(alm_bm_batch* batch);
+/* offsets: host count+1 int64 (row offsets of the instances; offsets[count] = sum n). */
+alm_bm_status alm_bm_batch_offsets(const alm_bm_batch* batch, int64_t* offsets);
+/* R: device (sum n) x rank_stride in the storage precision (in/out); r: host
+ * count ranks (in/out); y: device sum n doubles (in/out); results, status: host
+ * count each (nullable).  opts as for alm_bm_solve (graph_unroll must be >= 1).
+ * Returns ALM_BM_OK when every instance met eps_kkt, else NOT_CONVERGED.        */
+alm_bm_status alm_bm_batch_solve(alm_bm_batch* batch, const alm_bm_options* opts, void* R, int32_t* r,
+                                 double* y, alm_bm_result* results, int32_t* status, hipStream_t stream);
 
 /* Relative KKT measure of Sec. 6 at (RR^T, y) with lambda_min supplied by the
  * caller (host double); kkt_out: host array of 6 doubles

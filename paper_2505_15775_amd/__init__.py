@@ -14,7 +14,7 @@ import torch
 from . import _lib
 from ._lib import AlmBmError, check, default_options, lib  # noqa: F401
 
-__all__ = ["Problem", "AlmBmError", "default_options", "maxcut_cost", "TORCH_DTYPES"]
+__all__ = ["Problem", "Batch", "AlmBmError", "default_options", "maxcut_cost", "TORCH_DTYPES"]
 
 TORCH_DTYPES = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16}
 
@@ -280,3 +280,69 @@ class Problem:
                                     _stream(stream)), "solve")
         R = buf[: self.n * r.value].view(self.n, r.value)
         return st, res.as_dict(), R, y
+
+
+class Batch:
+    """Many MaxCut-type instances solved together (alm_bm_batch_*): one launch
+    per step of the method covers every instance.  `problems` are Problem
+    objects (DIAG family, one precision); their arrays are copied at creation."""
+
+    def __init__(self, problems, rank_stride, stream=None):
+        if not problems:
+            raise ValueError("empty batch")
+        self.precision = problems[0].precision
+        self.dtype = problems[0].dtype
+        self.device = problems[0].device
+        self.count = len(problems)
+        self.rank_stride = int(rank_stride)
+        descs = (_lib.Desc * self.count)(*[p.desc for p in problems])
+        h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            check(lib.alm_bm_batch_create(self.count, descs, self.rank_stride, _stream(stream), C.byref(h)),
+                  "batch_create")
+        self._h = h
+        offs = np.zeros(self.count + 1, dtype=np.int64)
+        check(lib.alm_bm_batch_offsets(self._h, offs.ctypes.data), "batch_offsets")
+        self.offsets = offs
+        self.n_total = int(offs[-1])
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib.alm_bm_batch_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def pack(self, factors):
+        """Device (sum n) x rank_stride factor from per-instance n_q x r_q arrays."""
+        R = torch.zeros((self.n_total, self.rank_stride), dtype=self.dtype, device=self.device)
+        for q, F in enumerate(factors):
+            F = torch.as_tensor(F)
+            R[self.offsets[q]:self.offsets[q + 1], : F.shape[1]] = F.to(device=self.device, dtype=self.dtype)
+        return R
+
+    def solve(self, factors, y0=None, stream=None, **opts):
+        """Returns (status, per-instance status list, results list, R, ranks, y)."""
+        o = default_options()
+        for k, v in opts.items():
+            if not hasattr(o, k):
+                raise KeyError(f"unknown solve option {k!r}")
+            setattr(o, k, v)
+        R = self.pack(factors)
+        r = np.array([int(torch.as_tensor(F).shape[1]) for F in factors], dtype=np.int32)
+        y = (torch.zeros(self.n_total, dtype=torch.float64, device=self.device) if y0 is None
+             else torch.as_tensor(y0).to(device=self.device, dtype=torch.float64).clone().contiguous())
+        res = (_lib.Result * self.count)()
+        sts = np.zeros(self.count, dtype=np.int32)
+        st = check(lib.alm_bm_batch_solve(self._h, C.byref(o), _ptr(R), r.ctypes.data, _ptr(y), res,
+                                          sts.ctypes.data, _stream(stream)), "batch_solve")
+        return st, sts.tolist(), [x.as_dict() for x in res], R, r.tolist(), y
+
+    def instance(self, q, R, y, r):
+        """Instance q's factor (n_q x r_q view) and dual."""
+        a, b = self.offsets[q], self.offsets[q + 1]
+        return R[a:b, :r], y[a:b]

@@ -76,6 +76,7 @@ class Options(C.Structure):
         ("time_limit_s", C.c_double),
         ("bf16_promote", C.c_int32),
         ("refresh_every", C.c_int32),
+        ("lanczos_restarts", C.c_int32),
     ]
 
 
@@ -108,6 +109,7 @@ EXPORTS = [
     "alm_bm_maxcut_cost_host", "alm_bm_abi_sizes", "alm_bm_gd_step", "alm_bm_set_tiles", "alm_bm_autotune",
     "alm_bm_inner_solve", "alm_bm_ws_features", "alm_bm_ws_pool", "alm_bm_ws_param_count", "alm_bm_ws_work_size",
     "alm_bm_ws_forward", "alm_bm_ws_loss_grad", "alm_bm_ws_adam", "alm_bm_ws_ridge_fit",
+    "alm_bm_batch_create", "alm_bm_batch_destroy", "alm_bm_batch_offsets", "alm_bm_batch_solve",
 ]
 
 vp = C.c_void_p
@@ -144,6 +146,10 @@ def _load():
         "alm_bm_ws_loss_grad": (i32, [vp, i32, i32, vp, vp, i64, vp, vp, vp, vp, vp, i32, vp]),
         "alm_bm_ws_adam": (i32, [vp, vp, vp, vp, i32, C.c_float, C.c_float, C.c_float, C.c_float, i32, vp]),
         "alm_bm_ws_ridge_fit": (i32, [vp, vp, i32, i32, f64, vp]),
+        "alm_bm_batch_create": (i32, [i32, vp, i32, vp, C.POINTER(vp)]),
+        "alm_bm_batch_destroy": (i32, [vp]),
+        "alm_bm_batch_offsets": (i32, [vp, vp]),
+        "alm_bm_batch_solve": (i32, [vp, C.POINTER(Options), vp, vp, vp, vp, vp, vp]),
         "alm_bm_inner_solve": (i32, [vp, C.POINTER(Options), i32, vp, vp, f64, i32, C.POINTER(i32), C.POINTER(i32),
                                      C.POINTER(f64), vp]),
         "alm_bm_autotune": (i32, [vp, i32, i32, C.POINTER(i32), C.POINTER(i32), vp]),

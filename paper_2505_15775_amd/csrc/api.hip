@@ -50,6 +50,8 @@ struct alm_bm_problem {
   int nblk = 0;
   int max_blocks = 0;
   int variant = 0;
+  BlockTab tab{};                 // batched super-problem: per-block instance rows
+  int count = 1;                  // instances (DevScalars in sc_solve)
   double* part = nullptr;     // nblk * (NUM_P + kMaxR)
   double* part_c2 = nullptr;  // nblk
   double* part_vec = nullptr; // vec kernels
@@ -240,6 +242,7 @@ extern "C" void alm_bm_default_options(alm_bm_options* o) {
   o->time_limit_s = 0.0;
   o->bf16_promote = 1;
   o->refresh_every = 0;
+  o->lanczos_restarts = 3;
 }
 
 extern "C" const char* alm_bm_last_error(void) { return g_err.c_str(); }
@@ -484,8 +487,9 @@ static void enqueue_objgrad(alm_bm_problem* p, int r, const T* R, const double* 
                             DevScalars* sc, int mode, double* f_out, hipStream_t st) {
   const auto& d = p->d;
   if (d.cons_kind == ALM_BM_CONS_DIAG) {
-    launch_objgrad_diag<T>(cost_of<T>(p), r, p->variant, R, y, d.b, sigma, G, Av, p->part, sc, 0, p->nblk, st);
-    launch_fin_objgrad(p->part, p->nblk, sc, sigma, mode, f_out, st);
+    launch_objgrad_diag<T>(cost_of<T>(p), r, p->variant, R, y, d.b, sigma, G, Av, p->part, sc, 0, p->tab, p->nblk,
+                           st);
+    launch_fin_objgrad(p->part, p->nblk, sc, sigma, mode, f_out, st, p->tab, p->count);
   } else {
     launch_edges_p1<T>(p->adj, d.n, r, p->variant, R, y, d.b, sigma, Av, p->wE, p->part, sc, p->nblk, st);
     launch_fin_edges1(p->part, p->nblk, r, sc, y, d.b, sigma, d.trace_coef, Av, st);
@@ -509,12 +513,13 @@ static void enqueue_inner_step(alm_bm_problem* p, int r, T* R, const double* y, 
   DevScalars* sc = p->sc_solve;
   if (d.cons_kind == ALM_BM_CONS_DIAG) {
     V* Q = static_cast<V*>(p->Qbuf);
-    launch_upd_eval_diag<T>(d.n, r, p->variant, R, G, Q, y, d.b, sigma, p->Av, p->part, sc, refresh, p->nblk, st);
-    launch_objgrad_diag<T>(cost_of<T>(p), r, p->variant, R, y, d.b, sigma, G, p->Av, p->part, sc, refresh, p->nblk,
-                           st);
-    launch_fin_objgrad(p->part, p->nblk, sc, sigma, 1, nullptr, st);
-    launch_quadq_diag<T>(cost_of<T>(p), r, p->variant, G, Q, p->part_c2, sc, p->nblk, st);
-    launch_fin_step(p->part_c2, p->nblk, 1, sc, sigma, 0.0, 1, nullptr, nullptr, st);
+    launch_upd_eval_diag<T>(d.n, r, p->variant, R, G, Q, y, d.b, sigma, p->Av, p->part, sc, refresh, p->tab, p->nblk,
+                            st);
+    launch_objgrad_diag<T>(cost_of<T>(p), r, p->variant, R, y, d.b, sigma, G, p->Av, p->part, sc, refresh, p->tab,
+                           p->nblk, st);
+    launch_fin_objgrad(p->part, p->nblk, sc, sigma, 1, nullptr, st, p->tab, p->count);
+    launch_quadq_diag<T>(cost_of<T>(p), r, p->variant, G, Q, p->part_c2, sc, p->tab, p->nblk, st);
+    launch_fin_step(p->part_c2, p->nblk, 1, sc, sigma, 0.0, 1, nullptr, nullptr, st, p->tab, p->count);
   } else {
     enqueue_objgrad<T>(p, r, R, y, sigma, G, p->Av, sc, 1, nullptr, st);
     launch_edges_p3<T>(cost_of<T>(p), p->adj, r, p->variant, R, G, y, d.b, p->Av, p->part, sc, p->nblk, st);
@@ -884,8 +889,8 @@ struct LanczosOut {
 
 // Lanczos on Z(y) with two classical Gram-Schmidt passes per step; the Ritz
 // vector for the smallest Ritz value goes to v (device, n).
-static alm_bm_status lanczos_run(alm_bm_problem* p, const double* y, int kmax, double tol, uint64_t seed, double* v,
-                                 LanczosOut& out, hipStream_t st) {
+static alm_bm_status lanczos_pass(alm_bm_problem* p, const double* y, int kmax, double tol, uint64_t seed,
+                                  bool restart, double* v, LanczosOut& out, hipStream_t st) {
   const auto& d = p->d;
   const long n = d.n;
   const long ldq = n;
@@ -896,9 +901,16 @@ static alm_bm_status lanczos_run(alm_bm_problem* p, const double* y, int kmax, d
   kmax = (int)std::min<long>(kmax, n);
   double* qsum = (d.j_coef != 0.0) ? &p->sc_api->qsum : nullptr;
   const int cons = d.cons_kind == ALM_BM_CONS_DIAG ? 0 : 1;
-  launch_rand(n, seed, p->lw, p->lpart2, nb, st);
-  launch_fin_sum(p->lpart2, nb, p->lscal, 1, st);
-  launch_scale(n, p->lw, p->lscal, p->Q, p->lpart2, nb, qsum, st);
+  if (restart) {
+    // restart from the previous (unit) Ritz vector in v
+    launch_resid(n, v, v, 0.0, nullptr, p->lpart2, nb, st);
+    launch_fin_sum(p->lpart2, nb, p->lscal, 1, st);
+    launch_scale(n, v, p->lscal, p->Q, p->lpart2, nb, qsum, st);
+  } else {
+    launch_rand(n, seed, p->lw, p->lpart2, nb, st);
+    launch_fin_sum(p->lpart2, nb, p->lscal, 1, st);
+    launch_scale(n, p->lw, p->lscal, p->Q, p->lpart2, nb, qsum, st);
+  }
   std::vector<double> ha(kmax + 1), hb(kmax + 1), z;
   int m = 0;
   double theta = 0.0;
@@ -942,7 +954,7 @@ static alm_bm_status lanczos_run(alm_bm_problem* p, const double* y, int kmax, d
   launch_fin_sum(p->lpart2, nb, p->lscal + 1, 1, st);
   launch_scale(n, v, p->lscal + 1, v, p->lpart2, nb, qsum, st);
   launch_slack_mv(p->C64, cons, p->adj, y, d.trace_coef, d.j_coef, p->sc_api, v, p->lw, st);
-  launch_resid(n, p->lw, v, theta, p->lpart2, nb, st);
+  launch_resid(n, p->lw, v, theta, nullptr, p->lpart2, nb, st);
   launch_fin_sum(p->lpart2, nb, p->lscal + 2, 1, st);
   double hres = 0.0;
   HIPCHK(hipMemcpyAsync(&hres, p->lscal + 2, sizeof(double), hipMemcpyDeviceToHost, st));
@@ -952,6 +964,21 @@ static alm_bm_status lanczos_run(alm_bm_problem* p, const double* y, int kmax, d
   out.resid = hres;
   out.iters = m;
   if (!std::isfinite(theta)) return fail(ALM_BM_ERR_NUMERIC, "lanczos: non-finite Ritz value");
+  return ALM_BM_OK;
+}
+
+// Lanczos with explicit restarts from the Ritz vector while its residual
+// exceeds tol (a pass that stops at kmax without converging overestimates
+// lambda_min; the restarts keep the KKT test and the rank test honest).
+static alm_bm_status lanczos_run(alm_bm_problem* p, const double* y, int kmax, double tol, uint64_t seed, double* v,
+                                 LanczosOut& out, hipStream_t st, int restarts = 3) {
+  int total = 0;
+  for (int rs = 0; rs <= restarts; ++rs) {
+    STCHK(lanczos_pass(p, y, kmax, tol, seed, rs > 0, v, out, st));
+    total += out.iters;
+    if (out.resid <= tol) break;
+  }
+  out.iters = total;
   return ALM_BM_OK;
 }
 
@@ -1114,7 +1141,8 @@ static alm_bm_status solve_impl(alm_bm_problem* p, const alm_bm_options& o, T* R
     launch_dual(d.m, p->Av, d.b, y, p->ybuf, sigma, p->part_vec, p->sc_solve, p->bnorm, nullptr, st);
     LanczosOut lo;
     const double tl = now_s();
-    STCHK(lanczos_run(p, p->ybuf, kmax, ltol, o.seed * 1000003ull + (uint64_t)k, p->lv, lo, st));
+    STCHK(lanczos_run(p, p->ybuf, kmax, ltol, o.seed * 1000003ull + (uint64_t)k, p->lv, lo, st,
+                      o.lanczos_restarts));
     acc.time_lanczos_s += now_s() - tl;
     bool expanded = false;
     const bool gate = (flag == 1) || !o.expand_needs_inner;
@@ -1144,7 +1172,8 @@ static alm_bm_status solve_impl(alm_bm_problem* p, const alm_bm_options& o, T* R
     if (expanded) {
       LanczosOut l2;
       const double tl2 = now_s();
-      STCHK(lanczos_run(p, y, kmax, ltol, o.seed * 1000003ull + (uint64_t)k + 7777777ull, p->lv, l2, st));
+      STCHK(lanczos_run(p, y, kmax, ltol, o.seed * 1000003ull + (uint64_t)k + 7777777ull, p->lv, l2, st,
+                        o.lanczos_restarts));
       acc.time_lanczos_s += now_s() - tl2;
       lam = l2.theta;
     }
@@ -1274,5 +1303,520 @@ extern "C" alm_bm_status alm_bm_solve(alm_bm_problem* p, const alm_bm_options* o
   acc.rank = r;
   acc.time_s = now_s() - t0;
   if (out) *out = acc;
+  return s;
+}
+
+// ===================================================================== batched solves
+
+struct alm_bm_batch {
+  alm_bm_problem* p = nullptr;      // the concatenated super-problem (owns workspace)
+  int count = 0;
+  int rs = 0;                       // rank stride
+  std::vector<int64_t> off;         // count + 1 row offsets
+  std::vector<double> cnorm;        // per instance ||C||_F
+  std::vector<int> kmax;            // per instance Lanczos basis limit (<= handle kmax)
+  std::vector<void*> own;           // device arrays owned by the batch
+  double* bnorm_dev = nullptr;      // per instance ||b||
+  int32_t* flags_dev = nullptr;     // 2 * count
+  double* tols_dev = nullptr;       // count
+  int32_t* active_dev = nullptr;    // count
+  int32_t* col_dev = nullptr;       // count
+  double* scale_dev = nullptr;      // count
+  double* thetas_dev = nullptr;     // count
+};
+
+static alm_bm_status balloc(alm_bm_batch* b, void** out, size_t bytes) {
+  if (bytes == 0) bytes = 8;
+  hipError_t e = hipMalloc(out, bytes);
+  if (e != hipSuccess) return fail(ALM_BM_ERR_OOM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
+  b->own.push_back(*out);
+  return ALM_BM_OK;
+}
+
+extern "C" alm_bm_status alm_bm_batch_destroy(alm_bm_batch* b) {
+  if (!b) return ALM_BM_OK;
+  (void)hipDeviceSynchronize();
+  if (b->p) alm_bm_destroy(b->p);
+  for (void* a : b->own) (void)hipFree(a);
+  delete b;
+  return ALM_BM_OK;
+}
+
+extern "C" alm_bm_status alm_bm_batch_offsets(const alm_bm_batch* b, int64_t* offsets) {
+  if (!b || !offsets) return fail(ALM_BM_ERR_INVALID_ARG, "batch_offsets: null argument");
+  for (int q = 0; q <= b->count; ++q) offsets[q] = b->off[q];
+  return ALM_BM_OK;
+}
+
+extern "C" alm_bm_status alm_bm_batch_create(int32_t count, const alm_bm_problem_desc* descs, int32_t rank_stride,
+                                             hipStream_t st, alm_bm_batch** out) {
+  if (!descs || !out || count < 1 || count > 4096) return fail(ALM_BM_ERR_INVALID_ARG, "batch_create: bad arguments");
+  if (rank_stride < 1 || rank_stride > kMaxR) return fail(ALM_BM_ERR_INVALID_ARG, "batch_create: rank_stride in 1..128");
+  *out = nullptr;
+  const alm_bm_precision prec = descs[0].precision;
+  long N = 0, NNZ = 0;
+  int kmax_all = 0;
+  for (int q = 0; q < count; ++q) {
+    const auto& d = descs[q];
+    if (d.cons_kind != ALM_BM_CONS_DIAG || d.m != d.n || d.j_coef != 0.0)
+      return fail(ALM_BM_ERR_UNSUPPORTED, "batch_create: DIAG family (m = n, no -J term) only");
+    if (d.precision != prec) return fail(ALM_BM_ERR_INVALID_ARG, "batch_create: one precision for all instances");
+    if (d.n <= 0 || !d.b || (d.nnz > 0 && (!d.col_idx || !d.val || (d.ell_width == 0 && !d.row_ptr))))
+      return fail(ALM_BM_ERR_INVALID_ARG, "batch_create: instance " + std::to_string(q) + " malformed");
+    N += d.n;
+    NNZ += d.nnz;
+    kmax_all = std::max(kmax_all, d.lanczos_kmax);
+  }
+  if (N > INT32_MAX || NNZ > INT32_MAX) return fail(ALM_BM_ERR_UNSUPPORTED, "batch_create: totals exceed int32");
+  if (kmax_all < 1) return fail(ALM_BM_ERR_INVALID_ARG, "batch_create: lanczos_kmax must be >= 1");
+  HIPCHK(hipStreamSynchronize(st));
+  alm_bm_batch* b = new alm_bm_batch();
+  b->count = count;
+  b->rs = rank_stride;
+  auto bail = [&](alm_bm_status s) {
+    alm_bm_batch_destroy(b);
+    return s;
+  };
+#define BK(x)                          \
+  do {                                 \
+    alm_bm_status s_ = (x);            \
+    if (s_ < 0) return bail(s_);       \
+  } while (0)
+#define BH(x)                                                                                          \
+  do {                                                                                                 \
+    hipError_t e_ = (x);                                                                               \
+    if (e_ != hipSuccess) return bail(fail(ALM_BM_ERR_HIP, std::string(#x) + ": " + hipGetErrorString(e_))); \
+  } while (0)
+  // ---- concatenate on the host (one round trip at set-up)
+  std::vector<int32_t> rp(N + 1), ci(std::max<long>(1, NNZ));
+  std::vector<double> cv(std::max<long>(1, NNZ)), dg(N, 0.0), bb(N);
+  b->off.assign(count + 1, 0);
+  b->cnorm.assign(count, 0.0);
+  b->kmax.assign(count, 0);
+  std::vector<double> bnorm(count, 0.0);
+  long ro = 0, ko = 0;
+  rp[0] = 0;
+  for (int q = 0; q < count; ++q) {
+    const auto& d = descs[q];
+    const long n = d.n;
+    b->off[q] = ro;
+    b->kmax[q] = std::max(1, d.lanczos_kmax);
+    std::vector<int32_t> lrp(n + 1), lci(d.nnz);
+    std::vector<double> lcv(d.nnz);
+    if (d.nnz) {
+      BH(hipMemcpy(lci.data(), d.col_idx, d.nnz * sizeof(int32_t), hipMemcpyDeviceToHost));
+      BH(hipMemcpy(lcv.data(), d.val, d.nnz * sizeof(double), hipMemcpyDeviceToHost));
+      if (d.ell_width > 0) {
+        for (long i = 0; i <= n; ++i) lrp[i] = (int32_t)(i * d.ell_width);
+      } else {
+        BH(hipMemcpy(lrp.data(), d.row_ptr, (n + 1) * sizeof(int32_t), hipMemcpyDeviceToHost));
+      }
+    } else {
+      std::fill(lrp.begin(), lrp.end(), 0);
+    }
+    if (d.validate && d.nnz && d.ell_width == 0) {
+      std::string why;
+      if (!check_csr(lrp, lci, n, d.nnz, why))
+        return bail(fail(ALM_BM_ERR_INVALID_PATTERN, "instance " + std::to_string(q) + ": " + why));
+    }
+    if (d.diag) BH(hipMemcpy(dg.data() + ro, d.diag, n * sizeof(double), hipMemcpyDeviceToHost));
+    BH(hipMemcpy(bb.data() + ro, d.b, n * sizeof(double), hipMemcpyDeviceToHost));
+    double c2 = 0.0, b2 = 0.0;
+    for (long i = 0; i < n; ++i) {
+      for (int k = lrp[i]; k < lrp[i + 1]; ++k) {
+        ci[ko] = lci[k] + (int32_t)ro;
+        cv[ko] = lcv[k];
+        c2 += lcv[k] * lcv[k];
+        ++ko;
+      }
+      rp[ro + i + 1] = (int32_t)ko;
+      c2 += dg[ro + i] * dg[ro + i];
+      b2 += bb[ro + i] * bb[ro + i];
+    }
+    b->cnorm[q] = std::sqrt(c2);
+    bnorm[q] = std::sqrt(b2);
+    ro += n;
+  }
+  b->off[count] = ro;
+  int32_t *drp, *dci;
+  double *dcv, *ddg, *dbb;
+  BK(balloc(b, (void**)&drp, (N + 1) * sizeof(int32_t)));
+  BK(balloc(b, (void**)&dci, std::max<long>(1, ko) * sizeof(int32_t)));
+  BK(balloc(b, (void**)&dcv, std::max<long>(1, ko) * sizeof(double)));
+  BK(balloc(b, (void**)&ddg, N * sizeof(double)));
+  BK(balloc(b, (void**)&dbb, N * sizeof(double)));
+  BH(hipMemcpy(drp, rp.data(), (N + 1) * sizeof(int32_t), hipMemcpyHostToDevice));
+  if (ko) BH(hipMemcpy(dci, ci.data(), ko * sizeof(int32_t), hipMemcpyHostToDevice));
+  if (ko) BH(hipMemcpy(dcv, cv.data(), ko * sizeof(double), hipMemcpyHostToDevice));
+  BH(hipMemcpy(ddg, dg.data(), N * sizeof(double), hipMemcpyHostToDevice));
+  BH(hipMemcpy(dbb, bb.data(), N * sizeof(double), hipMemcpyHostToDevice));
+  // ---- the super-problem handle
+  alm_bm_problem_desc sd{};
+  sd.n = N;
+  sd.nnz = ko;
+  sd.row_ptr = ko ? drp : nullptr;
+  sd.col_idx = dci;
+  sd.val = dcv;
+  sd.ell_width = 0;
+  sd.diag = ddg;
+  sd.j_coef = 0.0;
+  sd.cons_kind = ALM_BM_CONS_DIAG;
+  sd.m = N;
+  sd.b = dbb;
+  sd.precision = prec;
+  sd.r_max = rank_stride;
+  sd.lanczos_kmax = kmax_all;
+  sd.validate = 0;
+  BK(alm_bm_create(&sd, st, &b->p));
+  alm_bm_problem* p = b->p;
+  // ---- block table: instance q gets ceil(n_q / rows_per_block) blocks
+  const long rpb = std::max<long>(256, (N + 8191) / 8192);
+  std::vector<int32_t> binst, iblo(count), ibhi(count);
+  std::vector<int64_t> blo, bhi;
+  for (int q = 0; q < count; ++q) {
+    const long n = b->off[q + 1] - b->off[q];
+    const long nbq = std::max<long>(1, (n + rpb - 1) / rpb);
+    iblo[q] = (int32_t)binst.size();
+    for (long k = 0; k < nbq; ++k) {
+      binst.push_back(q);
+      blo.push_back(b->off[q] + n * k / nbq);
+      bhi.push_back(b->off[q] + n * (k + 1) / nbq);
+    }
+    ibhi[q] = (int32_t)binst.size();
+  }
+  const int nb = (int)binst.size();
+  int32_t *dbinst, *diblo, *dibhi;
+  int64_t *dblo, *dbhi;
+  BK(balloc(b, (void**)&dbinst, nb * sizeof(int32_t)));
+  BK(balloc(b, (void**)&dblo, nb * sizeof(int64_t)));
+  BK(balloc(b, (void**)&dbhi, nb * sizeof(int64_t)));
+  BK(balloc(b, (void**)&diblo, count * sizeof(int32_t)));
+  BK(balloc(b, (void**)&dibhi, count * sizeof(int32_t)));
+  BH(hipMemcpy(dbinst, binst.data(), nb * sizeof(int32_t), hipMemcpyHostToDevice));
+  BH(hipMemcpy(dblo, blo.data(), nb * sizeof(int64_t), hipMemcpyHostToDevice));
+  BH(hipMemcpy(dbhi, bhi.data(), nb * sizeof(int64_t), hipMemcpyHostToDevice));
+  BH(hipMemcpy(diblo, iblo.data(), count * sizeof(int32_t), hipMemcpyHostToDevice));
+  BH(hipMemcpy(dibhi, ibhi.data(), count * sizeof(int32_t), hipMemcpyHostToDevice));
+  p->tab = BlockTab{dbinst, dblo, dbhi, diblo, dibhi};
+  p->count = count;
+  p->nblk = nb;
+  // ---- per-instance workspace sized for the table and the instance count
+  const int kp = p->kmax + 1;
+  BK(balloc(b, (void**)&p->part, (size_t)nb * (NUM_P + kMaxR) * sizeof(double)));
+  BK(balloc(b, (void**)&p->part_c2, (size_t)nb * sizeof(double)));
+  BK(balloc(b, (void**)&p->part_vec, (size_t)nb * 2 * sizeof(double)));
+  BK(balloc(b, (void**)&p->sc_api, (size_t)count * sizeof(DevScalars)));
+  BK(balloc(b, (void**)&p->sc_solve, (size_t)count * sizeof(DevScalars)));
+  BH(hipMemset(p->sc_api, 0, (size_t)count * sizeof(DevScalars)));
+  BH(hipMemset(p->sc_solve, 0, (size_t)count * sizeof(DevScalars)));
+  p->lnb = nb;
+  BK(balloc(b, (void**)&p->lpart, (size_t)nb * kp * sizeof(double)));
+  BK(balloc(b, (void**)&p->lpart2, (size_t)nb * sizeof(double)));
+  BK(balloc(b, (void**)&p->lh1, (size_t)count * kp * sizeof(double)));
+  BK(balloc(b, (void**)&p->lh2, (size_t)count * kp * sizeof(double)));
+  BK(balloc(b, (void**)&p->lalpha, (size_t)count * kp * sizeof(double)));
+  BK(balloc(b, (void**)&p->lbeta, (size_t)count * kp * sizeof(double)));
+  BK(balloc(b, (void**)&p->ls, (size_t)count * kp * sizeof(double)));
+  BK(balloc(b, (void**)&p->lscal, (size_t)count * 4 * sizeof(double)));
+  BK(balloc(b, (void**)&b->bnorm_dev, count * sizeof(double)));
+  BK(balloc(b, (void**)&b->flags_dev, 2 * count * sizeof(int32_t)));
+  BK(balloc(b, (void**)&b->tols_dev, count * sizeof(double)));
+  BK(balloc(b, (void**)&b->active_dev, count * sizeof(int32_t)));
+  BK(balloc(b, (void**)&b->col_dev, count * sizeof(int32_t)));
+  BK(balloc(b, (void**)&b->scale_dev, count * sizeof(double)));
+  BK(balloc(b, (void**)&b->thetas_dev, count * sizeof(double)));
+  BH(hipMemcpy(b->bnorm_dev, bnorm.data(), count * sizeof(double), hipMemcpyHostToDevice));
+  BH(hipDeviceSynchronize());
+  *out = b;
+  return ALM_BM_OK;
+#undef BK
+#undef BH
+}
+
+namespace {
+
+struct BatchLanczos {
+  std::vector<double> theta, resid;
+  std::vector<int> m;
+};
+
+}  // namespace
+
+// Lanczos on Z(y) for every instance at once (lockstep steps; each instance
+// stops contributing to decisions once its Ritz residual meets tol[q]).
+static alm_bm_status batch_lanczos_pass(alm_bm_batch* b, const double* y, int kmax, const std::vector<double>& tol,
+                                        uint64_t seed, bool restart, double* v, BatchLanczos& out, hipStream_t st) {
+  alm_bm_problem* p = b->p;
+  const int count = b->count;
+  const long n = p->d.n, ldq = n;
+  const int nb = p->nblk, kp = p->kmax + 1;
+  kmax = std::min(kmax, p->kmax);
+  VecBatch vb{p->tab, count, kp, kp};
+  if (restart) {
+    launch_resid(n, v, v, 0.0, nullptr, p->lpart2, nb, st, vb);
+    launch_fin_sum(p->lpart2, nb, p->lscal, 1, st, vb, 4);
+    launch_scale(n, v, p->lscal, p->Q, p->lpart2, nb, nullptr, st, vb, 4);
+  } else {
+    launch_rand(n, seed, p->lw, p->lpart2, nb, st, vb);
+    launch_fin_sum(p->lpart2, nb, p->lscal, 1, st, vb, 4);
+    launch_scale(n, p->lw, p->lscal, p->Q, p->lpart2, nb, nullptr, st, vb, 4);
+  }
+  std::vector<double> ha((size_t)count * kp), hb((size_t)count * kp);
+  std::vector<std::vector<double>> z(count);
+  out.theta.assign(count, 0.0);
+  out.resid.assign(count, 0.0);
+  out.m.assign(count, 0);
+  std::vector<char> done(count, 0);
+  int ndone = 0;
+  for (int j = 0; j < kmax; ++j) {
+    const double* qj = p->Q + (long)j * ldq;
+    launch_slack_mv(p->C64, 0, p->adj, y, 0.0, 0.0, p->sc_api, qj, p->lw, st);
+    launch_dots(n, j + 1, p->Q, ldq, p->lw, p->lpart, kp, nb, p->lh1, st, vb);
+    launch_sub(n, j + 1, p->Q, ldq, p->lh1, p->lw, p->lpart2, nb, st, vb);
+    launch_dots(n, j + 1, p->Q, ldq, p->lw, p->lpart, kp, nb, p->lh2, st, vb);
+    launch_sub(n, j + 1, p->Q, ldq, p->lh2, p->lw, p->lpart2, nb, st, vb);
+    launch_fin_ab(p->lpart2, nb, p->lh1, p->lh2, j, p->lalpha, p->lbeta, st, vb);
+    launch_scale(n, p->lw, p->lbeta + j, p->Q + (long)(j + 1) * ldq, p->lpart2, nb, nullptr, st, vb, kp);
+    const bool last = (j + 1 == kmax);
+    if (((j + 1) % 8) == 0 || last) {
+      HIPCHK(hipMemcpyAsync(ha.data(), p->lalpha, ha.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipMemcpyAsync(hb.data(), p->lbeta, hb.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      for (int q = 0; q < count; ++q) {
+        if (done[q]) continue;
+        std::vector<double> a(ha.begin() + (long)q * kp, ha.begin() + (long)q * kp + j + 1);
+        std::vector<double> bt(hb.begin() + (long)q * kp, hb.begin() + (long)q * kp + j + 1);
+        for (int i = 0; i <= j; ++i)
+          if (!std::isfinite(a[i]) || !std::isfinite(bt[i])) return fail(ALM_BM_ERR_NUMERIC, "batch lanczos: NaN/Inf");
+        double anorm = 0.0;
+        for (int i = 0; i <= j; ++i) anorm = std::max(anorm, std::fabs(a[i]) + std::fabs(bt[i]));
+        int mm = j + 1;
+        bool breakdown = false;
+        for (int i = 0; i <= j; ++i)
+          if (bt[i] <= 1e-13 * std::max(anorm, 1e-300)) {
+            mm = i + 1;
+            breakdown = true;
+            break;
+          }
+        const double th = tri_min_eig(a, bt, mm);
+        tri_eigvec(a, bt, mm, th, z[q]);
+        out.theta[q] = th;
+        out.m[q] = mm;
+        const double est = breakdown ? 0.0 : std::fabs(bt[mm - 1] * z[q][mm - 1]);
+        if (breakdown || est <= tol[q] || mm >= b->kmax[q] || mm >= (int)(b->off[q + 1] - b->off[q])) {
+          done[q] = 1;
+          ++ndone;
+        }
+      }
+      if (ndone == count || last) break;
+    }
+  }
+  int mmax = 1;
+  std::vector<double> s((size_t)count * kp, 0.0);
+  for (int q = 0; q < count; ++q) {
+    for (int i = 0; i < out.m[q]; ++i) s[(size_t)q * kp + i] = z[q][i];
+    mmax = std::max(mmax, out.m[q]);
+  }
+  HIPCHK(hipMemcpyAsync(p->ls, s.data(), s.size() * sizeof(double), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(b->thetas_dev, out.theta.data(), count * sizeof(double), hipMemcpyHostToDevice, st));
+  launch_combine(n, mmax, p->Q, ldq, p->ls, v, p->lpart2, nb, st, vb);
+  launch_fin_sum(p->lpart2, nb, p->lscal + 1, 1, st, vb, 4);
+  launch_scale(n, v, p->lscal + 1, v, p->lpart2, nb, nullptr, st, vb, 4);
+  launch_slack_mv(p->C64, 0, p->adj, y, 0.0, 0.0, p->sc_api, v, p->lw, st);
+  launch_resid(n, p->lw, v, 0.0, b->thetas_dev, p->lpart2, nb, st, vb);
+  launch_fin_sum(p->lpart2, nb, p->lscal + 2, 1, st, vb, 4);
+  std::vector<double> sc4((size_t)count * 4);
+  HIPCHK(hipMemcpyAsync(sc4.data(), p->lscal, sc4.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  HIPCHK(hipGetLastError());
+  for (int q = 0; q < count; ++q) out.resid[q] = sc4[(size_t)q * 4 + 2];
+  return ALM_BM_OK;
+}
+
+static alm_bm_status batch_lanczos(alm_bm_batch* b, const double* y, int kmax, const std::vector<double>& tol,
+                                   uint64_t seed, double* v, BatchLanczos& out, hipStream_t st, int restarts = 3) {
+  for (int rs = 0; rs <= restarts; ++rs) {
+    STCHK(batch_lanczos_pass(b, y, kmax, tol, seed, rs > 0, v, out, st));
+    bool ok = true;
+    for (int q = 0; q < b->count; ++q)
+      if (out.resid[q] > tol[q]) ok = false;
+    if (ok) break;
+  }
+  return ALM_BM_OK;
+}
+
+template <typename T>
+static alm_bm_status batch_solve_impl(alm_bm_batch* b, const alm_bm_options& o, T* R, int32_t* r, double* y,
+                                      alm_bm_result* results, int32_t* status, hipStream_t st) {
+  alm_bm_problem* p = b->p;
+  const int count = b->count;
+  const long N = p->d.n;
+  const double sigma = o.sigma;
+  const double t0 = now_s();
+  const int refresh = o.refresh_every > 0 ? o.refresh_every
+                                          : default_refresh(sizeof(T) == 8 ? ALM_BM_F64
+                                                                           : (sizeof(T) == 4 ? ALM_BM_F32 : ALM_BM_BF16));
+  const int U = std::max(1, o.graph_unroll);
+  const int kmax = o.lanczos_kmax > 0 ? std::min(o.lanczos_kmax, p->kmax) : p->kmax;
+  std::vector<double> tolv(count), pinf_prev(count, INFINITY), tol_prev(count, INFINITY), tau(count), ltol(count);
+  std::vector<int> rcap(count);
+  std::vector<int32_t> active(count, 1), st_q(count, ALM_BM_NOT_CONVERGED);
+  std::vector<alm_bm_result> res(count);
+  for (int q = 0; q < count; ++q) {
+    const long nq = b->off[q + 1] - b->off[q];
+    rcap[q] = std::min(b->rs, bp_rank_cap(nq));
+    if (o.r_cap > 0) rcap[q] = std::min(rcap[q], o.r_cap);
+    tau[q] = o.tau_rank > 0.0 ? o.tau_rank : o.eps_kkt * (1.0 + b->cnorm[q]);
+    ltol[q] = o.lanczos_tol_rel * o.eps_kkt * (1.0 + b->cnorm[q]);
+    res[q] = alm_bm_result{};
+    res[q].promoted_at_outer = -1;
+    if (r[q] < 1 || r[q] > b->rs) return fail(ALM_BM_ERR_INVALID_ARG, "batch_solve: r[q] must be in 1..rank_stride");
+  }
+  T* G = static_cast<T*>(p->G);
+  GraphCache gc;
+  HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+  for (int u = 0; u < U; ++u) enqueue_inner_step<T>(p, b->rs, R, y, sigma, G, refresh, st);
+  HIPCHK(hipStreamEndCapture(st, &gc.graph));
+  HIPCHK(hipGraphInstantiate(&gc.exec, gc.graph, nullptr, nullptr, 0));
+  std::vector<int32_t> fl(2 * count);
+  int nactive = count;
+  for (int k = 0; k < o.max_outer && nactive > 0; ++k) {
+    for (int q = 0; q < count; ++q) {
+      if (!active[q]) continue;
+      tolv[q] = std::max(o.eps_kkt / 10.0, std::min(o.inner_tol_scale, std::min(pinf_prev[q], o.inner_tol_decay * tol_prev[q])));
+      tol_prev[q] = tolv[q];
+    }
+    HIPCHK(hipMemcpyAsync(b->tols_dev, tolv.data(), count * sizeof(double), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(b->active_dev, active.data(), count * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    launch_inner_reset_batch(p->sc_solve, count, b->tols_dev, b->active_dev, o.max_inner, (int)o.step_rule,
+                             o.eta_fixed, st);
+    int launched = 0;
+    while (true) {
+      HIPCHK(hipGraphLaunch(gc.exec, st));
+      launched += U;
+      launch_gather_flags(p->sc_solve, count, b->flags_dev, st);
+      HIPCHK(hipMemcpyAsync(fl.data(), b->flags_dev, 2 * count * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      bool all = true;
+      for (int q = 0; q < count; ++q)
+        if (fl[2 * q] == 0) all = false;
+      if (all) break;
+      if (launched > o.max_inner + 2 * U + 2) return fail(ALM_BM_ERR_HIP, "batch inner loop did not reach its stop flags");
+    }
+    for (int q = 0; q < count; ++q)
+      if (active[q]) res[q].inner_total += fl[2 * q + 1];
+    // w = y - sigma (A(RR^T) - b) for every instance
+    launch_dual_batch(N, p->Av, p->d.b, y, p->ybuf, sigma, p->part_vec, p->sc_solve, b->bnorm_dev, p->tab, p->nblk,
+                      count, st);
+    BatchLanczos L;
+    const double tl = now_s();
+    STCHK(batch_lanczos(b, p->ybuf, kmax, ltol, o.seed * 1000003ull + (uint64_t)k, p->lv, L, st,
+                        o.lanczos_restarts));
+    const double tlan = now_s() - tl;
+    // rank expansion decisions
+    std::vector<int32_t> col(count, 0);
+    std::vector<double> scale(count, -1.0);
+    std::vector<char> expanded(count, 0);
+    bool any = false;
+    if (o.rank_policy == ALM_BM_RANK_ADAPT) {
+      VecBatch vb{p->tab, count, p->kmax + 1, p->kmax + 1};
+      launch_quartic_norm(N, 0, p->adj, p->lv, p->lpart2, p->nblk, st, vb);
+      launch_fin_sum(p->lpart2, p->nblk, p->lscal + 3, 0, st, vb, 4);
+      std::vector<double> sc4((size_t)count * 4);
+      HIPCHK(hipMemcpyAsync(sc4.data(), p->lscal, sc4.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      for (int q = 0; q < count; ++q) {
+        if (!active[q]) continue;
+        const bool gate = (fl[2 * q] == 1) || !o.expand_needs_inner;
+        const double q4 = sc4[(size_t)q * 4 + 3];
+        if (gate && L.theta[q] < -tau[q] && r[q] < rcap[q] && q4 > 0.0) {
+          col[q] = r[q];
+          scale[q] = std::sqrt(std::max(0.0, -L.theta[q] / (sigma * q4)));
+          r[q] += 1;
+          expanded[q] = 1;
+          res[q].expansions += 1;
+          any = true;
+        }
+      }
+      if (any) {
+        HIPCHK(hipMemcpyAsync(b->col_dev, col.data(), count * sizeof(int32_t), hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(b->scale_dev, scale.data(), count * sizeof(double), hipMemcpyHostToDevice, st));
+        launch_fill_column<T>(N, b->rs, R, p->lv, b->col_dev, b->scale_dev, p->tab, p->nblk, st);
+        enqueue_objgrad<T>(p, b->rs, R, y, sigma, nullptr, p->Av, p->sc_api, 0, nullptr, st);
+        launch_dual_batch(N, p->Av, p->d.b, y, p->ybuf, sigma, p->part_vec, p->sc_solve, b->bnorm_dev, p->tab,
+                          p->nblk, count, st);
+      }
+    }
+    launch_copy_active(N, p->ybuf, y, b->active_dev, p->tab, p->nblk, st);
+    std::vector<double> lam(L.theta);
+    double tlan2 = 0.0;
+    if (any) {
+      BatchLanczos L2;
+      const double t2 = now_s();
+      STCHK(batch_lanczos(b, y, kmax, ltol, o.seed * 1000003ull + (uint64_t)k + 7777777ull, p->lv, L2, st,
+                          o.lanczos_restarts));
+      tlan2 = now_s() - t2;
+      for (int q = 0; q < count; ++q)
+        if (expanded[q]) lam[q] = L2.theta[q];
+    }
+    // KKT per instance: <C, RR^T> and pinf at R, b^T y at y
+    enqueue_objgrad<T>(p, b->rs, R, y, 0.0, nullptr, p->Av, p->sc_api, 0, nullptr, st);
+    launch_dual_batch(N, p->Av, p->d.b, y, nullptr, 0.0, p->part_vec, p->sc_api, b->bnorm_dev, p->tab, p->nblk, count,
+                      st);
+    std::vector<DevScalars> hs(count);
+    HIPCHK(hipMemcpyAsync(hs.data(), p->sc_api, count * sizeof(DevScalars), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    HIPCHK(hipGetLastError());
+    for (int q = 0; q < count; ++q) {
+      if (!active[q]) continue;
+      const double pobj = hs[q].tot[P_C0], dobj = hs[q].dobj, pinf = hs[q].pinf;
+      const double dinf = std::fabs(std::min(0.0, lam[q])) / (1.0 + b->cnorm[q]);
+      const double gap = std::fabs(pobj - dobj) / (1.0 + std::fabs(pobj) + std::fabs(dobj));
+      const double kkt = std::max(pinf, std::max(dinf, gap));
+      if (!std::isfinite(kkt)) return fail(ALM_BM_ERR_NUMERIC, "batch_solve: non-finite KKT in instance " + std::to_string(q));
+      res[q].outer = k + 1;
+      res[q].rank = r[q];
+      res[q].pobj = pobj;
+      res[q].dobj = dobj;
+      res[q].pinf = pinf;
+      res[q].dinf = dinf;
+      res[q].gap = gap;
+      res[q].kkt = kkt;
+      res[q].lam_min = lam[q];
+      res[q].time_lanczos_s += (tlan + tlan2) / nactive;
+      pinf_prev[q] = pinf;
+      if (kkt <= o.eps_kkt) {
+        active[q] = 0;
+        st_q[q] = ALM_BM_OK;
+        res[q].time_s = now_s() - t0;
+        --nactive;
+      }
+    }
+    if (o.verbose)
+      std::fprintf(stderr, "[almbm batch] k=%d active=%d t=%.2fs\n", k, nactive, now_s() - t0);
+    if (o.time_limit_s > 0.0 && now_s() - t0 > o.time_limit_s) break;
+  }
+  for (int q = 0; q < count; ++q) {
+    if (active[q]) res[q].time_s = now_s() - t0;
+    if (results) results[q] = res[q];
+    if (status) status[q] = st_q[q];
+  }
+  return nactive == 0 ? ALM_BM_OK : ALM_BM_NOT_CONVERGED;
+}
+
+extern "C" alm_bm_status alm_bm_batch_solve(alm_bm_batch* b, const alm_bm_options* opts, void* R, int32_t* r,
+                                            double* y, alm_bm_result* results, int32_t* status, hipStream_t st_user) {
+  if (!b || !R || !r || !y) return fail(ALM_BM_ERR_INVALID_ARG, "batch_solve: null argument");
+  alm_bm_options o;
+  if (opts) o = *opts;
+  else alm_bm_default_options(&o);
+  if (!(o.sigma > 0.0) || !(o.eps_kkt > 0.0) || o.max_outer < 1 || o.max_inner < 1)
+    return fail(ALM_BM_ERR_INVALID_ARG, "batch_solve: sigma, eps_kkt, max_outer and max_inner must be positive");
+  HIPCHK(hipStreamSynchronize(st_user));
+  hipStream_t st = b->p->ss;
+  alm_bm_status s = with_storage(b->p->d.precision, [&]<typename T>() {
+    return batch_solve_impl<T>(b, o, static_cast<T*>(R), r, y, results, status, st);
+  });
+  HIPCHK(hipStreamSynchronize(st));
   return s;
 }

@@ -20,8 +20,10 @@ __global__ void __launch_bounds__(kBlock)
 k_objgrad_diag(Cost<typename Acc<T>::type> C, int r, const T* __restrict__ R,
                const double* __restrict__ y, const double* __restrict__ b, double sigma,
                T* __restrict__ G, double* __restrict__ Av, double* __restrict__ part,
-               const DevScalars* __restrict__ sc, int refresh_every) {
+               const DevScalars* __restrict__ sc_base, int refresh_every, BlockTab tab) {
   using V = typename Acc<T>::type;
+  const Rows ch = rows_of(C.n, tab);
+  const DevScalars* sc = sc_base ? sc_base + ch.inst : nullptr;
   if (sc && sc->flag) return;
   // inside the inner loop this full pass runs only on refresh iterations
   if (sc && refresh_every > 1 && (sc->iter % refresh_every) != 0) return;
@@ -30,7 +32,6 @@ k_objgrad_diag(Cost<typename Acc<T>::type> C, int r, const T* __restrict__ R,
   const int slot = threadIdx.x / LPR;
   SplitAcc<NUM_P, LPR> acc;
   acc.zero();
-  const RowChunk ch = row_chunk(C.n);
   for (long base = ch.lo; base < ch.hi; base += RPB) {
     const long i = base + slot;
     if (i >= ch.hi) break;
@@ -119,14 +120,15 @@ k_quad_diag(Cost<typename Acc<T>::type> C, int r, const T* __restrict__ G,
 template <typename T, int LPR, int VEC, bool FULL>
 __global__ void __launch_bounds__(kBlock)
 k_quadq_diag(Cost<typename Acc<T>::type> C, int r, const T* __restrict__ G, typename Acc<T>::type* __restrict__ Q,
-             double* __restrict__ part, const DevScalars* __restrict__ sc) {
+             double* __restrict__ part, const DevScalars* __restrict__ sc_base, BlockTab tab) {
   using V = typename Acc<T>::type;
+  const Rows ch = rows_of(C.n, tab);
+  const DevScalars* sc = sc_base + ch.inst;
   if (sc->flag) return;
   constexpr int RPB = kBlock / LPR;
   const int lane = threadIdx.x % LPR;
   const int slot = threadIdx.x / LPR;
   double acc[1] = {0.0};
-  const RowChunk ch = row_chunk(C.n);
   for (long base = ch.lo; base < ch.hi; base += RPB) {
     const long i = base + slot;
     if (i >= ch.hi) break;
@@ -154,8 +156,10 @@ template <typename T, int LPR, int VEC, bool FULL>
 __global__ void __launch_bounds__(kBlock)
 k_upd_eval_diag(long n, int r, T* __restrict__ R, T* __restrict__ G, const typename Acc<T>::type* __restrict__ Q,
                 const double* __restrict__ y, const double* __restrict__ b, double sigma, double* __restrict__ Av,
-                double* __restrict__ part, const DevScalars* __restrict__ sc, int refresh_every) {
+                double* __restrict__ part, const DevScalars* __restrict__ sc_base, int refresh_every, BlockTab tab) {
   using V = typename Acc<T>::type;
+  const Rows ch = rows_of(n, tab);
+  const DevScalars* sc = sc_base + ch.inst;
   if (sc->flag) return;
   const int e = sc->iter;
   if (e == 0) return;
@@ -166,7 +170,6 @@ k_upd_eval_diag(long n, int r, T* __restrict__ R, T* __restrict__ G, const typen
   const int slot = threadIdx.x / LPR;
   SplitAcc<NUM_P, LPR> acc;
   acc.zero();
-  const RowChunk ch = row_chunk(n);
   for (long base = ch.lo; base < ch.hi; base += RPB) {
     const long i = base + slot;
     if (i >= ch.hi) break;
@@ -297,34 +300,36 @@ k_ls_diag(Cost<typename Acc<T>::type> C, int r, const T* __restrict__ R, const T
 template <typename T, int LPR, int VEC>
 static void launch_objgrad_cfg(const Cost<typename Acc<T>::type>& C, int r, const T* R, const double* y,
                                const double* b, double sigma, T* G, double* Av, double* part,
-                               const DevScalars* sc, int refresh_every, int nblk, hipStream_t st) {
+                               const DevScalars* sc, int refresh_every, const BlockTab& tab, int nblk,
+                               hipStream_t st) {
   if (r == LPR * VEC)
     hipLaunchKernelGGL((k_objgrad_diag<T, LPR, VEC, true>), dim3(nblk), dim3(kBlock), 0, st, C, r, R, y, b,
-                       sigma, G, Av, part, sc, refresh_every);
+                       sigma, G, Av, part, sc, refresh_every, tab);
   else
     hipLaunchKernelGGL((k_objgrad_diag<T, LPR, VEC, false>), dim3(nblk), dim3(kBlock), 0, st, C, r, R, y, b,
-                       sigma, G, Av, part, sc, refresh_every);
+                       sigma, G, Av, part, sc, refresh_every, tab);
 }
 
 template <typename T, int LPR, int VEC>
 static void launch_quadq_cfg(const Cost<typename Acc<T>::type>& C, int r, const T* G, typename Acc<T>::type* Q,
-                             double* part, const DevScalars* sc, int nblk, hipStream_t st) {
+                             double* part, const DevScalars* sc, const BlockTab& tab, int nblk, hipStream_t st) {
   if (r == LPR * VEC)
-    hipLaunchKernelGGL((k_quadq_diag<T, LPR, VEC, true>), dim3(nblk), dim3(kBlock), 0, st, C, r, G, Q, part, sc);
+    hipLaunchKernelGGL((k_quadq_diag<T, LPR, VEC, true>), dim3(nblk), dim3(kBlock), 0, st, C, r, G, Q, part, sc, tab);
   else
-    hipLaunchKernelGGL((k_quadq_diag<T, LPR, VEC, false>), dim3(nblk), dim3(kBlock), 0, st, C, r, G, Q, part, sc);
+    hipLaunchKernelGGL((k_quadq_diag<T, LPR, VEC, false>), dim3(nblk), dim3(kBlock), 0, st, C, r, G, Q, part, sc,
+                       tab);
 }
 
 template <typename T, int LPR, int VEC>
 static void launch_upd_eval_cfg(long n, int r, T* R, T* G, const typename Acc<T>::type* Q, const double* y,
                                 const double* b, double sigma, double* Av, double* part, const DevScalars* sc,
-                                int refresh_every, int nblk, hipStream_t st) {
+                                int refresh_every, const BlockTab& tab, int nblk, hipStream_t st) {
   if (r == LPR * VEC)
     hipLaunchKernelGGL((k_upd_eval_diag<T, LPR, VEC, true>), dim3(nblk), dim3(kBlock), 0, st, n, r, R, G, Q, y, b,
-                       sigma, Av, part, sc, refresh_every);
+                       sigma, Av, part, sc, refresh_every, tab);
   else
     hipLaunchKernelGGL((k_upd_eval_diag<T, LPR, VEC, false>), dim3(nblk), dim3(kBlock), 0, st, n, r, R, G, Q, y, b,
-                       sigma, Av, part, sc, refresh_every);
+                       sigma, Av, part, sc, refresh_every, tab);
 }
 
 template <typename T, int LPR, int VEC>
@@ -385,21 +390,22 @@ static void launch_ls_cfg(const Cost<typename Acc<T>::type>& C, int r, const T* 
 template <typename T>
 void launch_objgrad_diag(const Cost<typename Acc<T>::type>& C, int r, int variant, const T* R, const double* y,
                          const double* b, double sigma, T* G, double* Av, double* part, const DevScalars* sc,
-                         int refresh_every, int nblk, hipStream_t st) {
-  ALMBM_DISPATCH_DIAG(T, launch_objgrad_cfg, C, r, R, y, b, sigma, G, Av, part, sc, refresh_every, nblk, st);
+                         int refresh_every, const BlockTab& tab, int nblk, hipStream_t st) {
+  ALMBM_DISPATCH_DIAG(T, launch_objgrad_cfg, C, r, R, y, b, sigma, G, Av, part, sc, refresh_every, tab, nblk, st);
 }
 
 template <typename T>
 void launch_quadq_diag(const Cost<typename Acc<T>::type>& C, int r, int variant, const T* G,
-                       typename Acc<T>::type* Q, double* part, const DevScalars* sc, int nblk, hipStream_t st) {
-  ALMBM_DISPATCH_DIAG(T, launch_quadq_cfg, C, r, G, Q, part, sc, nblk, st);
+                       typename Acc<T>::type* Q, double* part, const DevScalars* sc, const BlockTab& tab, int nblk,
+                       hipStream_t st) {
+  ALMBM_DISPATCH_DIAG(T, launch_quadq_cfg, C, r, G, Q, part, sc, tab, nblk, st);
 }
 
 template <typename T>
 void launch_upd_eval_diag(long n, int r, int variant, T* R, T* G, const typename Acc<T>::type* Q, const double* y,
                           const double* b, double sigma, double* Av, double* part, const DevScalars* sc,
-                          int refresh_every, int nblk, hipStream_t st) {
-  ALMBM_DISPATCH_DIAG(T, launch_upd_eval_cfg, n, r, R, G, Q, y, b, sigma, Av, part, sc, refresh_every, nblk, st);
+                          int refresh_every, const BlockTab& tab, int nblk, hipStream_t st) {
+  ALMBM_DISPATCH_DIAG(T, launch_upd_eval_cfg, n, r, R, G, Q, y, b, sigma, Av, part, sc, refresh_every, tab, nblk, st);
 }
 
 template <typename T>
@@ -417,12 +423,12 @@ void launch_ls_diag(const Cost<typename Acc<T>::type>& C, int r, int variant, co
 #define ALMBM_INST(T)                                                                                     \
   template void launch_objgrad_diag<T>(const Cost<Acc<T>::type>&, int, int, const T*, const double*,      \
                                        const double*, double, T*, double*, double*, const DevScalars*, int, \
-                                       int, hipStream_t);                                                 \
+                                       const BlockTab&, int, hipStream_t);                                \
   template void launch_quadq_diag<T>(const Cost<Acc<T>::type>&, int, int, const T*, Acc<T>::type*, double*, \
-                                     const DevScalars*, int, hipStream_t);                                 \
+                                     const DevScalars*, const BlockTab&, int, hipStream_t);                \
   template void launch_upd_eval_diag<T>(long, int, int, T*, T*, const Acc<T>::type*, const double*,          \
-                                        const double*, double, double*, double*, const DevScalars*, int, int, \
-                                        hipStream_t);                                                      \
+                                        const double*, double, double*, double*, const DevScalars*, int,     \
+                                        const BlockTab&, int, hipStream_t);                                \
   template void launch_quad_diag<T>(const Cost<Acc<T>::type>&, int, int, const T*, double*,               \
                                     const DevScalars*, int, hipStream_t);                                 \
   template void launch_ls_diag<T>(const Cost<Acc<T>::type>&, int, int, const T*, const T*, const double*,  \

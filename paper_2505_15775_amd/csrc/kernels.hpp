@@ -71,4 +71,50 @@ struct EdgeAdj {
   const int32_t* uci;   // E, = edge_j in edge order
 };
 
+// Batched mode: many instances concatenated block-diagonally.  Every block of
+// a row kernel owns rows [lo, hi) of exactly one instance, so that per-block
+// partial sums belong to one instance; instance q owns blocks [iblo, ibhi).
+// A null table means a single instance with the default row chunking.
+struct BlockTab {
+  const int32_t* inst = nullptr;  // per block
+  const int64_t* lo = nullptr;    // per block, first row
+  const int64_t* hi = nullptr;    // per block, end row
+  const int32_t* iblo = nullptr;  // per instance, first block
+  const int32_t* ibhi = nullptr;  // per instance, end block
+};
+
+struct Rows {
+  long lo, hi;
+  int inst;
+};
+
+__device__ __forceinline__ Rows rows_of(long n, const BlockTab& t) {
+  if (!t.inst) {
+    const RowChunk c = row_chunk(n);
+    return {c.lo, c.hi, 0};
+  }
+  return {(long)t.lo[blockIdx.x], (long)t.hi[blockIdx.x], t.inst[blockIdx.x]};
+}
+
+// Lanczos vector kernels in batched mode: the table, the instance count and
+// the per-instance strides of the projection coefficients (h), of the
+// tridiagonal entries (alpha, beta) and of scalar outputs.
+struct VecBatch {
+  BlockTab tab{};
+  int count = 1;
+  int hstride = 0;
+  int astride = 0;
+};
+
+// Block range of instance `q` for a finalize kernel (single mode: [0, nb)).
+__device__ __forceinline__ void inst_blocks(const BlockTab& t, int q, int nb, int& b0, int& b1) {
+  if (!t.iblo) {
+    b0 = 0;
+    b1 = nb;
+  } else {
+    b0 = t.iblo[q];
+    b1 = t.ibhi[q];
+  }
+}
+
 }  // namespace almbm

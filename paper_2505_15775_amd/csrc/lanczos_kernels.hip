@@ -48,8 +48,8 @@ k_slack_mv(Cost<double> C, int cons_kind, EdgeAdj A, const double* __restrict__ 
 // Wave w of the block handles columns c = w, w+4, ...; lanes stride the rows.
 __global__ void __launch_bounds__(kBlock)
 k_dots(long n, int ncol, const double* __restrict__ Q, long ldq, const double* __restrict__ w,
-       double* __restrict__ part, int pstride) {
-  const RowChunk ch = row_chunk(n);
+       double* __restrict__ part, int pstride, BlockTab tab) {
+  const Rows ch = rows_of(n, tab);
   const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
   for (int c = wave; c < ncol; c += kBlock / kWave) {
     const double* q = Q + (long)c * ldq;
@@ -67,24 +67,28 @@ k_dots(long n, int ncol, const double* __restrict__ Q, long ldq, const double* _
   }
 }
 
-// h[c] = sum of the block partials of column c (one block per column, fixed order).
+// h[q][c] = sum of the block partials of column c over instance q's blocks
+// (grid: columns x instances, fixed order).
 __global__ void __launch_bounds__(kBlock)
-k_fin_dots(const double* __restrict__ part, int nb, int pstride, int ncol, double* __restrict__ h) {
-  const int c = blockIdx.x;
+k_fin_dots(const double* __restrict__ part, int nb, int pstride, int ncol, double* __restrict__ h, int hstride,
+           BlockTab tab) {
+  const int c = blockIdx.x, q = blockIdx.y;
   if (c >= ncol) return;
+  int b0, b1;
+  inst_blocks(tab, q, nb, b0, b1);
   double acc[1] = {0.0};
-  for (int b = threadIdx.x; b < nb; b += kBlock) acc[0] += part[(long)b * pstride + c];
-  block_sum_store<1>(acc, h + c);
+  for (int b = b0 + threadIdx.x; b < b1; b += kBlock) acc[0] += part[(long)b * pstride + c];
+  block_sum_store<1>(acc, h + (long)q * hstride + c);
 }
 
 // w_i -= sum_c Q[c][i] h[c]; partial ||w||^2 per block.
 __global__ void __launch_bounds__(kBlock)
-k_sub(long n, int ncol, const double* __restrict__ Q, long ldq, const double* __restrict__ h, double* __restrict__ w,
-      double* __restrict__ part) {
+k_sub(long n, int ncol, const double* __restrict__ Q, long ldq, const double* __restrict__ h, int hstride,
+      double* __restrict__ w, double* __restrict__ part, BlockTab tab) {
+  const Rows ch = rows_of(n, tab);
   __shared__ double hs[512 + 1];
-  for (int c = threadIdx.x; c < ncol; c += kBlock) hs[c] = h[c];
+  for (int c = threadIdx.x; c < ncol; c += kBlock) hs[c] = h[(long)ch.inst * hstride + c];
   __syncthreads();
-  const RowChunk ch = row_chunk(n);
   double acc[1] = {0.0};
   for (long i = ch.lo + threadIdx.x; i < ch.hi; i += kBlock) {
     double v = w[i];
@@ -98,11 +102,18 @@ k_sub(long n, int ncol, const double* __restrict__ Q, long ldq, const double* __
 // Tridiagonal entries after the two projections: alpha_j = h1[j] + h2[j],
 // beta_j = ||w||.
 __global__ void __launch_bounds__(kBlock)
-k_fin_ab(const double* __restrict__ part, int nb, const double* __restrict__ h1, const double* __restrict__ h2, int j,
-         double* __restrict__ alpha, double* __restrict__ beta) {
+k_fin_ab(const double* __restrict__ part, int nb, const double* __restrict__ h1, const double* __restrict__ h2,
+         int hstride, int j, double* __restrict__ alpha, double* __restrict__ beta, int astride, BlockTab tab) {
+  const int q = blockIdx.x;
+  int b0, b1;
+  inst_blocks(tab, q, nb, b0, b1);
+  h1 += (long)q * hstride;
+  h2 += (long)q * hstride;
+  alpha += (long)q * astride;
+  beta += (long)q * astride;
   __shared__ double red[kBlock / kWave];
   double a = 0.0;
-  for (int b = threadIdx.x; b < nb; b += kBlock) a += part[b];
+  for (int b = b0 + threadIdx.x; b < b1; b += kBlock) a += part[b];
   a = wave_sum(a);
   if (threadIdx.x % kWave == 0) red[threadIdx.x / kWave] = a;
   __syncthreads();
@@ -116,11 +127,11 @@ k_fin_ab(const double* __restrict__ part, int nb, const double* __restrict__ h1,
 
 // q = w / beta (beta > 0), partial sums of q for the -jJ term.
 __global__ void __launch_bounds__(kBlock)
-k_scale(long n, const double* __restrict__ w, const double* __restrict__ beta_ptr, double* __restrict__ q,
-        double* __restrict__ part) {
-  const double beta = *beta_ptr;
+k_scale(long n, const double* __restrict__ w, const double* __restrict__ beta_ptr, int bstride, double* __restrict__ q,
+        double* __restrict__ part, BlockTab tab) {
+  const Rows ch = rows_of(n, tab);
+  const double beta = beta_ptr[(long)ch.inst * bstride];
   const double inv = beta > 0.0 ? 1.0 / beta : 0.0;
-  const RowChunk ch = row_chunk(n);
   double acc[1] = {0.0};
   for (long i = ch.lo + threadIdx.x; i < ch.hi; i += kBlock) {
     const double v = w[i] * inv;
@@ -131,10 +142,14 @@ k_scale(long n, const double* __restrict__ w, const double* __restrict__ beta_pt
 }
 
 __global__ void __launch_bounds__(kBlock)
-k_fin_sum(const double* __restrict__ part, int nb, double* __restrict__ out, int do_sqrt) {
+k_fin_sum(const double* __restrict__ part, int nb, double* __restrict__ out, int ostride, int do_sqrt, BlockTab tab) {
+  const int q = blockIdx.x;
+  int b0, b1;
+  inst_blocks(tab, q, nb, b0, b1);
+  out += (long)q * ostride;
   __shared__ double red[kBlock / kWave];
   double a = 0.0;
-  for (int b = threadIdx.x; b < nb; b += kBlock) a += part[b];
+  for (int b = b0 + threadIdx.x; b < b1; b += kBlock) a += part[b];
   a = wave_sum(a);
   if (threadIdx.x % kWave == 0) red[threadIdx.x / kWave] = a;
   __syncthreads();
@@ -147,8 +162,8 @@ k_fin_sum(const double* __restrict__ part, int nb, double* __restrict__ out, int
 
 // Start vector: counter-based uniform entries, partial ||x||^2.
 __global__ void __launch_bounds__(kBlock)
-k_rand(long n, uint64_t seed, double* __restrict__ x, double* __restrict__ part) {
-  const RowChunk ch = row_chunk(n);
+k_rand(long n, uint64_t seed, double* __restrict__ x, double* __restrict__ part, BlockTab tab) {
+  const Rows ch = rows_of(n, tab);
   double acc[1] = {0.0};
   for (long i = ch.lo + threadIdx.x; i < ch.hi; i += kBlock) {
     const double v = counter_uniform(seed, (uint64_t)i);
@@ -160,12 +175,12 @@ k_rand(long n, uint64_t seed, double* __restrict__ x, double* __restrict__ part)
 
 // v = sum_c Q[c] s[c]; partial ||v||^2.
 __global__ void __launch_bounds__(kBlock)
-k_combine(long n, int ncol, const double* __restrict__ Q, long ldq, const double* __restrict__ s,
-          double* __restrict__ v, double* __restrict__ part) {
+k_combine(long n, int ncol, const double* __restrict__ Q, long ldq, const double* __restrict__ s, int sstride,
+          double* __restrict__ v, double* __restrict__ part, BlockTab tab) {
+  const Rows ch = rows_of(n, tab);
   __shared__ double ss[512 + 1];
-  for (int c = threadIdx.x; c < ncol; c += kBlock) ss[c] = s[c];
+  for (int c = threadIdx.x; c < ncol; c += kBlock) ss[c] = s[(long)ch.inst * sstride + c];
   __syncthreads();
-  const RowChunk ch = row_chunk(n);
   double acc[1] = {0.0};
   for (long i = ch.lo + threadIdx.x; i < ch.hi; i += kBlock) {
     double a = 0.0;
@@ -178,8 +193,10 @@ k_combine(long n, int ncol, const double* __restrict__ Q, long ldq, const double
 
 // partial ||z - theta v||^2 (residual of the Ritz pair).
 __global__ void __launch_bounds__(kBlock)
-k_resid(long n, const double* __restrict__ z, const double* __restrict__ v, double theta, double* __restrict__ part) {
-  const RowChunk ch = row_chunk(n);
+k_resid(long n, const double* __restrict__ z, const double* __restrict__ v, double theta,
+        const double* __restrict__ thetas, double* __restrict__ part, BlockTab tab) {
+  const Rows ch = rows_of(n, tab);
+  if (thetas) theta = thetas[ch.inst];
   double acc[1] = {0.0};
   for (long i = ch.lo + threadIdx.x; i < ch.hi; i += kBlock) {
     const double d = z[i] - theta * v[i];
@@ -191,8 +208,9 @@ k_resid(long n, const double* __restrict__ z, const double* __restrict__ v, doub
 // sum_i x_i^4 (DIAG) or sum over edges of (x_i x_j)^2 (TRACE_EDGES): the
 // curvature ||A(v v^T)||^2 of the rank-one step, without the trace row.
 __global__ void __launch_bounds__(kBlock)
-k_quartic_norm(long n, int cons_kind, EdgeAdj A, const double* __restrict__ x, double* __restrict__ part) {
-  const RowChunk ch = row_chunk(n);
+k_quartic_norm(long n, int cons_kind, EdgeAdj A, const double* __restrict__ x, double* __restrict__ part,
+               BlockTab tab) {
+  const Rows ch = rows_of(n, tab);
   double acc[1] = {0.0};
   for (long i = ch.lo + threadIdx.x; i < ch.hi; i += kBlock) {
     const double xi = x[i];
@@ -208,7 +226,7 @@ k_quartic_norm(long n, int cons_kind, EdgeAdj A, const double* __restrict__ x, d
   block_sum_store<1>(acc, part + blockIdx.x);
 }
 
-// ---- launchers -------------------------------------------------------------------
+// ---- launchers (single instance: empty table, count 1, strides 0) ---------------
 
 int vec_blocks(long n) {
   long nb = (n + kBlock * 16 - 1) / (kBlock * 16);
@@ -224,39 +242,55 @@ void launch_slack_mv(const Cost<double>& C, int cons_kind, const EdgeAdj& A, con
   hipLaunchKernelGGL(k_slack_mv, dim3(nb), dim3(kBlock), 0, st, C, cons_kind, A, y, c_tr, j_coef, sc, x, out);
 }
 void launch_dots(long n, int ncol, const double* Q, long ldq, const double* w, double* part, int pstride, int nb,
-                 double* h, hipStream_t st) {
-  hipLaunchKernelGGL(k_dots, dim3(nb), dim3(kBlock), 0, st, n, ncol, Q, ldq, w, part, pstride);
-  hipLaunchKernelGGL(k_fin_dots, dim3(ncol), dim3(kBlock), 0, st, part, nb, pstride, ncol, h);
+                 double* h, hipStream_t st, const VecBatch& vb) {
+  hipLaunchKernelGGL(k_dots, dim3(nb), dim3(kBlock), 0, st, n, ncol, Q, ldq, w, part, pstride, vb.tab);
+  hipLaunchKernelGGL(k_fin_dots, dim3(ncol, vb.count), dim3(kBlock), 0, st, part, nb, pstride, ncol, h, vb.hstride,
+                     vb.tab);
 }
 void launch_sub(long n, int ncol, const double* Q, long ldq, const double* h, double* w, double* part, int nb,
-                hipStream_t st) {
-  hipLaunchKernelGGL(k_sub, dim3(nb), dim3(kBlock), 0, st, n, ncol, Q, ldq, h, w, part);
+                hipStream_t st, const VecBatch& vb) {
+  hipLaunchKernelGGL(k_sub, dim3(nb), dim3(kBlock), 0, st, n, ncol, Q, ldq, h, vb.hstride, w, part, vb.tab);
 }
 void launch_fin_ab(const double* part, int nb, const double* h1, const double* h2, int j, double* alpha, double* beta,
-                   hipStream_t st) {
-  hipLaunchKernelGGL(k_fin_ab, dim3(1), dim3(kBlock), 0, st, part, nb, h1, h2, j, alpha, beta);
+                   hipStream_t st, const VecBatch& vb) {
+  hipLaunchKernelGGL(k_fin_ab, dim3(vb.count), dim3(kBlock), 0, st, part, nb, h1, h2, vb.hstride, j, alpha, beta,
+                     vb.astride, vb.tab);
 }
 void launch_scale(long n, const double* w, const double* beta, double* q, double* part, int nb, double* qsum,
-                  hipStream_t st) {
-  hipLaunchKernelGGL(k_scale, dim3(nb), dim3(kBlock), 0, st, n, w, beta, q, part);
-  if (qsum) hipLaunchKernelGGL(k_fin_sum, dim3(1), dim3(kBlock), 0, st, part, nb, qsum, 0);
+                  hipStream_t st, const VecBatch& vb, int bstride) {
+  hipLaunchKernelGGL(k_scale, dim3(nb), dim3(kBlock), 0, st, n, w, beta, bstride, q, part, vb.tab);
+  if (qsum) hipLaunchKernelGGL(k_fin_sum, dim3(vb.count), dim3(kBlock), 0, st, part, nb, qsum, 0, 0, vb.tab);
 }
-void launch_fin_sum(const double* part, int nb, double* out, int do_sqrt, hipStream_t st) {
-  hipLaunchKernelGGL(k_fin_sum, dim3(1), dim3(kBlock), 0, st, part, nb, out, do_sqrt);
+void launch_fin_sum(const double* part, int nb, double* out, int do_sqrt, hipStream_t st, const VecBatch& vb,
+                    int ostride) {
+  hipLaunchKernelGGL(k_fin_sum, dim3(vb.count), dim3(kBlock), 0, st, part, nb, out, ostride, do_sqrt, vb.tab);
 }
-void launch_rand(long n, uint64_t seed, double* x, double* part, int nb, hipStream_t st) {
-  hipLaunchKernelGGL(k_rand, dim3(nb), dim3(kBlock), 0, st, n, seed, x, part);
+void launch_rand(long n, uint64_t seed, double* x, double* part, int nb, hipStream_t st, const VecBatch& vb) {
+  hipLaunchKernelGGL(k_rand, dim3(nb), dim3(kBlock), 0, st, n, seed, x, part, vb.tab);
 }
 void launch_combine(long n, int ncol, const double* Q, long ldq, const double* s, double* v, double* part, int nb,
-                    hipStream_t st) {
-  hipLaunchKernelGGL(k_combine, dim3(nb), dim3(kBlock), 0, st, n, ncol, Q, ldq, s, v, part);
+                    hipStream_t st, const VecBatch& vb) {
+  hipLaunchKernelGGL(k_combine, dim3(nb), dim3(kBlock), 0, st, n, ncol, Q, ldq, s, vb.hstride, v, part, vb.tab);
 }
-void launch_resid(long n, const double* z, const double* v, double theta, double* part, int nb, hipStream_t st) {
-  hipLaunchKernelGGL(k_resid, dim3(nb), dim3(kBlock), 0, st, n, z, v, theta, part);
+void launch_resid(long n, const double* z, const double* v, double theta, const double* thetas, double* part, int nb,
+                  hipStream_t st, const VecBatch& vb) {
+  hipLaunchKernelGGL(k_resid, dim3(nb), dim3(kBlock), 0, st, n, z, v, theta, thetas, part, vb.tab);
 }
 void launch_quartic_norm(long n, int cons_kind, const EdgeAdj& A, const double* x, double* part, int nb,
-                         hipStream_t st) {
-  hipLaunchKernelGGL(k_quartic_norm, dim3(nb), dim3(kBlock), 0, st, n, cons_kind, A, x, part);
+                         hipStream_t st, const VecBatch& vb) {
+  hipLaunchKernelGGL(k_quartic_norm, dim3(nb), dim3(kBlock), 0, st, n, cons_kind, A, x, part, vb.tab);
+}
+
+// flags[q] = sc[q].flag, iters[q] = sc[q].iter (compact copy for the host).
+__global__ void k_gather_flags(const DevScalars* __restrict__ sc, int count, int32_t* __restrict__ out) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= count) return;
+  out[2 * q] = sc[q].flag;
+  out[2 * q + 1] = sc[q].iter;
+}
+
+void launch_gather_flags(const DevScalars* sc, int count, int32_t* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_gather_flags, dim3((count + 63) / 64), dim3(64), 0, st, sc, count, out);
 }
 
 }  // namespace almbm

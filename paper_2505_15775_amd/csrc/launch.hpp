@@ -8,14 +8,15 @@ namespace almbm {
 template <typename T>
 void launch_objgrad_diag(const Cost<typename Acc<T>::type>& C, int r, int variant, const T* R, const double* y,
                          const double* b, double sigma, T* G, double* Av, double* part, const DevScalars* sc,
-                         int refresh_every, int nblk, hipStream_t st);
+                         int refresh_every, const BlockTab& tab, int nblk, hipStream_t st);
 template <typename T>
 void launch_quadq_diag(const Cost<typename Acc<T>::type>& C, int r, int variant, const T* G,
-                       typename Acc<T>::type* Q, double* part, const DevScalars* sc, int nblk, hipStream_t st);
+                       typename Acc<T>::type* Q, double* part, const DevScalars* sc, const BlockTab& tab, int nblk,
+                       hipStream_t st);
 template <typename T>
 void launch_upd_eval_diag(long n, int r, int variant, T* R, T* G, const typename Acc<T>::type* Q, const double* y,
                           const double* b, double sigma, double* Av, double* part, const DevScalars* sc,
-                          int refresh_every, int nblk, hipStream_t st);
+                          int refresh_every, const BlockTab& tab, int nblk, hipStream_t st);
 template <typename T>
 void launch_quad_diag(const Cost<typename Acc<T>::type>& C, int r, int variant, const T* G, double* part,
                       const DevScalars* sc, int nblk, hipStream_t st);
@@ -44,9 +45,20 @@ void launch_fin_edges3(const double* part, int nb, int r, DevScalars* sc, const 
                        hipStream_t st);
 
 void launch_fin_objgrad(const double* part, int nb, DevScalars* sc, double sigma, int mode, double* f_out,
-                        hipStream_t st);
+                        hipStream_t st, const BlockTab& tab = BlockTab{}, int count = 1);
 void launch_fin_step(const double* part_c2, int nb, int c2_stride, DevScalars* sc, double sigma, double j_extra,
-                     int mode, double* coeffs_out, double* t_out, hipStream_t st);
+                     int mode, double* coeffs_out, double* t_out, hipStream_t st, const BlockTab& tab = BlockTab{},
+                     int count = 1);
+void launch_dual_batch(long m, const double* Av, const double* b, const double* y_in, double* y_out, double sigma,
+                       double* part, DevScalars* sc, const double* bnorms, const BlockTab& tab, int nb, int count,
+                       hipStream_t st);
+void launch_inner_reset_batch(DevScalars* sc, int count, const double* tols, const int32_t* active, int max_inner,
+                              int step_rule, double eta, hipStream_t st);
+void launch_copy_active(long m, const double* src, double* dst, const int32_t* active, const BlockTab& tab, int nb,
+                        hipStream_t st);
+template <typename T>
+void launch_fill_column(long n, int rs, T* R, const double* v, const int32_t* col, const double* scale,
+                        const BlockTab& tab, int nb, hipStream_t st);
 void launch_fin_ls(const double* part, int nb, DevScalars* sc, double sigma, double* coeffs_out, double* t_out,
                    hipStream_t st);
 template <typename T>
@@ -64,20 +76,24 @@ int vec_blocks(long n);
 void launch_slack_mv(const Cost<double>& C, int cons_kind, const EdgeAdj& A, const double* y, double c_tr,
                      double j_coef, const DevScalars* sc, const double* x, double* out, hipStream_t st);
 void launch_dots(long n, int ncol, const double* Q, long ldq, const double* w, double* part, int pstride, int nb,
-                 double* h, hipStream_t st);
+                 double* h, hipStream_t st, const VecBatch& vb = VecBatch{});
 void launch_sub(long n, int ncol, const double* Q, long ldq, const double* h, double* w, double* part, int nb,
-                hipStream_t st);
+                hipStream_t st, const VecBatch& vb = VecBatch{});
 void launch_fin_ab(const double* part, int nb, const double* h1, const double* h2, int j, double* alpha, double* beta,
-                   hipStream_t st);
+                   hipStream_t st, const VecBatch& vb = VecBatch{});
 void launch_scale(long n, const double* w, const double* beta, double* q, double* part, int nb, double* qsum,
-                  hipStream_t st);
-void launch_fin_sum(const double* part, int nb, double* out, int do_sqrt, hipStream_t st);
-void launch_rand(long n, uint64_t seed, double* x, double* part, int nb, hipStream_t st);
+                  hipStream_t st, const VecBatch& vb = VecBatch{}, int bstride = 0);
+void launch_gather_flags(const DevScalars* sc, int count, int32_t* out, hipStream_t st);
+void launch_fin_sum(const double* part, int nb, double* out, int do_sqrt, hipStream_t st,
+                    const VecBatch& vb = VecBatch{}, int ostride = 0);
+void launch_rand(long n, uint64_t seed, double* x, double* part, int nb, hipStream_t st,
+                 const VecBatch& vb = VecBatch{});
 void launch_combine(long n, int ncol, const double* Q, long ldq, const double* s, double* v, double* part, int nb,
-                    hipStream_t st);
-void launch_resid(long n, const double* z, const double* v, double theta, double* part, int nb, hipStream_t st);
+                    hipStream_t st, const VecBatch& vb = VecBatch{});
+void launch_resid(long n, const double* z, const double* v, double theta, const double* thetas, double* part, int nb,
+                  hipStream_t st, const VecBatch& vb = VecBatch{});
 void launch_quartic_norm(long n, int cons_kind, const EdgeAdj& A, const double* x, double* part, int nb,
-                         hipStream_t st);
+                         hipStream_t st, const VecBatch& vb = VecBatch{});
 
 void launch_ws_features(const Cost<double>& C, float* F, float* ldeg, hipStream_t st);
 int ws_param_count(int nin, int h);

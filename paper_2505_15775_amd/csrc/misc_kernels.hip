@@ -11,11 +11,11 @@ namespace almbm {
 // part is [nb][NS]; thread t sums blocks t, t+256, ... in order, then the block
 // tree is fixed, so the total does not depend on timing.
 template <int NS>
-__device__ void reduce_partials(const double* __restrict__ part, int nb, int stride, double* __restrict__ out) {
+__device__ void reduce_partials(const double* __restrict__ part, int b0, int b1, int stride, double* __restrict__ out) {
   double acc[NS];
 #pragma unroll
   for (int s = 0; s < NS; ++s) acc[s] = 0.0;
-  for (int bi = threadIdx.x; bi < nb; bi += kBlock) {
+  for (int bi = b0 + threadIdx.x; bi < b1; bi += kBlock) {
 #pragma unroll
     for (int s = 0; s < NS; ++s) acc[s] += part[(long)bi * stride + s];
   }
@@ -33,13 +33,19 @@ __device__ __forceinline__ bool finite(double x) { return isfinite(x); }
 // Objective totals of the DIAG family.  mode 0: API call, writes *f_out.
 // mode 1: inner loop step 1 -- after max_inner steps stop (flag 2), else the
 // stop test ||G|| ||R|| <= tol (1 + |<C,RR^T>|) (flag 1), else count the step.
+// One block per instance (blockIdx.x; a single instance without a table).
 __global__ void __launch_bounds__(kBlock)
-k_fin_objgrad(const double* __restrict__ part, int nb, DevScalars* __restrict__ sc, double sigma, int mode,
-              double* __restrict__ f_out) {
+k_fin_objgrad(const double* __restrict__ part, int nb, DevScalars* __restrict__ sc_base, double sigma, int mode,
+              double* __restrict__ f_out, BlockTab tab) {
+  const int q = blockIdx.x;
+  DevScalars* sc = sc_base + q;
   if (mode == 1 && sc->flag) return;
+  int b0, b1;
+  inst_blocks(tab, q, nb, b0, b1);
   __shared__ double tot[NUM_P];
-  reduce_partials<NUM_P>(part, nb, NUM_P, tot);
+  reduce_partials<NUM_P>(part, b0, b1, NUM_P, tot);
   if (threadIdx.x != 0) return;
+  if (f_out) f_out += q;
   for (int s = 0; s < NUM_P; ++s) sc->tot[s] = tot[s];
   const double f = tot[P_C0] + tot[P_YBMA] + 0.5 * sigma * tot[P_EE];
   sc->f = f;
@@ -60,11 +66,15 @@ k_fin_objgrad(const double* __restrict__ part, int nb, DevScalars* __restrict__ 
 // Step rule: reduce the <G, CG> partials into tot[P_C2], form the quartic and
 // pick t.  mode 0: API (coeffs/t to the given pointers).  mode 1: inner loop.
 __global__ void __launch_bounds__(kBlock)
-k_fin_step(const double* __restrict__ part_c2, int nb, int c2_stride, DevScalars* __restrict__ sc, double sigma,
-           double j_extra_c2, int mode, double* __restrict__ coeffs_out, double* __restrict__ t_out) {
+k_fin_step(const double* __restrict__ part_c2, int nb, int c2_stride, DevScalars* __restrict__ sc_base, double sigma,
+           double j_extra_c2, int mode, double* __restrict__ coeffs_out, double* __restrict__ t_out, BlockTab tab) {
+  const int q = blockIdx.x;
+  DevScalars* sc = sc_base + q;
   if (mode == 1 && sc->flag) return;
+  int b0, b1;
+  inst_blocks(tab, q, nb, b0, b1);
   __shared__ double c2[1];
-  if (part_c2) reduce_partials<1>(part_c2, nb, c2_stride, c2);
+  if (part_c2) reduce_partials<1>(part_c2, b0, b1, c2_stride, c2);
   if (threadIdx.x != 0) return;
   if (part_c2) sc->tot[P_C2] = c2[0] + j_extra_c2;
   double k[5];
@@ -86,7 +96,7 @@ __global__ void __launch_bounds__(kBlock)
 k_fin_ls(const double* __restrict__ part, int nb, DevScalars* __restrict__ sc, double sigma,
          double* __restrict__ coeffs_out, double* __restrict__ t_out) {
   __shared__ double tot[NUM_P];
-  reduce_partials<NUM_P>(part, nb, NUM_P, tot);
+  reduce_partials<NUM_P>(part, 0, nb, NUM_P, tot);
   if (threadIdx.x != 0) return;
   for (int s = 0; s < NUM_P; ++s) sc->tot[s] = tot[s];
   double k[5];
@@ -115,10 +125,20 @@ k_update(long len, T* __restrict__ R, const T* __restrict__ G, const DevScalars*
 // y_out = y_in - sigma (Av - b); partials {||Av - b||^2, b^T y_out}.
 __global__ void __launch_bounds__(kBlock)
 k_dual(long m, const double* __restrict__ Av, const double* __restrict__ b, const double* __restrict__ y_in,
-       double* __restrict__ y_out, double sigma, double* __restrict__ part) {
+       double* __restrict__ y_out, double sigma, double* __restrict__ part, BlockTab tab) {
   double acc[2] = {0.0, 0.0};
-  const long stride = (long)gridDim.x * kBlock;
-  for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < m; i += stride) {
+  long i0, i1, step;
+  if (tab.inst) {
+    const Rows rw = rows_of(m, tab);
+    i0 = rw.lo + threadIdx.x;
+    i1 = rw.hi;
+    step = kBlock;
+  } else {
+    i0 = (long)blockIdx.x * kBlock + threadIdx.x;
+    i1 = m;
+    step = (long)gridDim.x * kBlock;
+  }
+  for (long i = i0; i < i1; i += step) {
     const double e = Av[i] - b[i];
     const double yn = y_in[i] - sigma * e;
     if (y_out) y_out[i] = yn;
@@ -129,11 +149,17 @@ k_dual(long m, const double* __restrict__ Av, const double* __restrict__ b, cons
 }
 
 __global__ void __launch_bounds__(kBlock)
-k_fin_dual(const double* __restrict__ part, int nb, DevScalars* __restrict__ sc, double bnorm,
-           double* __restrict__ pinf_out) {
+k_fin_dual(const double* __restrict__ part, int nb, DevScalars* __restrict__ sc_base, double bnorm,
+           const double* __restrict__ bnorms, double* __restrict__ pinf_out, BlockTab tab) {
+  const int q = blockIdx.x;
+  DevScalars* sc = sc_base + q;
+  if (bnorms) bnorm = bnorms[q];
+  int b0, b1;
+  inst_blocks(tab, q, nb, b0, b1);
   __shared__ double tot[2];
-  reduce_partials<2>(part, nb, 2, tot);
+  reduce_partials<2>(part, b0, b1, 2, tot);
   if (threadIdx.x != 0) return;
+  if (pinf_out) pinf_out += q;
   sc->res2 = tot[0];
   sc->pinf = sqrt(tot[0]) / (1.0 + bnorm);
   sc->dobj = tot[1];
@@ -152,6 +178,41 @@ __global__ void k_inner_reset(DevScalars* sc, double tol, int max_inner, int ste
     sc->step_rule = step_rule;
     sc->eta_fixed = eta;
   }
+}
+
+// Batched reset: instance q runs (flag 0) when active[q], else is frozen (flag 3).
+__global__ void k_inner_reset_batch(DevScalars* sc, int count, const double* __restrict__ tols,
+                                    const int32_t* __restrict__ active, int max_inner, int step_rule, double eta) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= count) return;
+  sc[q].flag = active[q] ? 0 : 3;
+  sc[q].iter = 0;
+  sc[q].tol = tols[q];
+  sc[q].max_inner = max_inner;
+  sc[q].step_rule = step_rule;
+  sc[q].eta_fixed = eta;
+}
+
+// Batched helpers: y <- ybuf on the rows of active instances; column c_q of R
+// (row stride rs) <- scale_q v on the rows of instance q where scale_q >= 0.
+__global__ void __launch_bounds__(kBlock)
+k_copy_active(long m, const double* __restrict__ src, double* __restrict__ dst, const int32_t* __restrict__ active,
+              BlockTab tab) {
+  const Rows rw = rows_of(m, tab);
+  if (!active[rw.inst]) return;
+  for (long i = rw.lo + threadIdx.x; i < rw.hi; i += kBlock) dst[i] = src[i];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_fill_column(long n, int rs, T* __restrict__ R, const double* __restrict__ v, const int32_t* __restrict__ col,
+              const double* __restrict__ scale, BlockTab tab) {
+  const Rows rw = rows_of(n, tab);
+  const double s = scale[rw.inst];
+  if (!(s >= 0.0)) return;
+  const int c = col[rw.inst];
+  for (long i = rw.lo + threadIdx.x; i < rw.hi; i += kBlock)
+    R[i * rs + c] = from_acc<T>(static_cast<typename Acc<T>::type>(s * v[i]));
 }
 
 // Copy with change of row stride: dst (n x rd) <- src (n x rs) for the first
@@ -182,13 +243,13 @@ __global__ void __launch_bounds__(kBlock) k_convert(long len, const S* __restric
 // ---- launch helpers ------------------------------------------------------------
 
 void launch_fin_objgrad(const double* part, int nb, DevScalars* sc, double sigma, int mode, double* f_out,
-                        hipStream_t st) {
-  hipLaunchKernelGGL(k_fin_objgrad, dim3(1), dim3(kBlock), 0, st, part, nb, sc, sigma, mode, f_out);
+                        hipStream_t st, const BlockTab& tab, int count) {
+  hipLaunchKernelGGL(k_fin_objgrad, dim3(count), dim3(kBlock), 0, st, part, nb, sc, sigma, mode, f_out, tab);
 }
 void launch_fin_step(const double* part_c2, int nb, int c2_stride, DevScalars* sc, double sigma, double j_extra,
-                     int mode, double* coeffs_out, double* t_out, hipStream_t st) {
-  hipLaunchKernelGGL(k_fin_step, dim3(1), dim3(kBlock), 0, st, part_c2, nb, c2_stride, sc, sigma, j_extra, mode,
-                     coeffs_out, t_out);
+                     int mode, double* coeffs_out, double* t_out, hipStream_t st, const BlockTab& tab, int count) {
+  hipLaunchKernelGGL(k_fin_step, dim3(count), dim3(kBlock), 0, st, part_c2, nb, c2_stride, sc, sigma, j_extra, mode,
+                     coeffs_out, t_out, tab);
 }
 void launch_fin_ls(const double* part, int nb, DevScalars* sc, double sigma, double* coeffs_out, double* t_out,
                    hipStream_t st) {
@@ -217,12 +278,38 @@ int dual_blocks(long m) {
 void launch_dual(long m, const double* Av, const double* b, const double* y_in, double* y_out, double sigma,
                  double* part, DevScalars* sc, double bnorm, double* pinf_out, hipStream_t st) {
   const int nb = dual_blocks(m);
-  hipLaunchKernelGGL(k_dual, dim3(nb), dim3(kBlock), 0, st, m, Av, b, y_in, y_out, sigma, part);
-  hipLaunchKernelGGL(k_fin_dual, dim3(1), dim3(kBlock), 0, st, part, nb, sc, bnorm, pinf_out);
+  hipLaunchKernelGGL(k_dual, dim3(nb), dim3(kBlock), 0, st, m, Av, b, y_in, y_out, sigma, part, BlockTab{});
+  hipLaunchKernelGGL(k_fin_dual, dim3(1), dim3(kBlock), 0, st, part, nb, sc, bnorm, nullptr, pinf_out, BlockTab{});
+}
+void launch_dual_batch(long m, const double* Av, const double* b, const double* y_in, double* y_out, double sigma,
+                       double* part, DevScalars* sc, const double* bnorms, const BlockTab& tab, int nb, int count,
+                       hipStream_t st) {
+  hipLaunchKernelGGL(k_dual, dim3(nb), dim3(kBlock), 0, st, m, Av, b, y_in, y_out, sigma, part, tab);
+  hipLaunchKernelGGL(k_fin_dual, dim3(count), dim3(kBlock), 0, st, part, nb, sc, 0.0, bnorms, nullptr, tab);
 }
 void launch_inner_reset(DevScalars* sc, double tol, int max_inner, int step_rule, double eta, hipStream_t st) {
   hipLaunchKernelGGL(k_inner_reset, dim3(1), dim3(64), 0, st, sc, tol, max_inner, step_rule, eta);
 }
+void launch_inner_reset_batch(DevScalars* sc, int count, const double* tols, const int32_t* active, int max_inner,
+                              int step_rule, double eta, hipStream_t st) {
+  hipLaunchKernelGGL(k_inner_reset_batch, dim3((count + 63) / 64), dim3(64), 0, st, sc, count, tols, active,
+                     max_inner, step_rule, eta);
+}
+void launch_copy_active(long m, const double* src, double* dst, const int32_t* active, const BlockTab& tab, int nb,
+                        hipStream_t st) {
+  hipLaunchKernelGGL(k_copy_active, dim3(nb), dim3(kBlock), 0, st, m, src, dst, active, tab);
+}
+template <typename T>
+void launch_fill_column(long n, int rs, T* R, const double* v, const int32_t* col, const double* scale,
+                        const BlockTab& tab, int nb, hipStream_t st) {
+  hipLaunchKernelGGL((k_fill_column<T>), dim3(nb), dim3(kBlock), 0, st, n, rs, R, v, col, scale, tab);
+}
+template void launch_fill_column<double>(long, int, double*, const double*, const int32_t*, const double*,
+                                         const BlockTab&, int, hipStream_t);
+template void launch_fill_column<float>(long, int, float*, const double*, const int32_t*, const double*,
+                                        const BlockTab&, int, hipStream_t);
+template void launch_fill_column<bf16>(long, int, bf16*, const double*, const int32_t*, const double*,
+                                       const BlockTab&, int, hipStream_t);
 template <typename T>
 void launch_relayout(long n, int rs, int rd, const T* src, T* dst, const double* v, double scale, hipStream_t st) {
   hipLaunchKernelGGL((k_relayout<T>), dim3(elem_blocks(n * rd)), dim3(kBlock), 0, st, n, rs, rd, src, dst, v, scale);

@@ -1,0 +1,85 @@
+"""Batched solves (GPU only): every instance of a batch against its own
+single-instance solve and against the oracle's KKT measure at the batch's
+point, closed forms inside a batch, determinism, and the zero-padding
+invariant of the shared row width."""
+
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import gen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def _almbm():
+    import paper_2505_15775_amd as m
+
+    return m
+
+
+def _instances():
+    insts = [(gen.cycle_graph(8), 2), (gen.cycle_graph(9), 2)]
+    for (g, r) in gen.batch_instances(6, 3, n_lo=300, n_hi=3000, deg_lo=4, deg_hi=12, ranks=(4, 8)):
+        insts.append((g, r))
+    return insts
+
+
+def _problems(insts, prec="f64", r_max=48):
+    m = _almbm()
+    return [m.Problem.maxcut(g.n, g.ei, g.ej, g.w, precision=prec, r_max=r_max, lanczos_kmax=60, device=DEV)
+            for g, _ in insts]
+
+
+def test_batch_matches_single_solves_and_oracle_kkt():
+    insts = _instances()
+    probs = _problems(insts)
+    stride = 48  # the two largest instances reach rank 31 and 32 at the optimum
+    batch = _almbm().Batch(probs, rank_stride=stride)
+    factors = [gen.init_factor(g.n, r, 1) for g, r in insts]
+    st, sts, res, R, ranks, y = batch.solve(factors, eps_kkt=1e-6, max_outer=400)
+    print(f"batch: status {st} per-instance {sts} outer {[x['outer'] for x in res]} ranks {ranks}")
+    assert st == 0 and all(s == 0 for s in sts)
+    for q, ((g, r), p) in enumerate(zip(insts, probs)):
+        s1, r1, Rq1, yq1 = p.solve(factors[q], eps_kkt=1e-6, max_outer=400)
+        assert s1 == 0
+        Rq, yq = batch.instance(q, R, y, ranks[q])
+        po = oracle.maxcut_sdp(g)
+        lam = oracle.min_eig(po, yq.cpu().numpy())
+        k = oracle.kkt(po, Rq.cpu().numpy(), yq.cpu().numpy(), lam_min=lam)
+        print(f"instance {q} n={g.n}: batch pobj {res[q]['pobj']:.10f} single {r1['pobj']:.10f} "
+              f"oracle kkt {k['kkt']:.2e}")
+        assert abs(res[q]["pobj"] - r1["pobj"]) <= 2e-6 * abs(r1["pobj"])
+        assert k["pinf"] <= 1e-6 and k["gap"] <= 1e-6 and k["dinf"] <= 2e-6
+    # closed forms of the two cycles
+    assert math.isclose(-res[0]["pobj"], 8.0, rel_tol=1e-5)
+    assert math.isclose(-res[1]["pobj"], 9 * (1 + math.cos(math.pi / 9)) / 2, rel_tol=1e-5)
+    # padding columns stay exactly zero
+    for q in range(len(insts)):
+        a, b = batch.offsets[q], batch.offsets[q + 1]
+        assert float(R[a:b, ranks[q]:].abs().max() if ranks[q] < stride else 0.0) == 0.0
+
+
+def test_batch_deterministic():
+    insts = _instances()[2:6]
+    outs = []
+    for _ in range(2):
+        batch = _almbm().Batch(_problems(insts, prec="f32", r_max=16), rank_stride=16)
+        st, sts, res, R, ranks, y = batch.solve([gen.init_factor(g.n, r, 2) for g, r in insts], eps_kkt=1e-5)
+        outs.append((R.cpu().numpy().copy(), y.cpu().numpy().copy(), ranks))
+        batch.close()
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+    assert outs[0][2] == outs[1][2]
+
+
+def test_batch_rejects_edge_family():
+    m = _almbm()
+    g = gen.cycle_graph(5)
+    lov = m.Problem.lovasz(5, g.ei, g.ej, precision="f64", r_max=8, lanczos_kmax=5, device=DEV)
+    with pytest.raises(m.AlmBmError):
+        m.Batch([lov], rank_stride=8)

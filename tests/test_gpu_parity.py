@@ -281,7 +281,7 @@ def test_tile_variants_and_grids_agree(prec):
     y = torch.full((g.n,), -0.7, dtype=torch.float64, device=DEV)
     ref = None
     for v in (0, 1, 2):
-        for nb in (8, 64, 384):
+        for nb in (8, 64, 368):
             prob.set_tiles(v, nb)
             f, G, Av = prob.objective_grad(R, y, 1.0)
             out = (f.item(), G.double().cpu().numpy(), Av.cpu().numpy())
