@@ -189,6 +189,7 @@ def main():
     ap.add_argument("--modes", action="store_true", help="also time the other two precisions")
     ap.add_argument("--solve", action="store_true", help="also run the full solve to 1e-4 relative KKT")
     ap.add_argument("--solve-time-limit", type=float, default=600.0)
+    ap.add_argument("--sigma", type=float, default=16.0, help="penalty of the --solve leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true", help="run a 1 GiB copy kernel first (profiling)")
     args = ap.parse_args()
@@ -246,10 +247,11 @@ def main():
 
         ps = almbm.Problem.maxcut(g.n, g.ei, g.ej, g.w, precision=args.precision, r_max=48, lanczos_kmax=60,
                                   device="cuda:0", validate=False)
-        st, res, Rf, yf = ps.solve(gen.init_factor(g.n, args.rank, args.seed), eps_kkt=1e-4,
+        st, res, Rf, yf = ps.solve(gen.init_factor(g.n, args.rank, args.seed), eps_kkt=1e-4, sigma=args.sigma,
                                    time_limit_s=args.solve_time_limit, verbose=1)
-        solve = {"status": int(st), **{k: res[k] for k in ("outer", "inner_total", "rank", "kkt", "pobj", "time_s",
-                                                          "time_lanczos_s", "promoted_at_outer")}}
+        solve = {"status": int(st), "sigma": args.sigma,
+                 **{k: res[k] for k in ("outer", "inner_total", "rank", "kkt", "pinf", "dinf", "gap", "pobj", "time_s",
+                                        "time_lanczos_s", "promoted_at_outer")}}
         ps.close()
 
     cpu = None if args.no_cpu_baseline else cpu_baseline(args.n, args.deg, args.rank, args.seed)

@@ -1115,9 +1115,30 @@ static alm_bm_status inner_solve(alm_bm_problem* p, int r, T* R, const double* y
   return ALM_BM_OK;
 }
 
+// Row width of the factor inside a solve: the next tile width (4, 8, 16, 32, ...)
+// at or above the rank, so that rows stay aligned and every kernel takes its
+// full-tile path; the padding columns hold zeros, which every map of the method
+// keeps at zero, and a rank step fills the first of them.
+static int pad_width(int r, int r_max) {
+  int w = 4;
+  while (w < r) w *= 2;
+  return std::min(w, std::max(r, r_max));
+}
+
+// R (n x r, row stride r) <-> the same factor at row stride w, through the
+// handle's n x r_max scratch.
+template <typename T>
+static alm_bm_status restride(alm_bm_problem* p, T* R, int ss, int nc, int rd, hipStream_t st) {
+  if (ss == rd && nc == rd) return ALM_BM_OK;
+  T* Rt = static_cast<T*>(p->Rtmp);
+  launch_relayout<T>(p->d.n, ss, nc, rd, R, Rt, nullptr, 0.0, st);
+  HIPCHK(hipMemcpyAsync(R, Rt, (size_t)p->d.n * rd * sizeof(T), hipMemcpyDeviceToDevice, st));
+  return ALM_BM_OK;
+}
+
 template <typename T>
 static alm_bm_status solve_impl(alm_bm_problem* p, const alm_bm_options& o, T* R, double* y, hipStream_t st,
-                                int& r, int k_start, int& k_done,
+                                int& r, int& w, int k_start, int& k_done,
                                 bool stop_on_stall, bool& stalled, double t0, double& pinf_prev, double& tol_prev,
                                 alm_bm_result& acc) {
   const auto& d = p->d;
@@ -1135,7 +1156,7 @@ static alm_bm_status solve_impl(alm_bm_problem* p, const alm_bm_options& o, T* R
     const double tol = std::max(o.eps_kkt / 10.0, std::min(o.inner_tol_scale, std::min(pinf_prev, o.inner_tol_decay * tol_prev)));
     tol_prev = tol;
     int iters = 0, flag = 0;
-    STCHK(inner_solve<T>(p, r, R, y, sigma, tol, o, gc, st, iters, flag));
+    STCHK(inner_solve<T>(p, w, R, y, sigma, tol, o, gc, st, iters, flag));
     acc.inner_total += iters;
     // w = y - sigma (A(RR^T) - b) into ybuf (Av is current: the last pass ran at the final R)
     launch_dual(d.m, p->Av, d.b, y, p->ybuf, sigma, p->part_vec, p->sc_solve, p->bnorm, nullptr, st);
@@ -1156,14 +1177,20 @@ static alm_bm_status solve_impl(alm_bm_problem* p, const alm_bm_options& o, T* R
       if (d.cons_kind != ALM_BM_CONS_DIAG) q4 += d.trace_coef * d.trace_coef;
       if (q4 > 0.0) {
         const double s = std::max(0.0, -lo.theta / (sigma * q4));
-        T* Rt = static_cast<T*>(p->Rtmp);
-        launch_relayout<T>(n, r, r + 1, R, Rt, p->lv, std::sqrt(s), st);
-        HIPCHK(hipMemcpyAsync(R, Rt, (size_t)n * (r + 1) * sizeof(T), hipMemcpyDeviceToDevice, st));
+        if (r + 1 <= w) {
+          launch_set_column<T>(n, w, r, R, p->lv, std::sqrt(s), st);
+        } else {
+          const int w2 = pad_width(r + 1, d.r_max);
+          T* Rt = static_cast<T*>(p->Rtmp);
+          launch_relayout<T>(n, w, r, w2, R, Rt, p->lv, std::sqrt(s), st);
+          HIPCHK(hipMemcpyAsync(R, Rt, (size_t)n * w2 * sizeof(T), hipMemcpyDeviceToDevice, st));
+          w = w2;
+          gc.reset();
+        }
         r += 1;
-        gc.reset();
         expanded = true;
         acc.expansions += 1;
-        enqueue_objgrad<T>(p, r, R, y, sigma, nullptr, p->Av, p->sc_api, 0, nullptr, st);
+        enqueue_objgrad<T>(p, w, R, y, sigma, nullptr, p->Av, p->sc_api, 0, nullptr, st);
         launch_dual(d.m, p->Av, d.b, y, p->ybuf, sigma, p->part_vec, p->sc_solve, p->bnorm, nullptr, st);
       }
     }
@@ -1178,7 +1205,7 @@ static alm_bm_status solve_impl(alm_bm_problem* p, const alm_bm_options& o, T* R
       lam = l2.theta;
     }
     KktVals kv{};
-    STCHK(kkt_eval<T>(p, r, R, y, lam, kv, st));
+    STCHK(kkt_eval<T>(p, w, R, y, lam, kv, st));
     if (p->sc_host->numeric_error) return fail(ALM_BM_ERR_NUMERIC, "solve: NaN/Inf in objective or step");
     HIPCHK(hipMemcpyAsync(p->sc_host, p->sc_solve, sizeof(DevScalars), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
@@ -1197,8 +1224,9 @@ static alm_bm_status solve_impl(alm_bm_problem* p, const alm_bm_options& o, T* R
     k_done = k + 1;
     if (o.verbose)
       std::fprintf(stderr,
-                   "[almbm] k=%d inner=%d flag=%d r=%d theta=%.3e pinf=%.3e dinf=%.3e gap=%.3e pobj=%.10e t=%.2fs\n",
-                   k, iters, flag, r, lo.theta, kv.pinf, kv.dinf, kv.gap, kv.pobj, now_s() - t0);
+                   "[almbm] k=%d inner=%d flag=%d r=%d theta=%.3e lanczos=%d pinf=%.3e dinf=%.3e gap=%.3e "
+                   "pobj=%.10e t=%.2fs\n",
+                   k, iters, flag, r, lo.theta, lo.iters, kv.pinf, kv.dinf, kv.gap, kv.pobj, now_s() - t0);
     if (kv.kkt <= o.eps_kkt) return ALM_BM_OK;
     if (o.time_limit_s > 0.0 && now_s() - t0 > o.time_limit_s) return ALM_BM_NOT_CONVERGED;
     if (stop_on_stall) {
@@ -1258,15 +1286,16 @@ extern "C" alm_bm_status alm_bm_solve(alm_bm_problem* p, const alm_bm_options* o
   alm_bm_result acc{};
   acc.promoted_at_outer = -1;
   int r = *r_io;
+  int w = pad_width(r, p->d.r_max);
   int k_done = 0;
   double pinf_prev = INFINITY, tol_prev = INFINITY;
   bool stalled = false;
   alm_bm_status s;
   if (p->d.precision == ALM_BM_BF16 && o.bf16_promote) {
-    s = solve_impl<bf16>(p, o, static_cast<bf16*>(R), y, st, r, 0, k_done, true, stalled, t0, pinf_prev, tol_prev,
-                         acc);
-    if (s < 0) return s;
-    if (stalled) {
+    bf16* Rb = static_cast<bf16*>(R);
+    STCHK(restride<bf16>(p, Rb, r, r, w, st));
+    s = solve_impl<bf16>(p, o, Rb, y, st, r, w, 0, k_done, true, stalled, t0, pinf_prev, tol_prev, acc);
+    if (s >= 0 && stalled) {
       // precision ladder: continue with float storage (the float cost copy is resident)
       const long n = p->d.n;
       const size_t bytes = (size_t)n * p->d.r_max * sizeof(float);
@@ -1275,26 +1304,35 @@ extern "C" alm_bm_status alm_bm_solve(alm_bm_problem* p, const alm_bm_options* o
         STCHK(dalloc(p, &p->G32, bytes));
         STCHK(dalloc(p, &p->Rt32, bytes));
       }
-      launch_convert<bf16, float>((long)n * r, static_cast<const bf16*>(R), static_cast<float*>(p->R32), st);
+      float* Rf = static_cast<float*>(p->R32);
+      launch_convert<bf16, float>((long)n * w, Rb, Rf, st);
       void* Gsave = p->G;
       void* Rtsave = p->Rtmp;
       p->G = p->G32;
       p->Rtmp = p->Rt32;
       const double tp = now_s();
       acc.promoted_at_outer = k_done;
-      s = solve_impl<float>(p, o, static_cast<float*>(p->R32), y, st, r, k_done, k_done, false, stalled, t0,
-                            pinf_prev, tol_prev, acc);
+      s = solve_impl<float>(p, o, Rf, y, st, r, w, k_done, k_done, false, stalled, t0, pinf_prev, tol_prev, acc);
+      alm_bm_status s2 = restride<float>(p, Rf, w, r, r, st);
       p->G = Gsave;
       p->Rtmp = Rtsave;
       acc.time_promoted_s = now_s() - tp;
-      launch_convert<float, bf16>((long)n * r, static_cast<const float*>(p->R32), static_cast<bf16*>(R), st);
+      STCHK(s2);
+      launch_convert<float, bf16>((long)n * r, Rf, Rb, st);
       HIPCHK(hipStreamSynchronize(st));
+      if (s < 0) return s;
+    } else {
+      STCHK(restride<bf16>(p, Rb, w, r, r, st));
       if (s < 0) return s;
     }
   } else {
     s = with_storage(p->d.precision, [&]<typename T>() {
-      return solve_impl<T>(p, o, static_cast<T*>(R), y, st, r, 0, k_done, false, stalled, t0, pinf_prev, tol_prev,
-                           acc);
+      T* Rt = static_cast<T*>(R);
+      alm_bm_status s1 = restride<T>(p, Rt, r, r, w, st);
+      if (s1 < 0) return s1;
+      s1 = solve_impl<T>(p, o, Rt, y, st, r, w, 0, k_done, false, stalled, t0, pinf_prev, tol_prev, acc);
+      const alm_bm_status s2 = restride<T>(p, Rt, w, r, r, st);
+      return s1 < 0 ? s1 : (s2 < 0 ? s2 : s1);
     });
     if (s < 0) return s;
   }

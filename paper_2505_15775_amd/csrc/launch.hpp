@@ -68,7 +68,10 @@ void launch_dual(long m, const double* Av, const double* b, const double* y_in, 
                  double* part, DevScalars* sc, double bnorm, double* pinf_out, hipStream_t st);
 void launch_inner_reset(DevScalars* sc, double tol, int max_inner, int step_rule, double eta, hipStream_t st);
 template <typename T>
-void launch_relayout(long n, int rs, int rd, const T* src, T* dst, const double* v, double scale, hipStream_t st);
+void launch_set_column(long n, int rs, int c, T* R, const double* v, double scale, hipStream_t st);
+template <typename T>
+void launch_relayout(long n, int ss, int nc, int rd, const T* src, T* dst, const double* v, double scale,
+                     hipStream_t st);
 template <typename S, typename D>
 void launch_convert(long len, const S* src, D* dst, hipStream_t st);
 

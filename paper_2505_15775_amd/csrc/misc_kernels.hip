@@ -215,19 +215,29 @@ k_fill_column(long n, int rs, T* __restrict__ R, const double* __restrict__ v, c
     R[i * rs + c] = from_acc<T>(static_cast<typename Acc<T>::type>(s * v[i]));
 }
 
-// Copy with change of row stride: dst (n x rd) <- src (n x rs) for the first
-// min(rs, rd) columns; column `rs` of dst (when rd > rs) gets scale * v[i].
+// R[:, c] <- scale * v (row stride rs), one instance.
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
-k_relayout(long n, int rs, int rd, const T* __restrict__ src, T* __restrict__ dst, const double* __restrict__ v,
-           double scale) {
+k_set_column(long n, int rs, int c, T* __restrict__ R, const double* __restrict__ v, double scale) {
+  const long stride = (long)gridDim.x * kBlock;
+  for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride)
+    R[i * rs + c] = from_acc<T>(static_cast<typename Acc<T>::type>(scale * v[i]));
+}
+
+// Copy with change of row stride: dst (n x rd) gets the first nc columns of src
+// (row stride ss); column nc of dst (when nc < rd and v is given) gets
+// scale * v[i]; the remaining columns are zero.
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_relayout(long n, int ss, int nc, int rd, const T* __restrict__ src, T* __restrict__ dst,
+           const double* __restrict__ v, double scale) {
   const long len = n * rd;
   const long stride = (long)gridDim.x * kBlock;
   for (long idx = (long)blockIdx.x * kBlock + threadIdx.x; idx < len; idx += stride) {
     const long i = idx / rd;
     const int c = (int)(idx - i * rd);
-    if (c < rs) dst[idx] = src[i * rs + c];
-    else if (c == rs && v) dst[idx] = from_acc<T>(static_cast<typename Acc<T>::type>(scale * v[i]));
+    if (c < nc) dst[idx] = src[i * ss + c];
+    else if (c == nc && v) dst[idx] = from_acc<T>(static_cast<typename Acc<T>::type>(scale * v[i]));
     else dst[idx] = from_acc<T>(typename Acc<T>::type(0));
   }
 }
@@ -311,12 +321,23 @@ template void launch_fill_column<float>(long, int, float*, const double*, const 
 template void launch_fill_column<bf16>(long, int, bf16*, const double*, const int32_t*, const double*,
                                        const BlockTab&, int, hipStream_t);
 template <typename T>
-void launch_relayout(long n, int rs, int rd, const T* src, T* dst, const double* v, double scale, hipStream_t st) {
-  hipLaunchKernelGGL((k_relayout<T>), dim3(elem_blocks(n * rd)), dim3(kBlock), 0, st, n, rs, rd, src, dst, v, scale);
+void launch_set_column(long n, int rs, int c, T* R, const double* v, double scale, hipStream_t st) {
+  hipLaunchKernelGGL((k_set_column<T>), dim3(elem_blocks(n)), dim3(kBlock), 0, st, n, rs, c, R, v, scale);
 }
-template void launch_relayout<double>(long, int, int, const double*, double*, const double*, double, hipStream_t);
-template void launch_relayout<float>(long, int, int, const float*, float*, const double*, double, hipStream_t);
-template void launch_relayout<bf16>(long, int, int, const bf16*, bf16*, const double*, double, hipStream_t);
+template void launch_set_column<double>(long, int, int, double*, const double*, double, hipStream_t);
+template void launch_set_column<float>(long, int, int, float*, const double*, double, hipStream_t);
+template void launch_set_column<bf16>(long, int, int, bf16*, const double*, double, hipStream_t);
+
+template <typename T>
+void launch_relayout(long n, int ss, int nc, int rd, const T* src, T* dst, const double* v, double scale,
+                     hipStream_t st) {
+  hipLaunchKernelGGL((k_relayout<T>), dim3(elem_blocks(n * rd)), dim3(kBlock), 0, st, n, ss, nc, rd, src, dst, v,
+                     scale);
+}
+template void launch_relayout<double>(long, int, int, int, const double*, double*, const double*, double,
+                                      hipStream_t);
+template void launch_relayout<float>(long, int, int, int, const float*, float*, const double*, double, hipStream_t);
+template void launch_relayout<bf16>(long, int, int, int, const bf16*, bf16*, const double*, double, hipStream_t);
 
 template <typename S, typename D>
 void launch_convert(long len, const S* src, D* dst, hipStream_t st) {
