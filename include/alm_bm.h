@@ -173,6 +173,15 @@ alm_bm_status alm_bm_objective_grad(alm_bm_problem* prob, int32_t r, const void*
                                     const double* y, double sigma, double* f, void* G,
                                     double* Av, hipStream_t stream);
 
+/* Cost product P = C X with C = S + Diag(d) (the sparse product that dominates
+ * the gradient evaluation and the exact line search, Sec. 6): X device n x r in
+ * the storage precision, P device n x r in the arithmetic precision (double for
+ * F64, float for F32 and BF16), row-major, caller-owned; X and P must not
+ * overlap.  xpx (device, 1 double, nullable) receives <X, C X>.  Requires
+ * j_coef = 0 (ALM_BM_ERR_UNSUPPORTED otherwise).                                */
+alm_bm_status alm_bm_cost_apply(alm_bm_problem* prob, int32_t r, const void* X, void* P,
+                                double* xpx, hipStream_t stream);
+
 /* Coefficients k[0..4] of phi(t) = Lbar_sigma(R - t G, y) = sum_k k[k] t^k
  * (device, 5 doubles) and the exact minimiser t* over t >= 0 (device, 1 double,
  * nullable; ties to the smallest t; 0 when phi is unbounded below).  G is any

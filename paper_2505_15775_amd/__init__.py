@@ -187,6 +187,18 @@ class Problem:
                                         _ptr(Av), _stream(stream)), "objective_grad")
         return f, G, Av
 
+    def cost_apply(self, X, P=None, want_xpx=False, stream=None):
+        """P = C X (arithmetic precision: float64 for f64, float32 otherwise) and,
+        if asked, <X, C X> as a device scalar."""
+        self._check_R(X)
+        if P is None:
+            pdt = torch.float64 if self.precision == "f64" else torch.float32
+            P = torch.empty(X.shape, dtype=pdt, device=self.device)
+        xpx = torch.empty(1, dtype=torch.float64, device=self.device) if want_xpx else None
+        check(lib.alm_bm_cost_apply(self._h, X.shape[1], _ptr(X), _ptr(P), _ptr(xpx), _stream(stream)),
+              "cost_apply")
+        return (P, xpx) if want_xpx else P
+
     def line_search(self, R, G, y, sigma, stream=None):
         """(coeffs[5], t*) of phi(t) = Lbar(R - tG)."""
         self._check_R(R)

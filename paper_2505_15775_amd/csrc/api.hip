@@ -551,6 +551,22 @@ extern "C" alm_bm_status alm_bm_objective_grad(alm_bm_problem* p, int32_t r, con
   return ALM_BM_OK;
 }
 
+extern "C" alm_bm_status alm_bm_cost_apply(alm_bm_problem* p, int32_t r, const void* X, void* P, double* xpx,
+                                           hipStream_t st) {
+  if (!p || !X || !P) return fail(ALM_BM_ERR_INVALID_ARG, "cost_apply: null argument");
+  STCHK(check_r(p, r));
+  if (p->d.j_coef != 0.0) return fail(ALM_BM_ERR_UNSUPPORTED, "cost_apply: cost with a -J term");
+  with_storage(p->d.precision, [&]<typename T>() {
+    using V = typename Acc<T>::type;
+    launch_quadq_diag<T>(cost_of<T>(p), r, p->variant, static_cast<const T*>(X), static_cast<V*>(P), p->part_c2,
+                         nullptr, p->tab, p->nblk, st);
+    if (xpx) launch_fin_sum(p->part_c2, p->nblk, xpx, 0, st);
+    return 0;
+  });
+  HIPCHK(hipGetLastError());
+  return ALM_BM_OK;
+}
+
 extern "C" alm_bm_status alm_bm_line_search(alm_bm_problem* p, int32_t r, const void* R, const void* G,
                                             const double* y, double sigma, double* coeffs, double* t_star,
                                             hipStream_t st) {

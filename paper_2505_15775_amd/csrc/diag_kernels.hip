@@ -123,8 +123,7 @@ k_quadq_diag(Cost<typename Acc<T>::type> C, int r, const T* __restrict__ G, type
              double* __restrict__ part, const DevScalars* __restrict__ sc_base, BlockTab tab) {
   using V = typename Acc<T>::type;
   const Rows ch = rows_of(C.n, tab);
-  const DevScalars* sc = sc_base + ch.inst;
-  if (sc->flag) return;
+  if (sc_base && sc_base[ch.inst].flag) return;
   constexpr int RPB = kBlock / LPR;
   const int lane = threadIdx.x % LPR;
   const int slot = threadIdx.x / LPR;

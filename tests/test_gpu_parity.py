@@ -73,6 +73,46 @@ def test_objective_grad_diag_f64(name, r, ell):
     assert rel(Av.cpu(), a_o) <= 1e-10
 
 
+@pytest.mark.parametrize("name,r,ell", DIAG_CASES)
+def test_cost_apply_f64(name, r, ell):
+    """P = C X and <X, C X> against the oracle's sparse product."""
+    g = _case_graph(name)
+    prob = almbm().Problem.maxcut(g.n, g.ei, g.ej, g.w, precision="f64", r_max=max(r, 8), lanczos_kmax=0,
+                                  device=DEV, ell=ell)
+    po = oracle.maxcut_sdp(g)
+    X = np.random.default_rng(11).standard_normal((g.n, r))
+    P, xpx = prob.cost_apply(prob.factor(X), want_xpx=True)
+    torch.cuda.synchronize()
+    P_o = oracle.cost_apply(po, X)
+    assert rel(P.cpu(), P_o) <= 1e-10
+    x_o = float(np.sum(X * P_o))
+    assert abs(xpx.item() - x_o) <= 1e-10 * max(1.0, float(np.sum(np.abs(X * P_o))))
+
+
+@pytest.mark.parametrize("prec,bound", [("f32", 1e-6), ("bf16", 1e-2)])
+def test_cost_apply_reduced_precision(prec, bound):
+    g = _case_graph("er3001g")
+    prob = almbm().Problem.maxcut(g.n, g.ei, g.ej, g.w, precision=prec, r_max=16, lanczos_kmax=0, device=DEV)
+    X = np.random.default_rng(12).standard_normal((g.n, 16))
+    Xs = prob.factor(X)
+    P = prob.cost_apply(Xs)
+    torch.cuda.synchronize()
+    assert P.dtype == torch.float32
+    # against the oracle on the stored (rounded) factor: only float accumulation differs
+    P_o = oracle.cost_apply(oracle.maxcut_sdp(g), Xs.double().cpu().numpy())
+    err = rel(P.cpu(), P_o)
+    print(f"cost_apply {prec}: rel err vs FP64 product of the stored factor {err:.2e}")
+    assert err <= bound
+
+
+def test_cost_apply_rejects_j_term():
+    m = almbm()
+    g = gen.cycle_graph(5)
+    lov = m.Problem.lovasz(5, g.ei, g.ej, precision="f64", r_max=4, lanczos_kmax=0, device=DEV)
+    with pytest.raises(m.AlmBmError):
+        lov.cost_apply(lov.factor(np.ones((5, 2))))
+
+
 @pytest.mark.parametrize("name,r", [("er2000", 8), ("er3001g", 16), ("torus", 5)])
 def test_line_search_diag_f64(name, r):
     g = _case_graph(name)
