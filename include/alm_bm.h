@@ -121,7 +121,7 @@ typedef struct {
   alm_bm_rank_policy rank_policy; /* ADAPT p = 1 rank step of Alg. 1                 */
   int32_t r_cap;             /* 0 -> min(r_max, floor((sqrt(8m+1)-1)/2))              */
   double tau_rank;           /* <= 0 -> eps_kkt (1 + ||C||_F)                        */
-  int32_t expand_needs_inner;/* 1      expand only after an inner solve converged     */
+  int32_t expand_needs_inner;/* 0      1: expand only after an inner solve converged  */
   double inner_tol_scale;    /* 0.1    tol_k = max(eps/10, min(0.1, pinf, kappa tol)) */
   double inner_tol_decay;    /* 0.7    kappa                                           */
   int32_t lanczos_kmax;      /* 0 -> the handle's lanczos_kmax                        */

@@ -22,7 +22,9 @@ solve options):
   exact minimiser over s >= 0 of L(RR^T + s v v^T, y), whose expansion is
   L(X) + s theta + (sigma/2) s^2 ||A(v v^T)||^2; expand iff theta < -tau_rank
   (default eps (1 + ||C||_F)) and r < r_cap = min(r_max, Barvinok-Pataki bound
-  floor((sqrt(8m+1)-1)/2) of Sec. 3.3);
+  floor((sqrt(8m+1)-1)/2) of Sec. 3.3), whether or not the inner solve met its
+  tolerance, as Alg. 1 does (an optional gate waits for inner convergence; it
+  stalls the rank, hence the dual infeasibility, once max_inner binds);
 * fixed penalty sigma.
 
 Pins: the quartic coefficients against direct evaluation of the objective at
@@ -55,7 +57,7 @@ class SolveOptions:
     tau_rank: Optional[float] = None
     inner_tol_scale: float = 0.1   # the 0.1 in min(0.1, pinf_prev, kappa tol_prev)
     inner_tol_decay: float = 0.7   # kappa
-    expand_needs_inner: bool = True  # expand only after an inner solve met its tolerance
+    expand_needs_inner: bool = False  # True: expand only after an inner solve met its tolerance
 
 
 def line_search_coeffs(p, R, G, y, sigma, P=None, a=None):

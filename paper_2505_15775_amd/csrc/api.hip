@@ -231,7 +231,7 @@ extern "C" void alm_bm_default_options(alm_bm_options* o) {
   o->rank_policy = ALM_BM_RANK_ADAPT;
   o->r_cap = 0;
   o->tau_rank = 0.0;
-  o->expand_needs_inner = 1;
+  o->expand_needs_inner = 0;
   o->inner_tol_scale = 0.1;
   o->inner_tol_decay = 0.7;
   o->lanczos_kmax = 0;

@@ -172,6 +172,8 @@ def solve_warm(prob, model, r_max=None, fallback_outer=5, seed=1, **opts):
     start.  Returns (status, result, R, y, info)."""
     import gen
 
+    opts = dict(opts)
+    max_outer = int(opts.pop("max_outer", 1000))
     t0 = time.perf_counter()
     F = features(prob)
     y0 = model.predict_y0(prob, F)
@@ -182,11 +184,11 @@ def solve_warm(prob, model, r_max=None, fallback_outer=5, seed=1, **opts):
     try:
         theta, _, _, _ = prob.lanczos_min_eig(y0, max_iter=min(40, prob.desc.lanczos_kmax), tol=0.0, want_vector=False)
         k0 = prob.kkt(prob.factor(torch.from_numpy(R0)), y0, theta)["kkt"]
-        st, res, R, y = prob.solve(R0, y0, max_outer=fallback_outer, **opts)
+        st, res, R, y = prob.solve(R0, y0, max_outer=min(fallback_outer, max_outer), **opts)
         if st != 0 and not (res["kkt"] < k0):
             raise FloatingPointError(f"warm start not improving: kkt {res['kkt']:.3e} vs start {k0:.3e}")
-        if st != 0:
-            st, res2, R, y = prob.solve(R, y, **opts)
+        if st != 0 and res["outer"] < max_outer:
+            st, res2, R, y = prob.solve(R, y, max_outer=max_outer - res["outer"], **opts)
             res2["outer"] += res["outer"]
             res2["inner_total"] += res["inner_total"]
             res2["time_s"] += res["time_s"]
@@ -194,7 +196,7 @@ def solve_warm(prob, model, r_max=None, fallback_outer=5, seed=1, **opts):
     except (FloatingPointError, _lib.AlmBmError) as e:
         info["fallback"] = True
         info["reason"] = str(e)
-        st, res, R, y = prob.solve(gen.init_factor(prob.n, 16, seed), None, **opts)
+        st, res, R, y = prob.solve(gen.init_factor(prob.n, 16, seed), None, max_outer=max_outer, **opts)
     info["total_s"] = time.perf_counter() - t0
     return st, res, R, y, info
 
@@ -218,14 +220,14 @@ def training_graphs(count, seed, n_lo=1e4, n_hi=1e5, deg_lo=4.0, deg_hi=16.0):
     return out
 
 
-def generate_training_set(graphs, eps=1e-5, r0=16, r_max=64, device="cuda", log=None):
+def generate_training_set(graphs, eps=1e-5, r0=16, r_max=64, sigma=16.0, device="cuda", log=None):
     import gen
 
     feats, targets, pools, ns, ranks = [], [], [], [], []
     for k, g in enumerate(graphs):
         prob = Problem.maxcut(g.n, g.ei, g.ej, g.w, precision="f64", r_max=r_max, lanczos_kmax=60, device=device,
                               validate=False)
-        st, res, R, y = prob.solve(gen.init_factor(g.n, r0, 1), eps_kkt=eps, max_outer=300)
+        st, res, R, y = prob.solve(gen.init_factor(g.n, r0, 1), eps_kkt=eps, sigma=sigma, max_outer=300)
         if st != 0:
             if log:
                 log(f"[warmstart] graph {k} n={g.n}: not converged (kkt {res['kkt']:.2e}), skipped")
@@ -252,6 +254,7 @@ def main():
     t.add_argument("--seed", type=int, default=6)
     t.add_argument("--steps", type=int, default=600)
     t.add_argument("--hidden", type=int, default=32)
+    t.add_argument("--sigma", type=float, default=16.0, help="penalty of the labelling solves")
     t.add_argument("--out", default=MODEL_PATH)
     args = ap.parse_args()
 
@@ -261,7 +264,7 @@ def main():
     graphs = training_graphs(args.count, args.seed)
     n_hold = max(1, args.count // 10)
     t0 = time.time()
-    feats, targets, pools, ns, ranks = generate_training_set(graphs[n_hold:], log=log)
+    feats, targets, pools, ns, ranks = generate_training_set(graphs[n_hold:], sigma=args.sigma, log=log)
     log(f"[warmstart] {len(feats)} labelled solves in {time.time() - t0:.1f}s")
     X = torch.cat(feats).contiguous()
     T = torch.cat(targets).contiguous()
@@ -269,7 +272,7 @@ def main():
     hist = model.fit(X, T, steps=args.steps, log=log)
     model.fit_rank(pools, ns, ranks)
     model.save(args.out, meta={"count": args.count, "seed": args.seed, "holdout": n_hold, "vertices": int(X.shape[0]),
-                               "loss": hist[-1][1]})
+                               "loss": hist[-1][1], "sigma": args.sigma})
     log(f"[warmstart] saved {args.out}")
 
 

@@ -128,8 +128,8 @@ def test_trained_warm_start_beats_default_start_on_held_out_graphs():
     t_d = t_w = 0.0
     for g in graphs:
         prob = _prob(g)
-        st, rd, _, _ = prob.solve(gen.init_factor(g.n, 16, 1), eps_kkt=1e-5, max_outer=300)
-        stw, rw, _, _, info = ws.solve_warm(prob, model, eps_kkt=1e-5, max_outer=300)
+        st, rd, _, _ = prob.solve(gen.init_factor(g.n, 16, 1), eps_kkt=1e-5, sigma=16.0, max_outer=300)
+        stw, rw, _, _, info = ws.solve_warm(prob, model, eps_kkt=1e-5, sigma=16.0, max_outer=300)
         print(f"n={g.n}: default outer {rd['outer']} ({rd['time_s']:.2f}s) warm outer {rw['outer']} "
               f"({info['total_s']:.2f}s, r0 {info['r0']}, fallback {info['fallback']}) "
               f"pobj {rd['pobj']:.8e} vs {rw['pobj']:.8e}")
