@@ -159,6 +159,50 @@ def per_outer_rows(prob, y, steps):
             "lanczos_ms_total": 1000.0 * tl, "lanczos_ms_per_step": 1000.0 * tl / max(1, iters)}
 
 
+def batch_leg(count, eps, sigma, prec, seed=3):
+    """Uneven MaxCut instances (n log-uniform in [1e3, 2e5], average degree
+    uniform in [4, 32], +-1 weights, r in {8, 16}) solved together by one
+    batched solve, then one by one with the same options."""
+    import torch
+
+    import gen
+    import paper_2505_15775_amd as almbm
+
+    insts = gen.batch_instances(count, seed)
+    sum_n = sum(g.n for g, _ in insts)
+    sum_nnz = sum(2 * g.m_edges for g, _ in insts)
+    log(f"[bench] batch: {count} instances, sum n {sum_n}, sum nnz {sum_nnz}")
+    probs = [almbm.Problem.maxcut(g.n, g.ei, g.ej, g.w, precision=prec, r_max=64, lanczos_kmax=40, device="cuda:0",
+                                  validate=False) for g, _ in insts]
+    batch = almbm.Batch(probs, rank_stride=64)
+    factors = [gen.init_factor(g.n, r, 1) for g, r in insts]
+    opts = dict(eps_kkt=eps, sigma=sigma, max_outer=300)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st, sts, res, _, ranks, _ = batch.solve(factors, **opts)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    log(f"[bench] batch: batched solve {tb:.1f}s, {sum(s == 0 for s in sts)}/{count} converged")
+    t0 = time.perf_counter()
+    nconv = 0
+    worst = 0.0
+    for q, p in enumerate(probs):
+        s1, r1, _, _ = p.solve(factors[q], **opts)
+        nconv += int(s1 == 0)
+        worst = max(worst, abs(r1["pobj"] - res[q]["pobj"]) / abs(r1["pobj"]))
+    torch.cuda.synchronize()
+    tl = time.perf_counter() - t0
+    log(f"[bench] batch: per-instance loop {tl:.1f}s, {nconv}/{count} converged")
+    batch.close()
+    for p in probs:
+        p.close()
+    return {"instances": count, "sum_n": sum_n, "sum_nnz": sum_nnz, "precision": prec, "eps_kkt": eps,
+            "sigma": sigma, "batched_s": round(tb, 2), "batched_converged": int(sum(s == 0 for s in sts)),
+            "loop_s": round(tl, 2), "loop_converged": nconv, "speedup": round(tl / tb, 3),
+            "max_outer_batched": int(max(x["outer"] for x in res)),
+            "max_rel_objective_diff": worst}
+
+
 def calibrate_copy(nbytes=1 << 30):
     """A plain elementwise copy of known size (read nbytes, write nbytes), for
     scaling the HBM byte counters of a profiled run."""
@@ -212,8 +256,12 @@ def main():
     ap.add_argument("--seed", type=int, default=5)
     ap.add_argument("--modes", action="store_true", help="also time the other two precisions")
     ap.add_argument("--solve", action="store_true", help="also run the full solve to 1e-4 relative KKT")
+    ap.add_argument("--solve-f64", action="store_true", help="also the FP64 solve from the default start")
+    ap.add_argument("--warm", action="store_true", help="also the solve from the learned warm start")
     ap.add_argument("--solve-time-limit", type=float, default=600.0)
     ap.add_argument("--sigma", type=float, default=16.0, help="penalty of the --solve leg")
+    ap.add_argument("--batch", type=int, default=0, help="also the batched solve of this many instances vs a loop")
+    ap.add_argument("--batch-eps", type=float, default=1e-4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true", help="run a 1 GiB copy kernel first (profiling)")
     args = ap.parse_args()
@@ -270,21 +318,43 @@ def main():
                             "algorithmic_bytes_per_launch": main_out["objgrad_bytes"],
                             "launch_ms": round(main_out["objgrad_ms"], 4), "traffic": traffic_og}}
 
-    solve = None
-    if args.solve:
+    solves = {}
+    if args.solve or args.solve_f64 or args.warm:
         prob.close()
         del prob
         torch.cuda.empty_cache()
         import paper_2505_15775_amd as almbm
+        from paper_2505_15775_amd import warmstart
 
-        ps = almbm.Problem.maxcut(g.n, g.ei, g.ej, g.w, precision=args.precision, r_max=48, lanczos_kmax=60,
-                                  device="cuda:0", validate=False)
-        st, res, Rf, yf = ps.solve(gen.init_factor(g.n, args.rank, args.seed), eps_kkt=1e-4, sigma=args.sigma,
-                                   time_limit_s=args.solve_time_limit, verbose=1)
-        solve = {"status": int(st), "sigma": args.sigma,
-                 **{k: res[k] for k in ("outer", "inner_total", "rank", "kkt", "pinf", "dinf", "gap", "pobj", "time_s",
-                                        "time_lanczos_s", "promoted_at_outer")}}
-        ps.close()
+        keys = ("outer", "inner_total", "rank", "kkt", "pinf", "dinf", "gap", "pobj", "time_s", "time_lanczos_s",
+                "promoted_at_outer")
+        legs = []
+        if args.solve_f64:
+            legs.append(("f64_default_start", "f64", False))
+        if args.solve:
+            legs.append((f"{args.precision}_default_start", args.precision, False))
+        if args.warm:
+            legs.append((f"{args.precision}_learned_start", args.precision, True))
+        for name, pm, warm in legs:
+            log(f"[bench] solve leg {name}")
+            ps = almbm.Problem.maxcut(g.n, g.ei, g.ej, g.w, precision=pm, r_max=64, lanczos_kmax=60,
+                                      device="cuda:0", validate=False)
+            opts = dict(eps_kkt=1e-4, sigma=args.sigma, time_limit_s=args.solve_time_limit, verbose=1)
+            if warm:
+                model = warmstart.WarmStartModel.load(device="cuda:0")
+                st, res, Rf, yf, info = warmstart.solve_warm(ps, model, **opts)
+                extra = {"r0": info["r0"], "fallback": info["fallback"], "predict_s": round(info["predict_s"], 3),
+                         "total_s": round(info["total_s"], 3)}
+            else:
+                st, res, Rf, yf = ps.solve(gen.init_factor(g.n, args.rank, args.seed), **opts)
+                extra = {}
+            solves[name] = {"status": int(st), "sigma": args.sigma, **{k: res[k] for k in keys}, **extra}
+            log(f"[bench] {name}: {solves[name]}")
+            ps.close()
+            del ps
+            torch.cuda.empty_cache()
+
+    batch = batch_leg(args.batch, args.batch_eps, args.sigma, "f64") if args.batch > 0 else None
 
     cpu = None if args.no_cpu_baseline else cpu_baseline(args.n, args.deg, args.rank, args.seed)
 
@@ -313,8 +383,10 @@ def main():
     if modes:
         line["modes"] = {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                          for k, v in modes.items()}
-    if solve is not None:
-        line["solve"] = solve
+    if solves:
+        line["solve_to_1e-4_kkt"] = solves
+    if batch is not None:
+        line["batched_solve"] = batch
     print(json.dumps(line), flush=True)
 
 
