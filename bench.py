@@ -179,7 +179,7 @@ def batch_leg(count, eps, sigma, prec, seed=3):
     opts = dict(eps_kkt=eps, sigma=sigma, max_outer=300)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    st, sts, res, _, ranks, _ = batch.solve(factors, **opts)
+    st, sts, res, _, ranks, _ = batch.solve(factors, verbose=1, **opts)
     torch.cuda.synchronize()
     tb = time.perf_counter() - t0
     log(f"[bench] batch: batched solve {tb:.1f}s, {sum(s == 0 for s in sts)}/{count} converged")
@@ -190,6 +190,8 @@ def batch_leg(count, eps, sigma, prec, seed=3):
         s1, r1, _, _ = p.solve(factors[q], **opts)
         nconv += int(s1 == 0)
         worst = max(worst, abs(r1["pobj"] - res[q]["pobj"]) / abs(r1["pobj"]))
+        if q % 8 == 0:
+            log(f"[bench] batch loop: instance {q} n={p.n} outer {r1['outer']} {time.perf_counter() - t0:.1f}s")
     torch.cuda.synchronize()
     tl = time.perf_counter() - t0
     log(f"[bench] batch: per-instance loop {tl:.1f}s, {nconv}/{count} converged")
@@ -260,6 +262,7 @@ def main():
     ap.add_argument("--warm", action="store_true", help="also the solve from the learned warm start")
     ap.add_argument("--solve-time-limit", type=float, default=600.0)
     ap.add_argument("--sigma", type=float, default=16.0, help="penalty of the --solve leg")
+    ap.add_argument("--max-inner", type=int, default=500, help="gradient steps per subproblem in the solve legs")
     ap.add_argument("--batch", type=int, default=0, help="also the batched solve of this many instances vs a loop")
     ap.add_argument("--batch-eps", type=float, default=1e-4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -339,7 +342,8 @@ def main():
             log(f"[bench] solve leg {name}")
             ps = almbm.Problem.maxcut(g.n, g.ei, g.ej, g.w, precision=pm, r_max=64, lanczos_kmax=60,
                                       device="cuda:0", validate=False)
-            opts = dict(eps_kkt=1e-4, sigma=args.sigma, time_limit_s=args.solve_time_limit, verbose=1)
+            opts = dict(eps_kkt=1e-4, sigma=args.sigma, max_inner=args.max_inner, time_limit_s=args.solve_time_limit,
+                        verbose=1)
             if warm:
                 model = warmstart.WarmStartModel.load(device="cuda:0")
                 st, res, Rf, yf, info = warmstart.solve_warm(ps, model, **opts)
@@ -348,7 +352,8 @@ def main():
             else:
                 st, res, Rf, yf = ps.solve(gen.init_factor(g.n, args.rank, args.seed), **opts)
                 extra = {}
-            solves[name] = {"status": int(st), "sigma": args.sigma, **{k: res[k] for k in keys}, **extra}
+            solves[name] = {"status": int(st), "sigma": args.sigma, "max_inner": args.max_inner,
+                            **{k: res[k] for k in keys}, **extra}
             log(f"[bench] {name}: {solves[name]}")
             ps.close()
             del ps

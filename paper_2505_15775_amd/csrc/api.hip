@@ -1377,6 +1377,26 @@ struct alm_bm_batch {
   int32_t* col_dev = nullptr;       // count
   double* scale_dev = nullptr;      // count
   double* thetas_dev = nullptr;     // count
+  // Inside a solve every instance keeps its factor at its own padded width
+  // w_q (pad_width of its rank) in its region [off_q rs, (off_q + n_q) rs):
+  // row i at xbase_q + i w_q.  The row kernels run once per distinct width
+  // over the blocks of the active instances of that width (launch tables).
+  static constexpr int kNC = 8;
+  int32_t* c_inst[kNC] = {};
+  int64_t* c_lo[kNC] = {};
+  int64_t* c_hi[kNC] = {};
+  int32_t* c_gid[kNC] = {};
+  int c_nb[kNC] = {};
+  int c_w[kNC] = {};
+  int nclass = 0;
+  int64_t* xbase_dev = nullptr;     // count
+  int64_t* ob_dev = nullptr;        // count: re-layout arguments
+  int32_t* os_dev = nullptr;
+  int64_t* nbase_dev = nullptr;
+  int32_t* ns_dev = nullptr;
+  int32_t* nc_dev = nullptr;
+  std::vector<int32_t> h_iblo, h_ibhi;  // host copy of the block table
+  std::vector<int64_t> h_lo, h_hi;
 };
 
 static alm_bm_status balloc(alm_bm_batch* b, void** out, size_t bytes) {
@@ -1554,6 +1574,22 @@ extern "C" alm_bm_status alm_bm_batch_create(int32_t count, const alm_bm_problem
   p->tab = BlockTab{dbinst, dblo, dbhi, diblo, dibhi};
   p->count = count;
   p->nblk = nb;
+  b->h_iblo = iblo;
+  b->h_ibhi = ibhi;
+  b->h_lo = blo;
+  b->h_hi = bhi;
+  for (int c = 0; c < alm_bm_batch::kNC; ++c) {
+    BK(balloc(b, (void**)&b->c_inst[c], nb * sizeof(int32_t)));
+    BK(balloc(b, (void**)&b->c_lo[c], nb * sizeof(int64_t)));
+    BK(balloc(b, (void**)&b->c_hi[c], nb * sizeof(int64_t)));
+    BK(balloc(b, (void**)&b->c_gid[c], nb * sizeof(int32_t)));
+  }
+  BK(balloc(b, (void**)&b->xbase_dev, count * sizeof(int64_t)));
+  BK(balloc(b, (void**)&b->ob_dev, count * sizeof(int64_t)));
+  BK(balloc(b, (void**)&b->os_dev, count * sizeof(int32_t)));
+  BK(balloc(b, (void**)&b->nbase_dev, count * sizeof(int64_t)));
+  BK(balloc(b, (void**)&b->ns_dev, count * sizeof(int32_t)));
+  BK(balloc(b, (void**)&b->nc_dev, count * sizeof(int32_t)));
   // ---- per-instance workspace sized for the table and the instance count
   const int kp = p->kmax + 1;
   BK(balloc(b, (void**)&p->part, (size_t)nb * (NUM_P + kMaxR) * sizeof(double)));
@@ -1699,6 +1735,105 @@ static alm_bm_status batch_lanczos(alm_bm_batch* b, const double* y, int kmax, c
   return ALM_BM_OK;
 }
 
+// Row offset base of instance q stored at width w inside its region.
+static int64_t batch_xbase(const alm_bm_batch* b, int q, int w) { return b->off[q] * (int64_t)(b->rs - w); }
+
+// Re-lay every instance's factor out from (ob, os) to (nb, ns), keeping its
+// first nc_q columns and zeroing the rest, through the handle's scratch.
+template <typename T>
+static alm_bm_status batch_restride(alm_bm_batch* b, T* R, const std::vector<int64_t>& ob,
+                                    const std::vector<int32_t>& os, const std::vector<int64_t>& nbv,
+                                    const std::vector<int32_t>& ns, const int32_t* nc, hipStream_t st) {
+  alm_bm_problem* p = b->p;
+  const int count = b->count;
+  HIPCHK(hipMemcpyAsync(b->ob_dev, ob.data(), count * sizeof(int64_t), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(b->os_dev, os.data(), count * sizeof(int32_t), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(b->nbase_dev, nbv.data(), count * sizeof(int64_t), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(b->ns_dev, ns.data(), count * sizeof(int32_t), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(b->nc_dev, nc, count * sizeof(int32_t), hipMemcpyHostToDevice, st));
+  T* Rt = static_cast<T*>(p->Rtmp);
+  launch_restride_batch<T>(p->tab, p->nblk, R, Rt, b->ob_dev, b->os_dev, b->nbase_dev, b->ns_dev, b->nc_dev, st);
+  HIPCHK(hipMemcpyAsync(R, Rt, (size_t)p->d.n * b->rs * sizeof(T), hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));  // the host argument vectors may go out of scope
+  HIPCHK(hipGetLastError());
+  return ALM_BM_OK;
+}
+
+// Launch tables of the active instances, one per distinct width, and the
+// per-instance row bases of the current widths.
+static alm_bm_status batch_classes(alm_bm_batch* b, const std::vector<int>& w, const std::vector<int32_t>& active,
+                                   hipStream_t st) {
+  const int count = b->count;
+  std::vector<int> widths;
+  for (int q = 0; q < count; ++q)
+    if (active[q] && std::find(widths.begin(), widths.end(), w[q]) == widths.end()) widths.push_back(w[q]);
+  if ((int)widths.size() > alm_bm_batch::kNC) return fail(ALM_BM_ERR_UNSUPPORTED, "batch: too many width classes");
+  std::sort(widths.begin(), widths.end());
+  std::vector<std::vector<int32_t>> ci(widths.size()), cg(widths.size());
+  std::vector<std::vector<int64_t>> cl(widths.size()), ch(widths.size());
+  for (int q = 0; q < count; ++q) {
+    if (!active[q]) continue;
+    const int c = (int)(std::find(widths.begin(), widths.end(), w[q]) - widths.begin());
+    for (int blk = b->h_iblo[q]; blk < b->h_ibhi[q]; ++blk) {
+      ci[c].push_back(q);
+      cl[c].push_back(b->h_lo[blk]);
+      ch[c].push_back(b->h_hi[blk]);
+      cg[c].push_back(blk);
+    }
+  }
+  b->nclass = (int)widths.size();
+  for (int c = 0; c < b->nclass; ++c) {
+    const size_t k = ci[c].size();
+    b->c_nb[c] = (int)k;
+    b->c_w[c] = widths[c];
+    HIPCHK(hipMemcpyAsync(b->c_inst[c], ci[c].data(), k * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(b->c_lo[c], cl[c].data(), k * sizeof(int64_t), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(b->c_hi[c], ch[c].data(), k * sizeof(int64_t), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(b->c_gid[c], cg[c].data(), k * sizeof(int32_t), hipMemcpyHostToDevice, st));
+  }
+  std::vector<int64_t> xb(count);
+  for (int q = 0; q < count; ++q) xb[q] = batch_xbase(b, q, w[q]);
+  HIPCHK(hipMemcpyAsync(b->xbase_dev, xb.data(), count * sizeof(int64_t), hipMemcpyHostToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return ALM_BM_OK;
+}
+
+static BlockTab batch_class_tab(const alm_bm_batch* b, int c) {
+  const BlockTab& f = b->p->tab;
+  return BlockTab{b->c_inst[c], b->c_lo[c], b->c_hi[c], f.iblo, f.ibhi, b->c_gid[c], b->xbase_dev};
+}
+
+// One inner step of every running instance: each row kernel once per width.
+template <typename T>
+static void batch_enqueue_step(alm_bm_batch* b, T* R, const double* y, double sigma, T* G, int refresh,
+                               hipStream_t st) {
+  using V = typename Acc<T>::type;
+  alm_bm_problem* p = b->p;
+  const auto& d = p->d;
+  DevScalars* sc = p->sc_solve;
+  V* Q = static_cast<V*>(p->Qbuf);
+  for (int c = 0; c < b->nclass; ++c)
+    launch_upd_eval_diag<T>(d.n, b->c_w[c], 0, R, G, Q, y, d.b, sigma, p->Av, p->part, sc, refresh,
+                            batch_class_tab(b, c), b->c_nb[c], st);
+  for (int c = 0; c < b->nclass; ++c)
+    launch_objgrad_diag<T>(cost_of<T>(p), b->c_w[c], 0, R, y, d.b, sigma, G, p->Av, p->part, sc, refresh,
+                           batch_class_tab(b, c), b->c_nb[c], st);
+  launch_fin_objgrad(p->part, p->nblk, sc, sigma, 1, nullptr, st, p->tab, p->count);
+  for (int c = 0; c < b->nclass; ++c)
+    launch_quadq_diag<T>(cost_of<T>(p), b->c_w[c], 0, G, Q, p->part_c2, sc, batch_class_tab(b, c), b->c_nb[c], st);
+  launch_fin_step(p->part_c2, p->nblk, 1, sc, sigma, 0.0, 1, nullptr, nullptr, st, p->tab, p->count);
+}
+
+// Objective pass (API mode, into sc_api) over the active instances.
+template <typename T>
+static void batch_enqueue_objgrad(alm_bm_batch* b, const T* R, const double* y, double sigma, hipStream_t st) {
+  alm_bm_problem* p = b->p;
+  for (int c = 0; c < b->nclass; ++c)
+    launch_objgrad_diag<T>(cost_of<T>(p), b->c_w[c], 0, R, y, p->d.b, sigma, nullptr, p->Av, p->part, p->sc_api, 0,
+                           batch_class_tab(b, c), b->c_nb[c], st);
+  launch_fin_objgrad(p->part, p->nblk, p->sc_api, sigma, 0, nullptr, st, p->tab, p->count);
+}
+
 template <typename T>
 static alm_bm_status batch_solve_impl(alm_bm_batch* b, const alm_bm_options& o, T* R, int32_t* r, double* y,
                                       alm_bm_result* results, int32_t* status, hipStream_t st) {
@@ -1727,11 +1862,17 @@ static alm_bm_status batch_solve_impl(alm_bm_batch* b, const alm_bm_options& o, 
     if (r[q] < 1 || r[q] > b->rs) return fail(ALM_BM_ERR_INVALID_ARG, "batch_solve: r[q] must be in 1..rank_stride");
   }
   T* G = static_cast<T*>(p->G);
+  // per-instance widths: pack from the caller's layout (row i at i * rs)
+  std::vector<int> w(count);
+  std::vector<int64_t> xb(count), zero64(count, 0);
+  std::vector<int32_t> rsv(count, b->rs), wv(count);
+  for (int q = 0; q < count; ++q) {
+    w[q] = pad_width(r[q], b->rs);
+    wv[q] = w[q];
+    xb[q] = batch_xbase(b, q, w[q]);
+  }
+  STCHK(batch_restride<T>(b, R, zero64, rsv, xb, wv, r, st));
   GraphCache gc;
-  HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-  for (int u = 0; u < U; ++u) enqueue_inner_step<T>(p, b->rs, R, y, sigma, G, refresh, st);
-  HIPCHK(hipStreamEndCapture(st, &gc.graph));
-  HIPCHK(hipGraphInstantiate(&gc.exec, gc.graph, nullptr, nullptr, 0));
   std::vector<int32_t> fl(2 * count);
   int nactive = count;
   for (int k = 0; k < o.max_outer && nactive > 0; ++k) {
@@ -1740,6 +1881,13 @@ static alm_bm_status batch_solve_impl(alm_bm_batch* b, const alm_bm_options& o, 
       tolv[q] = std::max(o.eps_kkt / 10.0, std::min(o.inner_tol_scale, std::min(pinf_prev[q], o.inner_tol_decay * tol_prev[q])));
       tol_prev[q] = tolv[q];
     }
+    // launch tables of this outer iteration's running instances, and the graph
+    STCHK(batch_classes(b, w, active, st));
+    gc.reset();
+    HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    for (int u = 0; u < U; ++u) batch_enqueue_step<T>(b, R, y, sigma, G, refresh, st);
+    HIPCHK(hipStreamEndCapture(st, &gc.graph));
+    HIPCHK(hipGraphInstantiate(&gc.exec, gc.graph, nullptr, nullptr, 0));
     HIPCHK(hipMemcpyAsync(b->tols_dev, tolv.data(), count * sizeof(double), hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(b->active_dev, active.data(), count * sizeof(int32_t), hipMemcpyHostToDevice, st));
     launch_inner_reset_batch(p->sc_solve, count, b->tols_dev, b->active_dev, o.max_inner, (int)o.step_rule,
@@ -1786,17 +1934,41 @@ static alm_bm_status batch_solve_impl(alm_bm_batch* b, const alm_bm_options& o, 
         if (gate && L.theta[q] < -tau[q] && r[q] < rcap[q] && q4 > 0.0) {
           col[q] = r[q];
           scale[q] = std::sqrt(std::max(0.0, -L.theta[q] / (sigma * q4)));
-          r[q] += 1;
           expanded[q] = 1;
           res[q].expansions += 1;
           any = true;
         }
       }
       if (any) {
+        // widen the instances whose new column does not fit their width
+        std::vector<int> w2(w);
+        bool widen = false;
+        for (int q = 0; q < count; ++q)
+          if (expanded[q] && r[q] + 1 > w[q]) {
+            w2[q] = pad_width(r[q] + 1, b->rs);
+            widen = true;
+          }
+        if (widen) {
+          std::vector<int64_t> ob(count), nbv(count);
+          std::vector<int32_t> os(count), ns(count);
+          for (int q = 0; q < count; ++q) {
+            ob[q] = batch_xbase(b, q, w[q]);
+            os[q] = w[q];
+            nbv[q] = batch_xbase(b, q, w2[q]);
+            ns[q] = w2[q];
+          }
+          STCHK(batch_restride<T>(b, R, ob, os, nbv, ns, r, st));
+          w = w2;
+          STCHK(batch_classes(b, w, active, st));
+        }
+        for (int q = 0; q < count; ++q)
+          if (expanded[q]) r[q] += 1;
         HIPCHK(hipMemcpyAsync(b->col_dev, col.data(), count * sizeof(int32_t), hipMemcpyHostToDevice, st));
         HIPCHK(hipMemcpyAsync(b->scale_dev, scale.data(), count * sizeof(double), hipMemcpyHostToDevice, st));
-        launch_fill_column<T>(N, b->rs, R, p->lv, b->col_dev, b->scale_dev, p->tab, p->nblk, st);
-        enqueue_objgrad<T>(p, b->rs, R, y, sigma, nullptr, p->Av, p->sc_api, 0, nullptr, st);
+        for (int c = 0; c < b->nclass; ++c)
+          launch_fill_column<T>(N, b->c_w[c], R, p->lv, b->col_dev, b->scale_dev, batch_class_tab(b, c), b->c_nb[c],
+                                st);
+        batch_enqueue_objgrad<T>(b, R, y, sigma, st);
         launch_dual_batch(N, p->Av, p->d.b, y, p->ybuf, sigma, p->part_vec, p->sc_solve, b->bnorm_dev, p->tab,
                           p->nblk, count, st);
       }
@@ -1814,7 +1986,7 @@ static alm_bm_status batch_solve_impl(alm_bm_batch* b, const alm_bm_options& o, 
         if (expanded[q]) lam[q] = L2.theta[q];
     }
     // KKT per instance: <C, RR^T> and pinf at R, b^T y at y
-    enqueue_objgrad<T>(p, b->rs, R, y, 0.0, nullptr, p->Av, p->sc_api, 0, nullptr, st);
+    batch_enqueue_objgrad<T>(b, R, y, 0.0, st);
     launch_dual_batch(N, p->Av, p->d.b, y, nullptr, 0.0, p->part_vec, p->sc_api, b->bnorm_dev, p->tab, p->nblk, count,
                       st);
     std::vector<DevScalars> hs(count);
@@ -1849,6 +2021,16 @@ static alm_bm_status batch_solve_impl(alm_bm_batch* b, const alm_bm_options& o, 
     if (o.verbose)
       std::fprintf(stderr, "[almbm batch] k=%d active=%d t=%.2fs\n", k, nactive, now_s() - t0);
     if (o.time_limit_s > 0.0 && now_s() - t0 > o.time_limit_s) break;
+  }
+  // back to the caller's layout
+  {
+    std::vector<int64_t> ob(count);
+    std::vector<int32_t> os(count);
+    for (int q = 0; q < count; ++q) {
+      ob[q] = batch_xbase(b, q, w[q]);
+      os[q] = w[q];
+    }
+    STCHK(batch_restride<T>(b, R, ob, os, zero64, rsv, r, st));
   }
   for (int q = 0; q < count; ++q) {
     if (active[q]) res[q].time_s = now_s() - t0;

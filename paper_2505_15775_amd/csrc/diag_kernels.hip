@@ -30,6 +30,9 @@ k_objgrad_diag(Cost<typename Acc<T>::type> C, int r, const T* __restrict__ R,
   constexpr int RPB = kBlock / LPR;
   const int lane = threadIdx.x % LPR;
   const int slot = threadIdx.x / LPR;
+  const long xb = row_base(tab, ch.inst);
+  R += xb;
+  if (G) G += xb;
   SplitAcc<NUM_P, LPR> acc;
   acc.zero();
   for (long base = ch.lo; base < ch.hi; base += RPB) {
@@ -84,7 +87,7 @@ k_objgrad_diag(Cost<typename Acc<T>::type> C, int r, const T* __restrict__ R,
       acc.add(lane, P_RG, (double)rg);
     }
   }
-  acc.block_store(lane, part + (long)blockIdx.x * NUM_P);
+  acc.block_store(lane, part + part_slot(tab) * NUM_P);
 }
 
 // c2 = <G, C G> for the quartic line search (sparse product of the direction).
@@ -127,6 +130,9 @@ k_quadq_diag(Cost<typename Acc<T>::type> C, int r, const T* __restrict__ G, type
   constexpr int RPB = kBlock / LPR;
   const int lane = threadIdx.x % LPR;
   const int slot = threadIdx.x / LPR;
+  const long xb = row_base(tab, ch.inst);
+  G += xb;
+  Q += xb;
   double acc[1] = {0.0};
   for (long base = ch.lo; base < ch.hi; base += RPB) {
     const long i = base + slot;
@@ -141,7 +147,7 @@ k_quadq_diag(Cost<typename Acc<T>::type> C, int r, const T* __restrict__ G, type
     gq = group_sum<LPR>(gq);
     if (lane == 0) acc[0] += (double)gq;
   }
-  block_sum_store<1>(acc, part + blockIdx.x);
+  block_sum_store<1>(acc, part + part_slot(tab));
 }
 
 // Start of an inner iteration: apply the pending step R <- R - t G and, except
@@ -167,6 +173,10 @@ k_upd_eval_diag(long n, int r, T* __restrict__ R, T* __restrict__ G, const typen
   constexpr int RPB = kBlock / LPR;
   const int lane = threadIdx.x % LPR;
   const int slot = threadIdx.x / LPR;
+  const long xb = row_base(tab, ch.inst);
+  R += xb;
+  G += xb;
+  Q += xb;
   SplitAcc<NUM_P, LPR> acc;
   acc.zero();
   for (long base = ch.lo; base < ch.hi; base += RPB) {
@@ -231,7 +241,7 @@ k_upd_eval_diag(long n, int r, T* __restrict__ R, T* __restrict__ G, const typen
       acc.add(lane, P_RG, (double)rg);
     }
   }
-  if (!update_only) acc.block_store(lane, part + (long)blockIdx.x * NUM_P);
+  if (!update_only) acc.block_store(lane, part + part_slot(tab) * NUM_P);
 }
 
 // All line-search partials for an arbitrary direction G (API entry point).

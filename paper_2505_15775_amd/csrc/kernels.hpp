@@ -81,7 +81,16 @@ struct BlockTab {
   const int64_t* hi = nullptr;    // per block, end row
   const int32_t* iblo = nullptr;  // per instance, first block
   const int32_t* ibhi = nullptr;  // per instance, end block
+  // Optional, for launches over a subset of the blocks whose instances share
+  // one row width r: the partial-sum slot of each launched block (its index
+  // in the full table), and per instance the element offset xbase such that
+  // row i of the factor starts at xbase + i * r.
+  const int32_t* gid = nullptr;
+  const int64_t* xbase = nullptr;
 };
+
+__device__ __forceinline__ long part_slot(const BlockTab& t) { return t.gid ? t.gid[blockIdx.x] : blockIdx.x; }
+__device__ __forceinline__ long row_base(const BlockTab& t, int inst) { return t.xbase ? t.xbase[inst] : 0; }
 
 struct Rows {
   long lo, hi;

@@ -70,6 +70,9 @@ void launch_inner_reset(DevScalars* sc, double tol, int max_inner, int step_rule
 template <typename T>
 void launch_set_column(long n, int rs, int c, T* R, const double* v, double scale, hipStream_t st);
 template <typename T>
+void launch_restride_batch(const BlockTab& tab, int nb, const T* src, T* dst, const int64_t* ob, const int32_t* os,
+                           const int64_t* nbase, const int32_t* ns, const int32_t* nc, hipStream_t st);
+template <typename T>
 void launch_relayout(long n, int ss, int nc, int rd, const T* src, T* dst, const double* v, double scale,
                      hipStream_t st);
 template <typename S, typename D>

@@ -211,8 +211,28 @@ k_fill_column(long n, int rs, T* __restrict__ R, const double* __restrict__ v, c
   const double s = scale[rw.inst];
   if (!(s >= 0.0)) return;
   const int c = col[rw.inst];
+  R += row_base(tab, rw.inst);
   for (long i = rw.lo + threadIdx.x; i < rw.hi; i += kBlock)
     R[i * rs + c] = from_acc<T>(static_cast<typename Acc<T>::type>(s * v[i]));
+}
+
+// Batched factor re-layout: for every row i of instance q (blocks of the full
+// table), dst[nb_q + i ns_q + c] = src[ob_q + i os_q + c] for c < nc_q and 0
+// for nc_q <= c < ns_q.  src and dst must not overlap.
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_restride_batch(BlockTab tab, const T* __restrict__ src, T* __restrict__ dst, const int64_t* __restrict__ ob,
+                 const int32_t* __restrict__ os, const int64_t* __restrict__ nbase, const int32_t* __restrict__ ns,
+                 const int32_t* __restrict__ nc) {
+  const int q = tab.inst[blockIdx.x];
+  const long lo = tab.lo[blockIdx.x], hi = tab.hi[blockIdx.x];
+  const int w = ns[q], wo = os[q], c0 = nc[q];
+  const long len = (hi - lo) * (long)w;
+  for (long e = threadIdx.x; e < len; e += kBlock) {
+    const long i = lo + e / w;
+    const int c = (int)(e % w);
+    dst[nbase[q] + i * w + c] = c < c0 ? src[ob[q] + i * wo + c] : from_acc<T>(typename Acc<T>::type(0));
+  }
 }
 
 // R[:, c] <- scale * v (row stride rs), one instance.
@@ -320,6 +340,19 @@ template void launch_fill_column<float>(long, int, float*, const double*, const 
                                         const BlockTab&, int, hipStream_t);
 template void launch_fill_column<bf16>(long, int, bf16*, const double*, const int32_t*, const double*,
                                        const BlockTab&, int, hipStream_t);
+template <typename T>
+void launch_restride_batch(const BlockTab& tab, int nb, const T* src, T* dst, const int64_t* ob, const int32_t* os,
+                           const int64_t* nbase, const int32_t* ns, const int32_t* nc, hipStream_t st) {
+  hipLaunchKernelGGL((k_restride_batch<T>), dim3(nb), dim3(kBlock), 0, st, tab, src, dst, ob, os, nbase, ns, nc);
+}
+template void launch_restride_batch<double>(const BlockTab&, int, const double*, double*, const int64_t*,
+                                            const int32_t*, const int64_t*, const int32_t*, const int32_t*,
+                                            hipStream_t);
+template void launch_restride_batch<float>(const BlockTab&, int, const float*, float*, const int64_t*, const int32_t*,
+                                           const int64_t*, const int32_t*, const int32_t*, hipStream_t);
+template void launch_restride_batch<bf16>(const BlockTab&, int, const bf16*, bf16*, const int64_t*, const int32_t*,
+                                          const int64_t*, const int32_t*, const int32_t*, hipStream_t);
+
 template <typename T>
 void launch_set_column(long n, int rs, int c, T* R, const double* v, double scale, hipStream_t st) {
   hipLaunchKernelGGL((k_set_column<T>), dim3(elem_blocks(n)), dim3(kBlock), 0, st, n, rs, c, R, v, scale);
