@@ -1389,6 +1389,11 @@ struct alm_bm_batch {
   int c_nb[kNC] = {};
   int c_w[kNC] = {};
   int nclass = 0;
+  int32_t* a_inst = nullptr;        // blocks of every running instance (Lanczos)
+  int64_t* a_lo = nullptr;
+  int64_t* a_hi = nullptr;
+  int32_t* a_gid = nullptr;
+  int a_nb = 0;
   int64_t* xbase_dev = nullptr;     // count
   int64_t* ob_dev = nullptr;        // count: re-layout arguments
   int32_t* os_dev = nullptr;
@@ -1584,6 +1589,10 @@ extern "C" alm_bm_status alm_bm_batch_create(int32_t count, const alm_bm_problem
     BK(balloc(b, (void**)&b->c_hi[c], nb * sizeof(int64_t)));
     BK(balloc(b, (void**)&b->c_gid[c], nb * sizeof(int32_t)));
   }
+  BK(balloc(b, (void**)&b->a_inst, nb * sizeof(int32_t)));
+  BK(balloc(b, (void**)&b->a_lo, nb * sizeof(int64_t)));
+  BK(balloc(b, (void**)&b->a_hi, nb * sizeof(int64_t)));
+  BK(balloc(b, (void**)&b->a_gid, nb * sizeof(int32_t)));
   BK(balloc(b, (void**)&b->xbase_dev, count * sizeof(int64_t)));
   BK(balloc(b, (void**)&b->ob_dev, count * sizeof(int64_t)));
   BK(balloc(b, (void**)&b->os_dev, count * sizeof(int32_t)));
@@ -1635,13 +1644,17 @@ struct BatchLanczos {
 // Lanczos on Z(y) for every instance at once (lockstep steps; each instance
 // stops contributing to decisions once its Ritz residual meets tol[q]).
 static alm_bm_status batch_lanczos_pass(alm_bm_batch* b, const double* y, int kmax, const std::vector<double>& tol,
-                                        uint64_t seed, bool restart, double* v, BatchLanczos& out, hipStream_t st) {
+                                        uint64_t seed, bool restart, double* v, BatchLanczos& out, hipStream_t st,
+                                        const std::vector<int32_t>& active) {
   alm_bm_problem* p = b->p;
   const int count = b->count;
   const long n = p->d.n, ldq = n;
-  const int nb = p->nblk, kp = p->kmax + 1;
+  const int nb = b->a_nb, kp = p->kmax + 1;
   kmax = std::min(kmax, p->kmax);
-  VecBatch vb{p->tab, count, kp, kp};
+  // only the blocks of the running instances (partial sums in their slots of
+  // the full table, so the per-instance reductions are unchanged)
+  const BlockTab atab{b->a_inst, b->a_lo, b->a_hi, p->tab.iblo, p->tab.ibhi, b->a_gid, nullptr};
+  VecBatch vb{atab, count, kp, kp};
   if (restart) {
     launch_resid(n, v, v, 0.0, nullptr, p->lpart2, nb, st, vb);
     launch_fin_sum(p->lpart2, nb, p->lscal, 1, st, vb, 4);
@@ -1658,9 +1671,14 @@ static alm_bm_status batch_lanczos_pass(alm_bm_batch* b, const double* y, int km
   out.m.assign(count, 0);
   std::vector<char> done(count, 0);
   int ndone = 0;
+  for (int q = 0; q < count; ++q)
+    if (!active[q]) {
+      done[q] = 1;
+      ++ndone;
+    }
   for (int j = 0; j < kmax; ++j) {
     const double* qj = p->Q + (long)j * ldq;
-    launch_slack_mv(p->C64, 0, p->adj, y, 0.0, 0.0, p->sc_api, qj, p->lw, st);
+    launch_slack_mv_tab(p->C64, y, qj, p->lw, atab, nb, st);
     launch_dots(n, j + 1, p->Q, ldq, p->lw, p->lpart, kp, nb, p->lh1, st, vb);
     launch_sub(n, j + 1, p->Q, ldq, p->lh1, p->lw, p->lpart2, nb, st, vb);
     launch_dots(n, j + 1, p->Q, ldq, p->lw, p->lpart, kp, nb, p->lh2, st, vb);
@@ -1712,24 +1730,25 @@ static alm_bm_status batch_lanczos_pass(alm_bm_batch* b, const double* y, int km
   launch_combine(n, mmax, p->Q, ldq, p->ls, v, p->lpart2, nb, st, vb);
   launch_fin_sum(p->lpart2, nb, p->lscal + 1, 1, st, vb, 4);
   launch_scale(n, v, p->lscal + 1, v, p->lpart2, nb, nullptr, st, vb, 4);
-  launch_slack_mv(p->C64, 0, p->adj, y, 0.0, 0.0, p->sc_api, v, p->lw, st);
+  launch_slack_mv_tab(p->C64, y, v, p->lw, atab, nb, st);
   launch_resid(n, p->lw, v, 0.0, b->thetas_dev, p->lpart2, nb, st, vb);
   launch_fin_sum(p->lpart2, nb, p->lscal + 2, 1, st, vb, 4);
   std::vector<double> sc4((size_t)count * 4);
   HIPCHK(hipMemcpyAsync(sc4.data(), p->lscal, sc4.size() * sizeof(double), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   HIPCHK(hipGetLastError());
-  for (int q = 0; q < count; ++q) out.resid[q] = sc4[(size_t)q * 4 + 2];
+  for (int q = 0; q < count; ++q) out.resid[q] = active[q] ? sc4[(size_t)q * 4 + 2] : 0.0;
   return ALM_BM_OK;
 }
 
 static alm_bm_status batch_lanczos(alm_bm_batch* b, const double* y, int kmax, const std::vector<double>& tol,
-                                   uint64_t seed, double* v, BatchLanczos& out, hipStream_t st, int restarts = 3) {
+                                   uint64_t seed, double* v, BatchLanczos& out, hipStream_t st,
+                                   const std::vector<int32_t>& active, int restarts = 3) {
   for (int rs = 0; rs <= restarts; ++rs) {
-    STCHK(batch_lanczos_pass(b, y, kmax, tol, seed, rs > 0, v, out, st));
+    STCHK(batch_lanczos_pass(b, y, kmax, tol, seed, rs > 0, v, out, st, active));
     bool ok = true;
     for (int q = 0; q < b->count; ++q)
-      if (out.resid[q] > tol[q]) ok = false;
+      if (active[q] && out.resid[q] > tol[q]) ok = false;
     if (ok) break;
   }
   return ALM_BM_OK;
@@ -1791,6 +1810,22 @@ static alm_bm_status batch_classes(alm_bm_batch* b, const std::vector<int>& w, c
     HIPCHK(hipMemcpyAsync(b->c_hi[c], ch[c].data(), k * sizeof(int64_t), hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(b->c_gid[c], cg[c].data(), k * sizeof(int32_t), hipMemcpyHostToDevice, st));
   }
+  std::vector<int32_t> ai, ag;
+  std::vector<int64_t> al, ah;
+  for (int q = 0; q < count; ++q) {
+    if (!active[q]) continue;
+    for (int blk = b->h_iblo[q]; blk < b->h_ibhi[q]; ++blk) {
+      ai.push_back(q);
+      al.push_back(b->h_lo[blk]);
+      ah.push_back(b->h_hi[blk]);
+      ag.push_back(blk);
+    }
+  }
+  b->a_nb = (int)ai.size();
+  HIPCHK(hipMemcpyAsync(b->a_inst, ai.data(), ai.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(b->a_lo, al.data(), al.size() * sizeof(int64_t), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(b->a_hi, ah.data(), ah.size() * sizeof(int64_t), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(b->a_gid, ag.data(), ag.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
   std::vector<int64_t> xb(count);
   for (int q = 0; q < count; ++q) xb[q] = batch_xbase(b, q, w[q]);
   HIPCHK(hipMemcpyAsync(b->xbase_dev, xb.data(), count * sizeof(int64_t), hipMemcpyHostToDevice, st));
@@ -1912,7 +1947,7 @@ static alm_bm_status batch_solve_impl(alm_bm_batch* b, const alm_bm_options& o, 
                       count, st);
     BatchLanczos L;
     const double tl = now_s();
-    STCHK(batch_lanczos(b, p->ybuf, kmax, ltol, o.seed * 1000003ull + (uint64_t)k, p->lv, L, st,
+    STCHK(batch_lanczos(b, p->ybuf, kmax, ltol, o.seed * 1000003ull + (uint64_t)k, p->lv, L, st, active,
                         o.lanczos_restarts));
     const double tlan = now_s() - tl;
     // rank expansion decisions
@@ -1979,7 +2014,7 @@ static alm_bm_status batch_solve_impl(alm_bm_batch* b, const alm_bm_options& o, 
     if (any) {
       BatchLanczos L2;
       const double t2 = now_s();
-      STCHK(batch_lanczos(b, y, kmax, ltol, o.seed * 1000003ull + (uint64_t)k + 7777777ull, p->lv, L2, st,
+      STCHK(batch_lanczos(b, y, kmax, ltol, o.seed * 1000003ull + (uint64_t)k + 7777777ull, p->lv, L2, st, active,
                           o.lanczos_restarts));
       tlan2 = now_s() - t2;
       for (int q = 0; q < count; ++q)

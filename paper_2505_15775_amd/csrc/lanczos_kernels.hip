@@ -44,6 +44,27 @@ k_slack_mv(Cost<double> C, int cons_kind, EdgeAdj A, const double* __restrict__ 
   }
 }
 
+// The same product over the rows of a block table (batched mode: only the
+// blocks of the instances still running).
+__global__ void __launch_bounds__(kBlock)
+k_slack_mv_tab(Cost<double> C, const double* __restrict__ y, const double* __restrict__ x, double* __restrict__ out,
+               BlockTab tab) {
+  constexpr int L = kSpmvLpr;
+  constexpr int RPB = kBlock / L;
+  const Rows ch = rows_of(C.n, tab);
+  const int lane = threadIdx.x % L;
+  for (long base = ch.lo; base < ch.hi; base += RPB) {
+    const long i = base + threadIdx.x / L;
+    double acc = 0.0;
+    if (i < ch.hi) {
+      const long k0 = C.rp ? C.rp[i] : 0, k1 = C.rp ? C.rp[i + 1] : 0;
+      for (long k = k0 + lane; k < k1; k += L) acc += C.cv[k] * x[C.ci[k]];
+    }
+    acc = group_sum<L>(acc);
+    if (i < ch.hi && lane == 0) out[i] = acc + ((C.dg ? C.dg[i] : 0.0) - y[i]) * x[i];
+  }
+}
+
 // partials[b][c] = sum over the block's rows of Q[c][i] * w[i], c < ncol.
 // Wave w of the block handles columns c = w, w+4, ...; lanes stride the rows.
 __global__ void __launch_bounds__(kBlock)
@@ -63,7 +84,7 @@ k_dots(long n, int ncol, const double* __restrict__ Q, long ldq, const double* _
     }
     for (; i < ch.hi; i += kWave) a0 += q[i] * w[i];
     double a = wave_sum((a0 + a1) + (a2 + a3));
-    if (lane == 0) part[(long)blockIdx.x * pstride + c] = a;
+    if (lane == 0) part[part_slot(tab) * pstride + c] = a;
   }
 }
 
@@ -96,7 +117,7 @@ k_sub(long n, int ncol, const double* __restrict__ Q, long ldq, const double* __
     w[i] = v;
     acc[0] += v * v;
   }
-  block_sum_store<1>(acc, part + blockIdx.x);
+  block_sum_store<1>(acc, part + part_slot(tab));
 }
 
 // Tridiagonal entries after the two projections: alpha_j = h1[j] + h2[j],
@@ -138,7 +159,7 @@ k_scale(long n, const double* __restrict__ w, const double* __restrict__ beta_pt
     q[i] = v;
     acc[0] += v;
   }
-  block_sum_store<1>(acc, part + blockIdx.x);
+  block_sum_store<1>(acc, part + part_slot(tab));
 }
 
 __global__ void __launch_bounds__(kBlock)
@@ -170,7 +191,7 @@ k_rand(long n, uint64_t seed, double* __restrict__ x, double* __restrict__ part,
     x[i] = v;
     acc[0] += v * v;
   }
-  block_sum_store<1>(acc, part + blockIdx.x);
+  block_sum_store<1>(acc, part + part_slot(tab));
 }
 
 // v = sum_c Q[c] s[c]; partial ||v||^2.
@@ -188,7 +209,7 @@ k_combine(long n, int ncol, const double* __restrict__ Q, long ldq, const double
     v[i] = a;
     acc[0] += a * a;
   }
-  block_sum_store<1>(acc, part + blockIdx.x);
+  block_sum_store<1>(acc, part + part_slot(tab));
 }
 
 // partial ||z - theta v||^2 (residual of the Ritz pair).
@@ -202,7 +223,7 @@ k_resid(long n, const double* __restrict__ z, const double* __restrict__ v, doub
     const double d = z[i] - theta * v[i];
     acc[0] += d * d;
   }
-  block_sum_store<1>(acc, part + blockIdx.x);
+  block_sum_store<1>(acc, part + part_slot(tab));
 }
 
 // sum_i x_i^4 (DIAG) or sum over edges of (x_i x_j)^2 (TRACE_EDGES): the
@@ -223,7 +244,7 @@ k_quartic_norm(long n, int cons_kind, EdgeAdj A, const double* __restrict__ x, d
       }
     }
   }
-  block_sum_store<1>(acc, part + blockIdx.x);
+  block_sum_store<1>(acc, part + part_slot(tab));
 }
 
 // ---- launchers (single instance: empty table, count 1, strides 0) ---------------
@@ -240,6 +261,10 @@ void launch_slack_mv(const Cost<double>& C, int cons_kind, const EdgeAdj& A, con
   const long threads = C.n * kSpmvLpr;
   const int nb = (int)((threads + kBlock - 1) / kBlock);
   hipLaunchKernelGGL(k_slack_mv, dim3(nb), dim3(kBlock), 0, st, C, cons_kind, A, y, c_tr, j_coef, sc, x, out);
+}
+void launch_slack_mv_tab(const Cost<double>& C, const double* y, const double* x, double* out, const BlockTab& tab,
+                         int nb, hipStream_t st) {
+  hipLaunchKernelGGL(k_slack_mv_tab, dim3(nb), dim3(kBlock), 0, st, C, y, x, out, tab);
 }
 void launch_dots(long n, int ncol, const double* Q, long ldq, const double* w, double* part, int pstride, int nb,
                  double* h, hipStream_t st, const VecBatch& vb) {

@@ -81,6 +81,8 @@ void launch_convert(long len, const S* src, D* dst, hipStream_t st);
 int vec_blocks(long n);
 void launch_slack_mv(const Cost<double>& C, int cons_kind, const EdgeAdj& A, const double* y, double c_tr,
                      double j_coef, const DevScalars* sc, const double* x, double* out, hipStream_t st);
+void launch_slack_mv_tab(const Cost<double>& C, const double* y, const double* x, double* out, const BlockTab& tab,
+                         int nb, hipStream_t st);
 void launch_dots(long n, int ncol, const double* Q, long ldq, const double* w, double* part, int pstride, int nb,
                  double* h, hipStream_t st, const VecBatch& vb = VecBatch{});
 void launch_sub(long n, int ncol, const double* Q, long ldq, const double* h, double* w, double* part, int nb,
