@@ -138,6 +138,12 @@ def bench_mode(g, prec, r, steps, warmup, seed):
     out["objgrad_gbs"] = out["objgrad_bytes"] / per_og / 1e9
     out["spmm_gbs"] = out["spmm_bytes"] / per_cp / 1e9
     out["spmm_gathers_per_s"] = nnz / per_cp
+    # cache-line requests of one product: every gathered row is a separate
+    # request of ceil(row bytes / 128) lines; the streamed arrays add bytes/128
+    rb = {"f64": 8, "f32": 4, "bf16": 2}[prec]
+    lines = nnz * -(-(r * rb) // 128) + out["spmm_bytes"] / 128.0
+    out["spmm_line_requests"] = lines
+    out["spmm_line_requests_per_s"] = lines / per_cp
     return prob, R, y, out
 
 
@@ -315,6 +321,8 @@ def main():
                 "algorithmic_bytes_per_launch": main_out["spmm_bytes"],
                 "launch_ms": round(main_out["spmm_ms"], 4),
                 "gathered_rows_per_s": round(main_out["spmm_gathers_per_s"], 0),
+                "line_requests_per_launch": round(main_out["spmm_line_requests"], 0),
+                "line_requests_per_s": round(main_out["spmm_line_requests_per_s"], 0),
                 "objgrad": {"kernel": "k_objgrad_diag (full objective/gradient pass)",
                             "achieved": round(main_out["objgrad_gbs"], 1),
                             "frac": round(main_out["objgrad_gbs"] / HBM_PEAK_GBS, 4),
