@@ -211,6 +211,59 @@ def batch_leg(count, eps, sigma, prec, seed=3):
             "max_rel_objective_diff": worst}
 
 
+def kernels_leg(g, reps=20):
+    """The rows outside the MaxCut step: the edge family (Lovasz theta,
+    G(1e5, 1e6), r = 32, FP32: SDDMM + adjoint product + objective) and the
+    warm start's kernels at the full size (features; MLP forward and
+    backward, 8 -> 32 -> 32 -> 1, FP32)."""
+    import numpy as np
+    import torch
+
+    import gen
+    import paper_2505_15775_amd as almbm
+    from paper_2505_15775_amd import warmstart
+
+    out = {}
+    lv = gen.er_graph(100_000, 1_000_000, 4, "unit")
+    pl = almbm.Problem.lovasz(lv.n, lv.ei, lv.ej, precision="f32", r_max=32, lanczos_kmax=0, device="cuda:0",
+                              validate=False)
+    R = pl.factor(torch.from_numpy(gen.init_factor(lv.n, 32, 4) / np.sqrt(lv.n)))
+    y = torch.zeros(lv.m_edges + 1, dtype=torch.float64, device="cuda:0")
+    for _ in range(3):
+        pl.objective_grad(R, y, 1.0)
+    t = time_events(lambda: pl.objective_grad(R, y, 1.0), reps) / reps
+    E, n, r = lv.m_edges, lv.n, 32
+    # pattern (2E ids + 2E edge ids + n+1 row ptr + E upper cols), R read twice (SDDMM, adjoint),
+    # G write, y and A(RR^T) per edge (8 B each)
+    byts = (2 * E * 4 + 2 * E * 4 + (n + 1) * 4 + E * 4) + 2 * n * r * 4 + n * r * 4 + 2 * (E + 1) * 8
+    out["lovasz_objective_grad"] = {"n": n, "edges": E, "r": r, "precision": "f32", "ms": round(1000 * t, 4),
+                                    "evals_per_s": round(1.0 / t, 2), "algorithmic_bytes": byts,
+                                    "gbs": round(byts / t / 1e9, 1)}
+    pl.close()
+
+    pm = almbm.Problem.maxcut(g.n, g.ei, g.ej, g.w, precision="f32", r_max=16, lanczos_kmax=0, device="cuda:0",
+                              validate=False)
+    for _ in range(2):
+        F = warmstart.features(pm)
+    t = time_events(lambda: warmstart.features(pm), 5) / 5
+    nnz = int(pm.desc.nnz)
+    out["ws_features"] = {"n": g.n, "ms": round(1000 * t, 3), "algorithmic_bytes": nnz * 8 + g.n * 40,
+                          "gbs": round((nnz * 8 + g.n * 40) / t / 1e9, 1)}
+    model = warmstart.WarmStartModel(h=32, device="cuda:0")
+    model.predict_y0(pm, F)
+    t = time_events(lambda: model.predict_y0(pm, F), 5) / 5
+    h = 32
+    flops = 2.0 * g.n * (8 * h + h * h + h)
+    out["ws_mlp_forward"] = {"n": g.n, "h": h, "ms": round(1000 * t, 3), "tflops": round(flops / t / 1e12, 2),
+                             "peak_fp32_vector_tflops": 157.3}
+    T = torch.zeros(g.n, dtype=torch.float32, device="cuda:0")
+    model.loss_grad(F, T)
+    t = time_events(lambda: model.loss_grad(F, T), 3) / 3
+    out["ws_mlp_loss_grad"] = {"n": g.n, "h": h, "ms": round(1000 * t, 3), "tflops": round(3 * flops / t / 1e12, 2)}
+    pm.close()
+    return out
+
+
 def calibrate_copy(nbytes=1 << 30):
     """A plain elementwise copy of known size (read nbytes, write nbytes), for
     scaling the HBM byte counters of a profiled run."""
@@ -271,6 +324,7 @@ def main():
     ap.add_argument("--max-inner", type=int, default=500, help="gradient steps per subproblem in the solve legs")
     ap.add_argument("--batch", type=int, default=0, help="also the batched solve of this many instances vs a loop")
     ap.add_argument("--batch-eps", type=float, default=1e-4)
+    ap.add_argument("--kernels", action="store_true", help="also time the edge-family and warm-start kernels")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true", help="run a 1 GiB copy kernel first (profiling)")
     args = ap.parse_args()
@@ -368,6 +422,7 @@ def main():
             torch.cuda.empty_cache()
 
     batch = batch_leg(args.batch, args.batch_eps, args.sigma, "f64") if args.batch > 0 else None
+    other = kernels_leg(g) if args.kernels else None
 
     cpu = None if args.no_cpu_baseline else cpu_baseline(args.n, args.deg, args.rank, args.seed)
 
@@ -400,6 +455,8 @@ def main():
         line["solve_to_1e-4_kkt"] = solves
     if batch is not None:
         line["batched_solve"] = batch
+    if other is not None:
+        line["other_kernels"] = other
     print(json.dumps(line), flush=True)
 
 

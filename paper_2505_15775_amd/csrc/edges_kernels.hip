@@ -17,6 +17,27 @@ namespace almbm {
 
 constexpr int kEdgePS = NUM_P + kMaxR;  // partial stride: scalars, then r column sums
 
+// out[c] = sum over blocks of the column-sum partials (c < r <= kMaxR), by the
+// whole (single) block: P = kBlock / r threads per column take the blocks
+// bi = j, j + P, ... and their P values are added in order of j, so the result
+// does not depend on timing.  Every thread of the block must call it.
+__device__ __forceinline__ void colsum_reduce(const double* __restrict__ part, int nb, int r, double* __restrict__ out) {
+  __shared__ double buf[kBlock];
+  const int P = kBlock / r;
+  const int c = threadIdx.x % r, j = threadIdx.x / r;
+  double a = 0.0;
+  if (j < P)
+    for (int bi = j; bi < nb; bi += P) a += part[(long)bi * kEdgePS + NUM_P + c];
+  buf[threadIdx.x] = a;
+  __syncthreads();
+  if (threadIdx.x < r) {
+    double t = 0.0;
+    for (int k = 0; k < P; ++k) t += buf[k * r + threadIdx.x];
+    out[threadIdx.x] = t;
+  }
+  __syncthreads();
+}
+
 // Sum over the lanes of a block that share the same lane-in-row index (i.e.
 // over row groups) of a VEC-wide fragment, deterministic; thread t < LPR of the
 // first wave ends with the block totals for columns [t*VEC, t*VEC+VEC).
@@ -114,12 +135,7 @@ k_fin_edges1(const double* __restrict__ part, int nb, int r, DevScalars* __restr
     tot3[q] = t;
     __syncthreads();
   }
-  // column sums: one thread per column, blocks in order
-  for (int c = threadIdx.x; c < r; c += kBlock) {
-    double a = 0.0;
-    for (int bi = 0; bi < nb; ++bi) a += part[(long)bi * kEdgePS + NUM_P + c];
-    sc->colsum[c] = a;
-  }
+  colsum_reduce(part, nb, r, sc->colsum);
   if (threadIdx.x == 0) {
     const double rr = tot3[2];
     const double a0 = c_tr * rr;
@@ -226,11 +242,7 @@ k_fin_edges2(const double* __restrict__ part, int nb, int r, DevScalars* __restr
     tot4[q] = t;
     __syncthreads();
   }
-  for (int c = threadIdx.x; c < r; c += kBlock) {
-    double a = 0.0;
-    for (int bi = 0; bi < nb; ++bi) a += part[(long)bi * kEdgePS + NUM_P + c];
-    sc->gcolsum[c] = a;
-  }
+  colsum_reduce(part, nb, r, sc->gcolsum);
   if (threadIdx.x != 0) return;
   sc->tot[P_C0] = tot4[0];
   sc->tot[P_GG] = tot4[1];
