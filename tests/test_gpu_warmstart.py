@@ -126,8 +126,11 @@ def test_trained_warm_start_beats_default_start_on_held_out_graphs():
     graphs = ws.training_graphs(120, 6)[:4]
     tot_d = tot_w = 0
     t_d = t_w = 0.0
+    import paper_2505_15775_amd as almbm
+
     for g in graphs:
-        prob = _prob(g)
+        # these graphs reach ranks 39-56 at 1e-5, so the cap must be above that
+        prob = almbm.Problem.maxcut(g.n, g.ei, g.ej, g.w, precision="f64", r_max=64, lanczos_kmax=60, device=DEV)
         st, rd, _, _ = prob.solve(gen.init_factor(g.n, 16, 1), eps_kkt=1e-5, sigma=16.0, max_outer=300)
         stw, rw, _, _, info = ws.solve_warm(prob, model, eps_kkt=1e-5, sigma=16.0, max_outer=300)
         print(f"n={g.n}: default outer {rd['outer']} ({rd['time_s']:.2f}s) warm outer {rw['outer']} "
