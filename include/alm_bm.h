@@ -255,14 +255,16 @@ alm_bm_status alm_bm_autotune(alm_bm_problem* prob, int32_t r, int32_t reps, int
 /* ---- batched solves ----------------------------------------------------------
  * Many independent problems (DIAG family, one storage precision) solved
  * together: the instances are concatenated block-diagonally on the device and
- * every kernel launch of the method covers all of them (per-instance step
- * sizes, tolerances, stop flags, duals, Lanczos recurrences and ranks; the
+ * each launch of the method covers every instance still running (per-instance
+ * step sizes, tolerances, stop flags, duals, Lanczos recurrences and ranks; the
  * inner loop of all instances is one captured HIP graph per chunk of steps).
- * Factors share one row width, rank_stride: instance q's rows sit at rows
- * [off_q, off_q + n_q) of one (sum n) x rank_stride array, its first r_q columns
- * used and the rest zero (zero columns stay exactly zero under the gradient
- * step, so the padded problem is the rank-r_q problem).  Rank expansion fills
- * the next zero column, up to rank_stride.                                      */
+ * At the interface the factors share one row width, rank_stride: instance q's
+ * rows sit at rows [off_q, off_q + n_q) of one (sum n) x rank_stride array, its
+ * first r_q columns used and the rest zero (zero columns stay exactly zero
+ * under the gradient step, so the padded problem is the rank-r_q problem).
+ * Inside a solve each instance is kept at its own padded width (the next tile
+ * width at or above r_q) in its region of that array and is laid out back on
+ * return.  Rank expansion fills the next zero column, up to rank_stride.       */
 typedef struct alm_bm_batch alm_bm_batch;
 
 /* descs: host array of count descriptors (device arrays as for alm_bm_create,
