@@ -136,6 +136,10 @@ typedef struct {
                                 carried as C R - t C G (1 = always recompute)      */
   int32_t lanczos_restarts;  /* 3      restarts from the Ritz vector while the Ritz
                                 residual exceeds its tolerance                    */
+  double sigma_edges;        /* 0      TRACE_EDGES: penalty of the edge rows (the trace
+                                row keeps sigma); 0 -> sigma.  With tr X fixed the
+                                entries are O(1/n) and the edge rows need a penalty
+                                ~ n sigma to move their multipliers              */
 } alm_bm_options;
 
 typedef struct {

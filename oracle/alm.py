@@ -25,7 +25,8 @@ solve options):
   floor((sqrt(8m+1)-1)/2) of Sec. 3.3), whether or not the inner solve met its
   tolerance, as Alg. 1 does (an optional gate waits for inner convergence; it
   stalls the rank, hence the dual infeasibility, once max_inner binds);
-* fixed penalty sigma.
+* fixed penalty sigma; the edges family may give its edge rows their own penalty
+  sigma_edges (the trace row keeps sigma), one penalty per constraint throughout.
 
 Pins: the quartic coefficients against direct evaluation of the objective at
 R - tG (tests/test_oracle_alm.py); solve values against closed-form MaxCut and
@@ -58,6 +59,7 @@ class SolveOptions:
     inner_tol_scale: float = 0.1   # the 0.1 in min(0.1, pinf_prev, kappa tol_prev)
     inner_tol_decay: float = 0.7   # kappa
     expand_needs_inner: bool = False  # True: expand only after an inner solve met its tolerance
+    sigma_edges: Optional[float] = None  # edges family: penalty of the edge rows (trace row keeps sigma)
 
 
 def line_search_coeffs(p, R, G, y, sigma, P=None, a=None):
@@ -79,11 +81,12 @@ def line_search_coeffs(p, R, G, y, sigma, P=None, a=None):
     a1 = 2.0 * amap_uv(p, R, G)
     a2 = amap(p, G)
     e = a - p.b
-    k0 = c0 + float(np.dot(y, p.b - a)) + 0.5 * sigma * float(np.dot(e, e))
-    k1 = -c1 + float(np.dot(y, a1)) - sigma * float(np.dot(e, a1))
-    k2 = c2 - float(np.dot(y, a2)) + 0.5 * sigma * (float(np.dot(a1, a1)) + 2.0 * float(np.dot(e, a2)))
-    k3 = -sigma * float(np.dot(a1, a2))
-    k4 = 0.5 * sigma * float(np.dot(a2, a2))
+    s = sigma  # scalar, or one penalty per constraint
+    k0 = c0 + float(np.dot(y, p.b - a)) + 0.5 * float(np.dot(s * e, e))
+    k1 = -c1 + float(np.dot(y, a1)) - float(np.dot(s * e, a1))
+    k2 = c2 - float(np.dot(y, a2)) + 0.5 * (float(np.dot(s * a1, a1)) + 2.0 * float(np.dot(s * e, a2)))
+    k3 = -float(np.dot(s * a1, a2))
+    k4 = 0.5 * float(np.dot(s * a2, a2))
     return np.array([k0, k1, k2, k3, k4])
 
 
@@ -152,6 +155,10 @@ def solve(p, R0, y0=None, opts=None, callback=None):
     R = np.array(R0, dtype=np.float64, copy=True)
     y = np.zeros(p.m) if y0 is None else np.array(y0, dtype=np.float64, copy=True)
     sigma = opts.sigma
+    if p.kind == "edges" and opts.sigma_edges:
+        # one penalty per constraint: sigma on the trace row, sigma_edges on the edge rows
+        sigma = np.full(p.m, float(opts.sigma_edges))
+        sigma[0] = opts.sigma
     cnorm = cost_fro_norm(p)
     tau_rank = opts.tau_rank if opts.tau_rank is not None else opts.eps_kkt * (1.0 + cnorm)
     r_cap = min(opts.r_max, bp_rank_cap(p.m))
@@ -172,7 +179,8 @@ def solve(p, R0, y0=None, opts=None, callback=None):
             theta, v = min_eig(p, w, want_vector=True)
             gate = inner["converged"] or not opts.expand_needs_inner
             if gate and theta < -tau_rank and R.shape[1] < r_cap:
-                s = max(0.0, -theta / (sigma * rank_one_norm2(p, v)))
+                av = amap(p, v[:, None])
+                s = max(0.0, -theta / float(np.dot(sigma * av, av)))
                 R = np.concatenate([R, math.sqrt(s) * v[:, None]], axis=1)
                 a = amap(p, R)
                 w = y - sigma * (a - p.b)

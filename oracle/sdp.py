@@ -170,11 +170,12 @@ def rank_one_norm2(p, v):
 
 
 def objective(p, R, y, sigma):
-    """Lbar_sigma(R, y) = <C, R R^T> + <y, b - A(R R^T)> + sigma/2 ||A(R R^T) - b||^2  (eq. AL-BM)."""
+    """Lbar_sigma(R, y) = <C, R R^T> + <y, b - A(R R^T)> + sigma/2 ||A(R R^T) - b||^2  (eq. AL-BM).
+    sigma may be a scalar or one penalty per constraint (then sum_i sigma_i/2 res_i^2)."""
     P = cost_apply(p, R)
     a = amap(p, R)
     res = a - p.b
-    return float(np.sum(R * P) + np.dot(y, p.b - a) + 0.5 * sigma * np.dot(res, res))
+    return float(np.sum(R * P) + np.dot(y, p.b - a) + 0.5 * np.dot(sigma * res, res))
 
 
 def objective_grad(p, R, y, sigma):
@@ -189,7 +190,7 @@ def objective_grad(p, R, y, sigma):
     a = amap(p, R)
     res = a - p.b
     w = y - sigma * res
-    f = float(np.sum(R * P) + np.dot(y, p.b - a) + 0.5 * sigma * np.dot(res, res))
+    f = float(np.sum(R * P) + np.dot(y, p.b - a) + 0.5 * np.dot(sigma * res, res))
     G = 2.0 * (P - adjoint_apply(p, w, R))
     return f, G, a, P
 

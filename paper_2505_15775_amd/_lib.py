@@ -77,6 +77,7 @@ class Options(C.Structure):
         ("bf16_promote", C.c_int32),
         ("refresh_every", C.c_int32),
         ("lanczos_restarts", C.c_int32),
+        ("sigma_edges", C.c_double),
     ]
 
 

@@ -52,6 +52,7 @@ struct alm_bm_problem {
   int variant = 0;
   BlockTab tab{};                 // batched super-problem: per-block instance rows
   int count = 1;                  // instances (DevScalars in sc_solve)
+  double rho = 1.0;               // edge rows' penalty / sigma (set for the length of a solve)
   double* part = nullptr;     // nblk * (NUM_P + kMaxR)
   double* part_c2 = nullptr;  // nblk
   double* part_vec = nullptr; // vec kernels
@@ -243,6 +244,7 @@ extern "C" void alm_bm_default_options(alm_bm_options* o) {
   o->bf16_promote = 1;
   o->refresh_every = 0;
   o->lanczos_restarts = 3;
+  o->sigma_edges = 0.0;
 }
 
 extern "C" const char* alm_bm_last_error(void) { return g_err.c_str(); }
@@ -491,7 +493,7 @@ static void enqueue_objgrad(alm_bm_problem* p, int r, const T* R, const double* 
                            st);
     launch_fin_objgrad(p->part, p->nblk, sc, sigma, mode, f_out, st, p->tab, p->count);
   } else {
-    launch_edges_p1<T>(p->adj, d.n, r, p->variant, R, y, d.b, sigma, Av, p->wE, p->part, sc, p->nblk, st);
+    launch_edges_p1<T>(p->adj, d.n, r, p->variant, R, y, d.b, sigma, Av, p->wE, p->part, sc, p->nblk, st, p->rho);
     launch_fin_edges1(p->part, p->nblk, r, sc, y, d.b, sigma, d.trace_coef, Av, st);
     launch_edges_p2<T>(cost_of<T>(p), p->adj, r, p->variant, R, p->wE, d.trace_coef, d.j_coef, nullptr, G, p->part,
                        sc, p->nblk, st);
@@ -522,7 +524,8 @@ static void enqueue_inner_step(alm_bm_problem* p, int r, T* R, const double* y, 
     launch_fin_step(p->part_c2, p->nblk, 1, sc, sigma, 0.0, 1, nullptr, nullptr, st, p->tab, p->count);
   } else {
     enqueue_objgrad<T>(p, r, R, y, sigma, G, p->Av, sc, 1, nullptr, st);
-    launch_edges_p3<T>(cost_of<T>(p), p->adj, r, p->variant, R, G, y, d.b, p->Av, p->part, sc, p->nblk, st);
+    launch_edges_p3<T>(cost_of<T>(p), p->adj, r, p->variant, R, G, y, d.b, p->Av, p->part, sc, p->nblk, st,
+                       p->rho);
     launch_fin_edges3(p->part, p->nblk, r, sc, y, d.b, sigma, d.trace_coef, d.j_coef, 1, nullptr, nullptr, st);
     launch_update<T>((long)d.n * r, R, G, sc, 1, st);
   }
@@ -1175,7 +1178,8 @@ static alm_bm_status solve_impl(alm_bm_problem* p, const alm_bm_options& o, T* R
     STCHK(inner_solve<T>(p, w, R, y, sigma, tol, o, gc, st, iters, flag));
     acc.inner_total += iters;
     // w = y - sigma (A(RR^T) - b) into ybuf (Av is current: the last pass ran at the final R)
-    launch_dual(d.m, p->Av, d.b, y, p->ybuf, sigma, p->part_vec, p->sc_solve, p->bnorm, nullptr, st);
+    launch_dual(d.m, p->Av, d.b, y, p->ybuf, sigma, p->part_vec, p->sc_solve, p->bnorm, nullptr, st,
+                sigma * p->rho);
     LanczosOut lo;
     const double tl = now_s();
     STCHK(lanczos_run(p, p->ybuf, kmax, ltol, o.seed * 1000003ull + (uint64_t)k, p->lv, lo, st,
@@ -1190,7 +1194,8 @@ static alm_bm_status solve_impl(alm_bm_problem* p, const alm_bm_options& o, T* R
       double q4 = 0.0;
       HIPCHK(hipMemcpyAsync(&q4, p->lscal + 3, sizeof(double), hipMemcpyDeviceToHost, st));
       HIPCHK(hipStreamSynchronize(st));
-      if (d.cons_kind != ALM_BM_CONS_DIAG) q4 += d.trace_coef * d.trace_coef;
+      // curvature sum_i sigma_i a_i(v v^T)^2 / sigma of the rank-one step (edge rows weighted by rho)
+      if (d.cons_kind != ALM_BM_CONS_DIAG) q4 = p->rho * q4 + d.trace_coef * d.trace_coef;
       if (q4 > 0.0) {
         const double s = std::max(0.0, -lo.theta / (sigma * q4));
         if (r + 1 <= w) {
@@ -1207,7 +1212,8 @@ static alm_bm_status solve_impl(alm_bm_problem* p, const alm_bm_options& o, T* R
         expanded = true;
         acc.expansions += 1;
         enqueue_objgrad<T>(p, w, R, y, sigma, nullptr, p->Av, p->sc_api, 0, nullptr, st);
-        launch_dual(d.m, p->Av, d.b, y, p->ybuf, sigma, p->part_vec, p->sc_solve, p->bnorm, nullptr, st);
+        launch_dual(d.m, p->Av, d.b, y, p->ybuf, sigma, p->part_vec, p->sc_solve, p->bnorm, nullptr, st,
+                    sigma * p->rho);
       }
     }
     HIPCHK(hipMemcpyAsync(y, p->ybuf, d.m * sizeof(double), hipMemcpyDeviceToDevice, st));
@@ -1269,8 +1275,14 @@ extern "C" alm_bm_status alm_bm_inner_solve(alm_bm_problem* p, const alm_bm_opti
   else alm_bm_default_options(&o);
   if (!(o.sigma > 0.0)) return fail(ALM_BM_ERR_INVALID_ARG, "inner_solve: sigma must be positive");
   o.max_inner = max_steps;
+  if (o.sigma_edges < 0.0) return fail(ALM_BM_ERR_INVALID_ARG, "inner_solve: sigma_edges must be >= 0");
   HIPCHK(hipStreamSynchronize(st_user));
   hipStream_t st = p->ss;
+  struct RhoScope {
+    alm_bm_problem* p;
+    ~RhoScope() { p->rho = 1.0; }
+  } rho_scope{p};
+  p->rho = (p->d.cons_kind != ALM_BM_CONS_DIAG && o.sigma_edges > 0.0) ? o.sigma_edges / o.sigma : 1.0;
   int iters = 0, flag = 0;
   GraphCache gc;
   alm_bm_status s = with_storage(p->d.precision, [&]<typename T>() {
@@ -1296,8 +1308,15 @@ extern "C" alm_bm_status alm_bm_solve(alm_bm_problem* p, const alm_bm_options* o
   if (!(o.sigma > 0.0) || !(o.eps_kkt > 0.0) || o.max_outer < 1 || o.max_inner < 1)
     return fail(ALM_BM_ERR_INVALID_ARG, "solve: sigma, eps_kkt, max_outer and max_inner must be positive");
   if (p->kmax < 1) return fail(ALM_BM_ERR_INVALID_ARG, "solve: the handle has no Lanczos workspace");
+  if (o.sigma_edges < 0.0) return fail(ALM_BM_ERR_INVALID_ARG, "solve: sigma_edges must be >= 0");
   HIPCHK(hipStreamSynchronize(st_user));
   hipStream_t st = p->ss;
+  // penalty of the edge rows relative to sigma, for the length of this solve
+  struct RhoScope {
+    alm_bm_problem* p;
+    ~RhoScope() { p->rho = 1.0; }
+  } rho_scope{p};
+  p->rho = (p->d.cons_kind != ALM_BM_CONS_DIAG && o.sigma_edges > 0.0) ? o.sigma_edges / o.sigma : 1.0;
   const double t0 = now_s();
   alm_bm_result acc{};
   acc.promoted_at_outer = -1;

@@ -10,6 +10,10 @@
 //   P_i = (S R)_i + d_i R_i - j (1^T R); the symmetric pattern carries edge ids.
 // Pass 3 (line search): a1_e = <R_i,G_j> + <G_i,R_j>, a2_e = <G_i,G_j> over the
 //   upper half and <G, (S + D) G>.
+// The edge rows may carry their own penalty rho * sigma (the trace row keeps
+// sigma): pass 1 forms w_e with it and weights the edge residual sums by rho,
+// pass 3 weights the edge terms of the quartic by rho, so the finalizers'
+// common factor sigma yields sigma on the trace row and rho sigma on the edges.
 #include "spmm_row.hpp"
 #include "quartic.hpp"
 
@@ -67,7 +71,7 @@ template <typename T, int LPR, int VEC, bool FULL>
 __global__ void __launch_bounds__(kBlock)
 k_edges_p1(EdgeAdj A, long n, int r, const T* __restrict__ R, const double* __restrict__ y,
            const double* __restrict__ b, double sigma, double* __restrict__ Av, double* __restrict__ wE,
-           double* __restrict__ part, const DevScalars* __restrict__ sc) {
+           double* __restrict__ part, const DevScalars* __restrict__ sc, double rho) {
   using V = typename Acc<T>::type;
   if (sc && sc->flag) return;
   constexpr int RPB = kBlock / LPR;
@@ -104,10 +108,10 @@ k_edges_p1(EdgeAdj A, long n, int r, const T* __restrict__ R, const double* __re
       const double e = a - be;
       if (lane == 0) {
         if (Av) Av[1 + k] = a;
-        wE[k] = ye - sigma * e;
+        wE[k] = ye - rho * sigma * e;
       }
       acc.add(lane, P_YBMA, ye * (be - a));
-      acc.add(lane, P_EE, e * e);
+      acc.add(lane, P_EE, rho * e * e);
     }
     acc.add(lane, P_RR, (double)rr);
   }
@@ -265,7 +269,7 @@ template <typename T, int LPR, int VEC, bool FULL>
 __global__ void __launch_bounds__(kBlock)
 k_edges_p3(Cost<typename Acc<T>::type> C, EdgeAdj A, int r, const T* __restrict__ R, const T* __restrict__ G,
            const double* __restrict__ y, const double* __restrict__ b, const double* __restrict__ Av,
-           double* __restrict__ part, const DevScalars* __restrict__ sc) {
+           double* __restrict__ part, const DevScalars* __restrict__ sc, double rho) {
   using V = typename Acc<T>::type;
   if (sc->flag) return;
   constexpr int RPB = kBlock / LPR;
@@ -304,11 +308,11 @@ k_edges_p3(Cost<typename Acc<T>::type> C, EdgeAdj A, int r, const T* __restrict_
       const double d1 = a1, d2 = a2;
       acc.add(lane, P_YA1, ye * d1);
       acc.add(lane, P_YA2, ye * d2);
-      acc.add(lane, P_EA1, e * d1);
-      acc.add(lane, P_EA2, e * d2);
-      acc.add(lane, P_A1A1, d1 * d1);
-      acc.add(lane, P_A1A2, d1 * d2);
-      acc.add(lane, P_A2A2, d2 * d2);
+      acc.add(lane, P_EA1, rho * e * d1);
+      acc.add(lane, P_EA2, rho * e * d2);
+      acc.add(lane, P_A1A1, rho * d1 * d1);
+      acc.add(lane, P_A1A2, rho * d1 * d2);
+      acc.add(lane, P_A2A2, rho * d2 * d2);
     }
   }
   acc.block_store(lane, part + (long)blockIdx.x * kEdgePS);
@@ -394,13 +398,13 @@ k_fin_edges3(const double* __restrict__ part, int nb, int r, DevScalars* __restr
 
 template <typename T, int LPR, int VEC>
 static void p1_cfg(const EdgeAdj& A, long n, int r, const T* R, const double* y, const double* b, double sigma,
-                   double* Av, double* wE, double* part, const DevScalars* sc, int nblk, hipStream_t st) {
+                   double* Av, double* wE, double* part, const DevScalars* sc, int nblk, hipStream_t st, double rho) {
   if (r == LPR * VEC)
     hipLaunchKernelGGL((k_edges_p1<T, LPR, VEC, true>), dim3(nblk), dim3(kBlock), 0, st, A, n, r, R, y, b, sigma,
-                       Av, wE, part, sc);
+                       Av, wE, part, sc, rho);
   else
     hipLaunchKernelGGL((k_edges_p1<T, LPR, VEC, false>), dim3(nblk), dim3(kBlock), 0, st, A, n, r, R, y, b, sigma,
-                       Av, wE, part, sc);
+                       Av, wE, part, sc, rho);
 }
 template <typename T, int LPR, int VEC>
 static void p2_cfg(const Cost<typename Acc<T>::type>& C, const EdgeAdj& A, int r, const T* R, const double* wE,
@@ -416,20 +420,20 @@ static void p2_cfg(const Cost<typename Acc<T>::type>& C, const EdgeAdj& A, int r
 template <typename T, int LPR, int VEC>
 static void p3_cfg(const Cost<typename Acc<T>::type>& C, const EdgeAdj& A, int r, const T* R, const T* G,
                    const double* y, const double* b, const double* Av, double* part, const DevScalars* sc, int nblk,
-                   hipStream_t st) {
+                   hipStream_t st, double rho) {
   if (r == LPR * VEC)
     hipLaunchKernelGGL((k_edges_p3<T, LPR, VEC, true>), dim3(nblk), dim3(kBlock), 0, st, C, A, r, R, G, y, b, Av,
-                       part, sc);
+                       part, sc, rho);
   else
     hipLaunchKernelGGL((k_edges_p3<T, LPR, VEC, false>), dim3(nblk), dim3(kBlock), 0, st, C, A, r, R, G, y, b, Av,
-                       part, sc);
+                       part, sc, rho);
 }
 
 template <typename T>
 void launch_edges_p1(const EdgeAdj& A, long n, int r, int variant, const T* R, const double* y, const double* b,
                      double sigma, double* Av, double* wE, double* part, const DevScalars* sc, int nblk,
-                     hipStream_t st) {
-  ALMBM_DISPATCH_EDGES(T, p1_cfg, A, n, r, R, y, b, sigma, Av, wE, part, sc, nblk, st);
+                     hipStream_t st, double rho) {
+  ALMBM_DISPATCH_EDGES(T, p1_cfg, A, n, r, R, y, b, sigma, Av, wE, part, sc, nblk, st, rho);
 }
 template <typename T>
 void launch_edges_p2(const Cost<typename Acc<T>::type>& C, const EdgeAdj& A, int r, int variant, const T* R,
@@ -440,8 +444,8 @@ void launch_edges_p2(const Cost<typename Acc<T>::type>& C, const EdgeAdj& A, int
 template <typename T>
 void launch_edges_p3(const Cost<typename Acc<T>::type>& C, const EdgeAdj& A, int r, int variant, const T* R,
                      const T* G, const double* y, const double* b, const double* Av, double* part,
-                     const DevScalars* sc, int nblk, hipStream_t st) {
-  ALMBM_DISPATCH_EDGES(T, p3_cfg, C, A, r, R, G, y, b, Av, part, sc, nblk, st);
+                     const DevScalars* sc, int nblk, hipStream_t st, double rho) {
+  ALMBM_DISPATCH_EDGES(T, p3_cfg, C, A, r, R, G, y, b, Av, part, sc, nblk, st, rho);
 }
 
 void launch_fin_edges1(const double* part, int nb, int r, DevScalars* sc, const double* y, const double* b,
@@ -461,12 +465,12 @@ void launch_fin_edges3(const double* part, int nb, int r, DevScalars* sc, const 
 
 #define ALMBM_INST_E(T)                                                                                        \
   template void launch_edges_p1<T>(const EdgeAdj&, long, int, int, const T*, const double*, const double*, double, \
-                                   double*, double*, double*, const DevScalars*, int, hipStream_t);            \
+                                   double*, double*, double*, const DevScalars*, int, hipStream_t, double);    \
   template void launch_edges_p2<T>(const Cost<Acc<T>::type>&, const EdgeAdj&, int, int, const T*, const double*, \
                                    double, double, const T*, T*, double*, const DevScalars*, int, hipStream_t); \
   template void launch_edges_p3<T>(const Cost<Acc<T>::type>&, const EdgeAdj&, int, int, const T*, const T*,     \
                                    const double*, const double*, const double*, double*, const DevScalars*, int, \
-                                   hipStream_t);
+                                   hipStream_t, double);
 
 ALMBM_INST_E(double)
 ALMBM_INST_E(float)

@@ -27,7 +27,7 @@ void launch_ls_diag(const Cost<typename Acc<T>::type>& C, int r, int variant, co
 template <typename T>
 void launch_edges_p1(const EdgeAdj& A, long n, int r, int variant, const T* R, const double* y, const double* b,
                      double sigma, double* Av, double* wE, double* part, const DevScalars* sc, int nblk,
-                     hipStream_t st);
+                     hipStream_t st, double rho = 1.0);
 template <typename T>
 void launch_edges_p2(const Cost<typename Acc<T>::type>& C, const EdgeAdj& A, int r, int variant, const T* R,
                      const double* wE, double c_tr, double j_coef, const T* G_in, T* G, double* part,
@@ -35,7 +35,7 @@ void launch_edges_p2(const Cost<typename Acc<T>::type>& C, const EdgeAdj& A, int
 template <typename T>
 void launch_edges_p3(const Cost<typename Acc<T>::type>& C, const EdgeAdj& A, int r, int variant, const T* R,
                      const T* G, const double* y, const double* b, const double* Av, double* part,
-                     const DevScalars* sc, int nblk, hipStream_t st);
+                     const DevScalars* sc, int nblk, hipStream_t st, double rho = 1.0);
 void launch_fin_edges1(const double* part, int nb, int r, DevScalars* sc, const double* y, const double* b,
                        double sigma, double c_tr, double* Av, hipStream_t st);
 void launch_fin_edges2(const double* part, int nb, int r, DevScalars* sc, double sigma, int mode, double* f_out,
@@ -64,8 +64,11 @@ void launch_fin_ls(const double* part, int nb, DevScalars* sc, double sigma, dou
 template <typename T>
 void launch_update(long len, T* R, const T* G, const DevScalars* sc, int use_flag, hipStream_t st);
 int dual_blocks(long m);
+// y_out = y_in - sigma (Av - b) on row 0 and - sigma_tail (Av - b) on the other
+// rows (sigma_tail <= 0: sigma everywhere).
 void launch_dual(long m, const double* Av, const double* b, const double* y_in, double* y_out, double sigma,
-                 double* part, DevScalars* sc, double bnorm, double* pinf_out, hipStream_t st);
+                 double* part, DevScalars* sc, double bnorm, double* pinf_out, hipStream_t st,
+                 double sigma_tail = 0.0);
 void launch_inner_reset(DevScalars* sc, double tol, int max_inner, int step_rule, double eta, hipStream_t st);
 template <typename T>
 void launch_set_column(long n, int rs, int c, T* R, const double* v, double scale, hipStream_t st);

@@ -125,7 +125,7 @@ k_update(long len, T* __restrict__ R, const T* __restrict__ G, const DevScalars*
 // y_out = y_in - sigma (Av - b); partials {||Av - b||^2, b^T y_out}.
 __global__ void __launch_bounds__(kBlock)
 k_dual(long m, const double* __restrict__ Av, const double* __restrict__ b, const double* __restrict__ y_in,
-       double* __restrict__ y_out, double sigma, double* __restrict__ part, BlockTab tab) {
+       double* __restrict__ y_out, double sigma, double sigma_tail, double* __restrict__ part, BlockTab tab) {
   double acc[2] = {0.0, 0.0};
   long i0, i1, step;
   if (tab.inst) {
@@ -140,7 +140,7 @@ k_dual(long m, const double* __restrict__ Av, const double* __restrict__ b, cons
   }
   for (long i = i0; i < i1; i += step) {
     const double e = Av[i] - b[i];
-    const double yn = y_in[i] - sigma * e;
+    const double yn = y_in[i] - (i == 0 ? sigma : sigma_tail) * e;
     if (y_out) y_out[i] = yn;
     acc[0] += e * e;
     acc[1] += b[i] * yn;
@@ -306,15 +306,17 @@ int dual_blocks(long m) {
   return (int)nb;
 }
 void launch_dual(long m, const double* Av, const double* b, const double* y_in, double* y_out, double sigma,
-                 double* part, DevScalars* sc, double bnorm, double* pinf_out, hipStream_t st) {
+                 double* part, DevScalars* sc, double bnorm, double* pinf_out, hipStream_t st, double sigma_tail) {
   const int nb = dual_blocks(m);
-  hipLaunchKernelGGL(k_dual, dim3(nb), dim3(kBlock), 0, st, m, Av, b, y_in, y_out, sigma, part, BlockTab{});
+  if (!(sigma_tail > 0.0)) sigma_tail = sigma;
+  hipLaunchKernelGGL(k_dual, dim3(nb), dim3(kBlock), 0, st, m, Av, b, y_in, y_out, sigma, sigma_tail, part,
+                     BlockTab{});
   hipLaunchKernelGGL(k_fin_dual, dim3(1), dim3(kBlock), 0, st, part, nb, sc, bnorm, nullptr, pinf_out, BlockTab{});
 }
 void launch_dual_batch(long m, const double* Av, const double* b, const double* y_in, double* y_out, double sigma,
                        double* part, DevScalars* sc, const double* bnorms, const BlockTab& tab, int nb, int count,
                        hipStream_t st) {
-  hipLaunchKernelGGL(k_dual, dim3(nb), dim3(kBlock), 0, st, m, Av, b, y_in, y_out, sigma, part, tab);
+  hipLaunchKernelGGL(k_dual, dim3(nb), dim3(kBlock), 0, st, m, Av, b, y_in, y_out, sigma, sigma, part, tab);
   hipLaunchKernelGGL(k_fin_dual, dim3(count), dim3(kBlock), 0, st, part, nb, sc, 0.0, bnorms, nullptr, tab);
 }
 void launch_inner_reset(DevScalars* sc, double tol, int max_inner, int step_rule, double eta, hipStream_t st) {

@@ -193,3 +193,54 @@ def test_rank_expansion_step_is_exact_minimiser():
         pred = base + s * theta + 0.5 * sigma * s * s * oracle.rank_one_norm2(p, v)
         assert math.isclose(L(s), pred, rel_tol=1e-10, abs_tol=1e-10)
     assert L(s_star) <= min(L(0.9 * s_star), L(1.1 * s_star))
+
+
+def test_quartic_with_one_penalty_per_constraint():
+    """With a penalty vector (trace row sigma, edge rows sigma_e) the quartic
+    still reproduces sum_i sigma_i/2 res_i^2 along the ray, and phi'(0) = -||G||^2."""
+    p = oracle.lovasz_sdp(gen.er_graph(12, 20, 4))
+    rng = np.random.default_rng(8)
+    R = rng.standard_normal((p.n, 3))
+    y = rng.standard_normal(p.m)
+    sig = np.full(p.m, 37.0)
+    sig[0] = 1.3
+    f, G, a, P = oracle.objective_grad(p, R, y, sig)
+    k = oracle.line_search_coeffs(p, R, G, y, sig, P, a)
+    for t in [0.0, 0.02, 0.1, 0.5]:
+        Rt = R - t * G
+        at = oracle.amap(p, Rt)
+        direct = (float(np.sum(Rt * oracle.cost_apply(p, Rt))) + float(np.dot(y, p.b - at))
+                  + 0.5 * float(np.sum(sig * (at - p.b) ** 2)))
+        poly = sum(k[i] * t ** i for i in range(5))
+        assert math.isclose(poly, direct, rel_tol=1e-11, abs_tol=1e-11 * (1 + abs(direct)))
+    assert math.isclose(k[1], -np.sum(G * G), rel_tol=1e-11)
+
+
+def test_rank_step_with_one_penalty_per_constraint():
+    """L(X + s vv^T) = L(X) + s theta + s^2/2 sum_i sigma_i a_i(vv^T)^2, minimised at
+    s* = -theta / sum_i sigma_i a_i(vv^T)^2."""
+    p = oracle.lovasz_sdp(gen.er_graph(15, 30, 5))
+    R = gen.init_factor(15, 2, 3) / math.sqrt(15)
+    y = np.zeros(p.m)
+    sig = np.full(p.m, 15.0)
+    sig[0] = 1.0
+    f, G, a, _ = oracle.objective_grad(p, R, y, sig)
+    w = y - sig * (a - p.b)
+    theta, v = oracle.min_eig(p, w, want_vector=True)
+    assert theta < 0
+    av = oracle.amap(p, v[:, None])
+    curv = float(np.dot(sig * av, av))
+    base = oracle.objective(p, R, y, sig)
+    for s in [0.3, 1.0, 2.0]:
+        s = s * (-theta / curv)
+        val = oracle.objective(p, np.concatenate([R, math.sqrt(s) * v[:, None]], axis=1), y, sig)
+        assert math.isclose(val, base + s * theta + 0.5 * s * s * curv, rel_tol=1e-10, abs_tol=1e-10)
+
+
+@pytest.mark.parametrize("n,expect", [
+    (5, math.sqrt(5.0)),
+    (7, 7 * math.cos(math.pi / 7) / (1 + math.cos(math.pi / 7))),
+])
+def test_lovasz_theta_cycles_with_edge_penalty(n, expect):
+    val, _ = _solve_value(oracle.lovasz_sdp(gen.cycle_graph(n)), 3, eps=1e-6, sigma_edges=float(n))
+    assert math.isclose(val, expect, rel_tol=1e-5)
