@@ -21,3 +21,4 @@ from .graphs import (  # noqa: F401
     init_factor,
     draw_weights,
 )
+from .completion import Completion, completion_instance, sample_count  # noqa: F401

@@ -20,6 +20,7 @@ from .sdp import (  # noqa: F401
     maxcut_sdp,
     lovasz_sdp,
     edges_sdp,
+    completion_sdp,
     generic_sdp,
     cost_apply,
     cost_fro_norm,

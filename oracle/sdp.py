@@ -89,6 +89,18 @@ def edges_sdp(n, C, b, c_tr, ei, ej, j_coef=0.0):
                c_tr=float(c_tr), ei=np.asarray(ei, np.int64), ej=np.asarray(ej, np.int64))
 
 
+def completion_sdp(inst):
+    """Matrix completion as an SDP (Sec. 6): min tr(X)/2 over X = [[W1, Y], [Y^T, W2]]
+    PSD with Y_ij = M_ij on the observed entries.  X is (n1 + n2) x (n1 + n2);
+    entry (i, j) of Y is X_{i, n1 + j}, an entry constraint of the edges family
+    with no trace row (c_tr = 0, b_0 = 0).  Its value is the nuclear norm of the
+    completed matrix."""
+    n = inst.n1 + inst.n2
+    b = np.concatenate([[0.0], np.asarray(inst.vals, dtype=np.float64)])
+    C = 0.5 * sp.identity(n, format="csr")
+    return edges_sdp(n, C, b, 0.0, np.asarray(inst.rows, np.int64), inst.n1 + np.asarray(inst.cols, np.int64))
+
+
 def generic_sdp(C, A_list, b):
     C = sp.csr_matrix(np.asarray(C, dtype=np.float64) if not sp.issparse(C) else C)
     A = [sp.csr_matrix(np.asarray(a, dtype=np.float64) if not sp.issparse(a) else a) for a in A_list]

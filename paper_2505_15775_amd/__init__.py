@@ -144,6 +144,18 @@ class Problem:
         b[0] = 1.0
         return cls.edges(n, ei, ej, b, 1.0, j_coef=1.0, **kw)
 
+    @classmethod
+    def matrix_completion(cls, n1, n2, rows, cols, vals, **kw):
+        """Matrix completion (Sec. 6): min tr(X)/2 over X = [[W1, Y], [Y^T, W2]] PSD
+        with Y_ij = M_ij on the observed entries (rows, cols sorted by (row, col),
+        unique).  The factor is (n1 + n2) x r, U above V; entry (i, j) of Y is the
+        entry constraint X_{i, n1 + j}; no trace row (its coefficient is 0)."""
+        rows = np.asarray(rows, dtype=np.int64)
+        cols = np.asarray(cols, dtype=np.int64)
+        b = np.concatenate([[0.0], np.asarray(vals, dtype=np.float64)])
+        n = int(n1) + int(n2)
+        return cls.edges(n, rows, int(n1) + cols, b, 0.0, j_coef=0.0, cost_diag=np.full(n, 0.5), **kw)
+
     # ------------------------------------------------------------ lifetime
 
     def close(self):

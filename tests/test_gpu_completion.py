@@ -1,0 +1,65 @@
+"""Matrix completion (Sec. 6) on the GPU: objective/gradient and line search
+against the oracle in FP64, and solves whose value is the nuclear norm of the
+ground truth, with the oracle's KKT measure at the returned point."""
+
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import gen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def _almbm():
+    import paper_2505_15775_amd as m
+
+    return m
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def _problem(inst, prec="f64", r_max=16, kmax=60):
+    return _almbm().Problem.matrix_completion(inst.n1, inst.n2, inst.rows, inst.cols, inst.vals, precision=prec,
+                                              r_max=r_max, lanczos_kmax=kmax, device=DEV)
+
+
+@pytest.mark.parametrize("r", [3, 5])
+def test_completion_objective_grad_and_line_search_f64(r):
+    inst = gen.completion_instance(300, 200, 3, 7)
+    p = _problem(inst, r_max=8, kmax=0)
+    po = oracle.completion_sdp(inst)
+    rng = np.random.default_rng(r)
+    R = rng.standard_normal((inst.n, r))
+    y = rng.standard_normal(po.m)
+    f, G, Av = p.objective_grad(p.factor(R), torch.from_numpy(y).to(DEV), 2.5)
+    torch.cuda.synchronize()
+    f_o, G_o, a_o, P_o = oracle.objective_grad(po, R, y, 2.5)
+    assert abs(f.item() - f_o) <= 1e-10 * abs(f_o)
+    assert rel(G.cpu(), G_o) <= 1e-10 and rel(Av.cpu(), a_o) <= 1e-10
+    k, t = p.line_search(p.factor(R), p.factor(G_o), torch.from_numpy(y).to(DEV), 2.5)
+    k_o = oracle.line_search_coeffs(po, R, G_o, y, 2.5)
+    np.testing.assert_allclose(k.cpu().numpy(), k_o, rtol=1e-9, atol=1e-9 * float(np.max(np.abs(k_o))))
+
+
+@pytest.mark.parametrize("prec,eps,tol", [("f64", 1e-6, 1e-5), ("f32", 1e-5, 1e-4)])
+def test_completion_solve_reaches_the_nuclear_norm(prec, eps, tol):
+    inst = gen.completion_instance(1000, 1000, 3, 11)
+    nuc = float(np.sum(np.linalg.svd(inst.U @ inst.V.T, compute_uv=False)))
+    p = _problem(inst, prec=prec)
+    st, res, R, y = p.solve(gen.init_factor(inst.n, 3, 1), eps_kkt=eps, max_outer=500, time_limit_s=60)
+    print(f"completion 1000x1000 r=3 m={inst.m} {prec}: status {st} outer {res['outer']} rank {res['rank']} "
+          f"kkt {res['kkt']:.2e} value {res['pobj']:.10e} nuclear norm {nuc:.10e} time {res['time_s']:.2f}s")
+    assert st == 0
+    assert math.isclose(res["pobj"], nuc, rel_tol=tol)
+    if prec == "f64":
+        k = oracle.kkt(oracle.completion_sdp(inst), R.double().cpu().numpy(), y.cpu().numpy())
+        print(f"oracle KKT at the GPU point: {k['kkt']:.2e}")
+        assert k["kkt"] <= 2 * eps
