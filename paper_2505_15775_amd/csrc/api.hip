@@ -424,13 +424,15 @@ extern "C" alm_bm_status alm_bm_create(const alm_bm_problem_desc* desc, hipStrea
       HK(hipMemcpy(dci, ci.data(), 2 * E * sizeof(int32_t), hipMemcpyHostToDevice));
       HK(hipMemcpy(deid, eid.data(), 2 * E * sizeof(int32_t), hipMemcpyHostToDevice));
     }
-    p->adj = EdgeAdj{drp, dci, deid, durp, d.edge_j};
+    p->adj = EdgeAdj{drp, dci, deid, durp, d.edge_j, (float)(2.0 * (double)d.n_edges / (double)std::max<long>(1, d.n))};
     CK(dalloc_t(p, &p->wE, std::max<long>(1, E)));
   }
 
   // ---- workspace
   p->nblk = row_blocks(n);
   p->max_blocks = std::max(p->nblk, max_row_blocks(n));
+  // long edge-family rows (each split over a whole wave) need more, shorter blocks to fill the chip
+  if (d.cons_kind == ALM_BM_CONS_TRACE_EDGES && p->adj.avg_deg >= 32.f) p->nblk = max_row_blocks(n);
   const size_t es = esize(d.precision);
   CK(dalloc_t(p, &p->part, (size_t)p->max_blocks * (NUM_P + kMaxR)));
   CK(dalloc_t(p, &p->part_c2, (size_t)p->max_blocks));

@@ -67,16 +67,17 @@ __device__ __forceinline__ void block_colsum_store(double (&cs)[VEC], int r, dou
   }
 }
 
-template <typename T, int LPR, int VEC, bool FULL>
+template <typename T, int LPR, int VEC, bool FULL, int S>
 __global__ void __launch_bounds__(kBlock)
 k_edges_p1(EdgeAdj A, long n, int r, const T* __restrict__ R, const double* __restrict__ y,
            const double* __restrict__ b, double sigma, double* __restrict__ Av, double* __restrict__ wE,
            double* __restrict__ part, const DevScalars* __restrict__ sc, double rho) {
   using V = typename Acc<T>::type;
   if (sc && sc->flag) return;
-  constexpr int RPB = kBlock / LPR;
+  constexpr int RPB = kBlock / (LPR * S);
   const int lane = threadIdx.x % LPR;
-  const int slot = threadIdx.x / LPR;
+  const int grp = (threadIdx.x / LPR) % S;
+  const int slot = threadIdx.x / (LPR * S);
   SplitAcc<NUM_P, LPR> acc;
   acc.zero();
   double cs[VEC];
@@ -92,11 +93,11 @@ k_edges_p1(EdgeAdj A, long n, int r, const T* __restrict__ R, const double* __re
 #pragma unroll
     for (int v = 0; v < VEC; ++v) {
       rr += ri[v] * ri[v];
-      cs[v] += (double)ri[v];
+      if (grp == 0) cs[v] += (double)ri[v];
     }
     rr = group_sum<LPR>(rr);
     const int k0 = A.urp[i], k1 = A.urp[i + 1];
-    for (int k = k0; k < k1; ++k) {
+    for (int k = k0 + grp; k < k1; k += S) {
       const int j = A.uci[k];
       V rj[VEC];
       load_frag<T, VEC, FULL>(R + (long)j * r, lane, r, rj);
@@ -113,7 +114,7 @@ k_edges_p1(EdgeAdj A, long n, int r, const T* __restrict__ R, const double* __re
       acc.add(lane, P_YBMA, ye * (be - a));
       acc.add(lane, P_EE, rho * e * e);
     }
-    acc.add(lane, P_RR, (double)rr);
+    if (grp == 0) acc.add(lane, P_RR, (double)rr);
   }
   acc.block_store(lane, part + (long)blockIdx.x * kEdgePS);
   block_colsum_store<LPR, VEC>(cs, r, part + (long)blockIdx.x * kEdgePS + NUM_P);
@@ -155,16 +156,17 @@ k_fin_edges1(const double* __restrict__ part, int nb, int r, DevScalars* __restr
 
 // Pass 2: P = C R, gradient and its partials.  If G_in is given, the direction
 // is read instead of computed (line-search API) and nothing is written.
-template <typename T, int LPR, int VEC, bool FULL>
+template <typename T, int LPR, int VEC, bool FULL, int S>
 __global__ void __launch_bounds__(kBlock)
 k_edges_p2(Cost<typename Acc<T>::type> C, EdgeAdj A, int r, const T* __restrict__ R,
            const double* __restrict__ wE, double c_tr, double j_coef, const T* __restrict__ G_in,
            T* __restrict__ G, double* __restrict__ part, const DevScalars* __restrict__ sc) {
   using V = typename Acc<T>::type;
   if (sc->flag) return;
-  constexpr int RPB = kBlock / LPR;
+  constexpr int RPB = kBlock / (LPR * S);
   const int lane = threadIdx.x % LPR;
-  const int slot = threadIdx.x / LPR;
+  const int grp = (threadIdx.x / LPR) % S;
+  const int slot = threadIdx.x / (LPR * S);
   SplitAcc<NUM_P, LPR> acc;
   acc.zero();
   double gcs[VEC];
@@ -182,14 +184,19 @@ k_edges_p2(Cost<typename Acc<T>::type> C, EdgeAdj A, int r, const T* __restrict_
     if (i >= ch.hi) break;
     V ri[VEC], p[VEC], ad[VEC];
     load_frag<T, VEC, FULL>(R + i * r, lane, r, ri);
-    spmm_row<T, LPR, VEC, FULL>(C, i, lane, r, R, ri, p);
+    if (grp == 0) {
+      spmm_row<T, LPR, VEC, FULL>(C, i, lane, r, R, ri, p);
+    } else {
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) p[v] = V(0);
+    }
 #pragma unroll
     for (int v = 0; v < VEC; ++v) {
       p[v] -= jcs[v];
-      ad[v] = cw0 * ri[v];
+      ad[v] = grp == 0 ? cw0 * ri[v] : V(0);
     }
     const int k0 = A.rp[i], k1 = A.rp[i + 1];
-    for (int k = k0; k < k1; ++k) {
+    for (int k = k0 + grp; k < k1; k += S) {
       const int j = A.ci[k];
       const V we = static_cast<V>(0.5 * wE[A.eid[k]]);
       V rj[VEC];
@@ -197,31 +204,38 @@ k_edges_p2(Cost<typename Acc<T>::type> C, EdgeAdj A, int r, const T* __restrict_
 #pragma unroll
       for (int v = 0; v < VEC; ++v) ad[v] += we * rj[v];
     }
-    V g[VEC];
-    if (G_in) {
-      load_frag<T, VEC, FULL>(G_in + i * r, lane, r, g);
-    } else {
+    // the S groups of the row add their shares in a fixed butterfly order
 #pragma unroll
-      for (int v = 0; v < VEC; ++v) g[v] = round_st<T>(V(2) * (p[v] - ad[v]));
-      if (G) store_frag<T, VEC, FULL>(G + i * r, lane, r, g);
-    }
-    V rp = 0, gg = 0, gp = 0, rg = 0;
+    for (int o = LPR; o < LPR * S; o <<= 1)
 #pragma unroll
-    for (int v = 0; v < VEC; ++v) {
-      rp += ri[v] * p[v];
-      gg += g[v] * g[v];
-      gp += g[v] * p[v];
-      rg += ri[v] * g[v];
-      gcs[v] += (double)g[v];
+      for (int v = 0; v < VEC; ++v) ad[v] += __shfl_xor(ad[v], o, kWave);
+    if (grp == 0) {  // the row's own terms, once
+      V g[VEC];
+      if (G_in) {
+        load_frag<T, VEC, FULL>(G_in + i * r, lane, r, g);
+      } else {
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) g[v] = round_st<T>(V(2) * (p[v] - ad[v]));
+        if (G) store_frag<T, VEC, FULL>(G + i * r, lane, r, g);
+      }
+      V rp = 0, gg = 0, gp = 0, rg = 0;
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) {
+        rp += ri[v] * p[v];
+        gg += g[v] * g[v];
+        gp += g[v] * p[v];
+        rg += ri[v] * g[v];
+        gcs[v] += (double)g[v];
+      }
+      rp = group_sum<LPR>(rp);
+      gg = group_sum<LPR>(gg);
+      gp = group_sum<LPR>(gp);
+      rg = group_sum<LPR>(rg);
+      acc.add(lane, P_C0, (double)rp);
+      acc.add(lane, P_GG, (double)gg);
+      acc.add(lane, P_GP, (double)gp);
+      acc.add(lane, P_RG, (double)rg);
     }
-    rp = group_sum<LPR>(rp);
-    gg = group_sum<LPR>(gg);
-    gp = group_sum<LPR>(gp);
-    rg = group_sum<LPR>(rg);
-    acc.add(lane, P_C0, (double)rp);
-    acc.add(lane, P_GG, (double)gg);
-    acc.add(lane, P_GP, (double)gp);
-    acc.add(lane, P_RG, (double)rg);
   }
   acc.block_store(lane, part + (long)blockIdx.x * kEdgePS);
   block_colsum_store<LPR, VEC>(gcs, r, part + (long)blockIdx.x * kEdgePS + NUM_P);
@@ -265,16 +279,17 @@ k_fin_edges2(const double* __restrict__ part, int nb, int r, DevScalars* __restr
 }
 
 // Pass 3: line-search partials over the edges and <G, (S + D) G>.
-template <typename T, int LPR, int VEC, bool FULL>
+template <typename T, int LPR, int VEC, bool FULL, int S>
 __global__ void __launch_bounds__(kBlock)
 k_edges_p3(Cost<typename Acc<T>::type> C, EdgeAdj A, int r, const T* __restrict__ R, const T* __restrict__ G,
            const double* __restrict__ y, const double* __restrict__ b, const double* __restrict__ Av,
            double* __restrict__ part, const DevScalars* __restrict__ sc, double rho) {
   using V = typename Acc<T>::type;
   if (sc->flag) return;
-  constexpr int RPB = kBlock / LPR;
+  constexpr int RPB = kBlock / (LPR * S);
   const int lane = threadIdx.x % LPR;
-  const int slot = threadIdx.x / LPR;
+  const int grp = (threadIdx.x / LPR) % S;
+  const int slot = threadIdx.x / (LPR * S);
   SplitAcc<NUM_P, LPR> acc;
   acc.zero();
   const RowChunk ch = row_chunk(C.n);
@@ -284,14 +299,16 @@ k_edges_p3(Cost<typename Acc<T>::type> C, EdgeAdj A, int r, const T* __restrict_
     V ri[VEC], gi[VEC], q[VEC];
     load_frag<T, VEC, FULL>(R + i * r, lane, r, ri);
     load_frag<T, VEC, FULL>(G + i * r, lane, r, gi);
-    spmm_row<T, LPR, VEC, FULL>(C, i, lane, r, G, gi, q);
-    V gq = 0;
+    if (grp == 0) {
+      spmm_row<T, LPR, VEC, FULL>(C, i, lane, r, G, gi, q);
+      V gq = 0;
 #pragma unroll
-    for (int v = 0; v < VEC; ++v) gq += gi[v] * q[v];
-    gq = group_sum<LPR>(gq);
-    acc.add(lane, P_C2, (double)gq);
+      for (int v = 0; v < VEC; ++v) gq += gi[v] * q[v];
+      gq = group_sum<LPR>(gq);
+      acc.add(lane, P_C2, (double)gq);
+    }
     const int k0 = A.urp[i], k1 = A.urp[i + 1];
-    for (int k = k0; k < k1; ++k) {
+    for (int k = k0 + grp; k < k1; k += S) {
       const int j = A.uci[k];
       V rj[VEC], gj[VEC];
       load_frag<T, VEC, FULL>(R + (long)j * r, lane, r, rj);
@@ -399,34 +416,61 @@ k_fin_edges3(const double* __restrict__ part, int nb, int r, DevScalars* __restr
 template <typename T, int LPR, int VEC>
 static void p1_cfg(const EdgeAdj& A, long n, int r, const T* R, const double* y, const double* b, double sigma,
                    double* Av, double* wE, double* part, const DevScalars* sc, int nblk, hipStream_t st, double rho) {
+  const bool split = A.avg_deg >= 8.f * (kWave / LPR);
   if (r == LPR * VEC)
-    hipLaunchKernelGGL((k_edges_p1<T, LPR, VEC, true>), dim3(nblk), dim3(kBlock), 0, st, A, n, r, R, y, b, sigma,
-                       Av, wE, part, sc, rho);
+    {
+      if (split)
+        hipLaunchKernelGGL((k_edges_p1<T, LPR, VEC, true, kWave / LPR>), dim3(nblk), dim3(kBlock), 0, st, A, n, r, R, y, b, sigma, Av, wE, part, sc, rho);
+      else
+        hipLaunchKernelGGL((k_edges_p1<T, LPR, VEC, true, 1>), dim3(nblk), dim3(kBlock), 0, st, A, n, r, R, y, b, sigma, Av, wE, part, sc, rho);
+    }
   else
-    hipLaunchKernelGGL((k_edges_p1<T, LPR, VEC, false>), dim3(nblk), dim3(kBlock), 0, st, A, n, r, R, y, b, sigma,
-                       Av, wE, part, sc, rho);
+    {
+      if (split)
+        hipLaunchKernelGGL((k_edges_p1<T, LPR, VEC, false, kWave / LPR>), dim3(nblk), dim3(kBlock), 0, st, A, n, r, R, y, b, sigma, Av, wE, part, sc, rho);
+      else
+        hipLaunchKernelGGL((k_edges_p1<T, LPR, VEC, false, 1>), dim3(nblk), dim3(kBlock), 0, st, A, n, r, R, y, b, sigma, Av, wE, part, sc, rho);
+    }
 }
 template <typename T, int LPR, int VEC>
 static void p2_cfg(const Cost<typename Acc<T>::type>& C, const EdgeAdj& A, int r, const T* R, const double* wE,
                    double c_tr, double j_coef, const T* G_in, T* G, double* part, const DevScalars* sc, int nblk,
                    hipStream_t st) {
+  const bool split = A.avg_deg >= 8.f * (kWave / LPR);
   if (r == LPR * VEC)
-    hipLaunchKernelGGL((k_edges_p2<T, LPR, VEC, true>), dim3(nblk), dim3(kBlock), 0, st, C, A, r, R, wE, c_tr,
-                       j_coef, G_in, G, part, sc);
+    {
+      if (split)
+        hipLaunchKernelGGL((k_edges_p2<T, LPR, VEC, true, kWave / LPR>), dim3(nblk), dim3(kBlock), 0, st, C, A, r, R, wE, c_tr, j_coef, G_in, G, part, sc);
+      else
+        hipLaunchKernelGGL((k_edges_p2<T, LPR, VEC, true, 1>), dim3(nblk), dim3(kBlock), 0, st, C, A, r, R, wE, c_tr, j_coef, G_in, G, part, sc);
+    }
   else
-    hipLaunchKernelGGL((k_edges_p2<T, LPR, VEC, false>), dim3(nblk), dim3(kBlock), 0, st, C, A, r, R, wE, c_tr,
-                       j_coef, G_in, G, part, sc);
+    {
+      if (split)
+        hipLaunchKernelGGL((k_edges_p2<T, LPR, VEC, false, kWave / LPR>), dim3(nblk), dim3(kBlock), 0, st, C, A, r, R, wE, c_tr, j_coef, G_in, G, part, sc);
+      else
+        hipLaunchKernelGGL((k_edges_p2<T, LPR, VEC, false, 1>), dim3(nblk), dim3(kBlock), 0, st, C, A, r, R, wE, c_tr, j_coef, G_in, G, part, sc);
+    }
 }
 template <typename T, int LPR, int VEC>
 static void p3_cfg(const Cost<typename Acc<T>::type>& C, const EdgeAdj& A, int r, const T* R, const T* G,
                    const double* y, const double* b, const double* Av, double* part, const DevScalars* sc, int nblk,
                    hipStream_t st, double rho) {
+  const bool split = A.avg_deg >= 8.f * (kWave / LPR);
   if (r == LPR * VEC)
-    hipLaunchKernelGGL((k_edges_p3<T, LPR, VEC, true>), dim3(nblk), dim3(kBlock), 0, st, C, A, r, R, G, y, b, Av,
-                       part, sc, rho);
+    {
+      if (split)
+        hipLaunchKernelGGL((k_edges_p3<T, LPR, VEC, true, kWave / LPR>), dim3(nblk), dim3(kBlock), 0, st, C, A, r, R, G, y, b, Av, part, sc, rho);
+      else
+        hipLaunchKernelGGL((k_edges_p3<T, LPR, VEC, true, 1>), dim3(nblk), dim3(kBlock), 0, st, C, A, r, R, G, y, b, Av, part, sc, rho);
+    }
   else
-    hipLaunchKernelGGL((k_edges_p3<T, LPR, VEC, false>), dim3(nblk), dim3(kBlock), 0, st, C, A, r, R, G, y, b, Av,
-                       part, sc, rho);
+    {
+      if (split)
+        hipLaunchKernelGGL((k_edges_p3<T, LPR, VEC, false, kWave / LPR>), dim3(nblk), dim3(kBlock), 0, st, C, A, r, R, G, y, b, Av, part, sc, rho);
+      else
+        hipLaunchKernelGGL((k_edges_p3<T, LPR, VEC, false, 1>), dim3(nblk), dim3(kBlock), 0, st, C, A, r, R, G, y, b, Av, part, sc, rho);
+    }
 }
 
 template <typename T>

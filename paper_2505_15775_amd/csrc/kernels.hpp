@@ -69,6 +69,7 @@ struct EdgeAdj {
   const int32_t* eid;   // 2E
   const int32_t* urp;   // n+1, upper half; urp[i]..urp[i+1] are edges with ei = i
   const int32_t* uci;   // E, = edge_j in edge order
+  float avg_deg = 0.f;  // 2E / n: long rows (matrix completion) are split over several lane groups
 };
 
 // Batched mode: many instances concatenated block-diagonally.  Every block of
