@@ -22,7 +22,10 @@
  *               edge e = {i, j} (i < j), A_{1+e} = (e_i e_j^T + e_j e_i^T)/2,
  *               so <A_{1+e}, X> = X_ij; m = n_edges + 1.  This is the entry
  *               constraint of the examples of Sec. 3.3 and Sec. 4.3 and the
- *               constraint set of the Lovasz-theta SDP.
+ *               constraint set of the Lovasz-theta SDP.  The matrix completion
+ *               SDP of Sec. 6 is this family with trace_coef = 0 (b_0 = 0),
+ *               C = I/2 (d = 1/2, no S) on n = n1 + n2 rows and one edge
+ *               (i, n1 + j) with b = M_ij per observed entry.
  *
  * Conventions (all entry points)
  *   - Every call returns alm_bm_status.  Nothing throws or aborts across the
