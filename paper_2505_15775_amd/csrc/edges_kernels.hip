@@ -42,6 +42,26 @@ __device__ __forceinline__ void colsum_reduce(const double* __restrict__ part, i
   __syncthreads();
 }
 
+// out[q] = sum over blocks of the scalar partial part[b * kEdgePS + sl[q]], all K
+// slots in one pass (each thread takes the blocks t, t + kBlock, ...; the block
+// reduction is in fixed order).  Every thread of the (single) block must call it.
+template <int K>
+__device__ __forceinline__ void reduce_slots(const double* __restrict__ part, int nb, const int (&sl)[K],
+                                             double (&out)[K]) {
+  double acc[K];
+#pragma unroll
+  for (int q = 0; q < K; ++q) acc[q] = 0.0;
+  for (int bi = threadIdx.x; bi < nb; bi += kBlock)
+#pragma unroll
+    for (int q = 0; q < K; ++q) acc[q] += part[(long)bi * kEdgePS + sl[q]];
+  __shared__ double res[K];
+  block_sum_store<K>(acc, res);
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < K; ++q) out[q] = res[q];
+  __syncthreads();
+}
+
 // Sum over the lanes of a block that share the same lane-in-row index (i.e.
 // over row groups) of a VEC-wide fragment, deterministic; thread t < LPR of the
 // first wave ends with the block totals for columns [t*VEC, t*VEC+VEC).
@@ -126,20 +146,9 @@ k_fin_edges1(const double* __restrict__ part, int nb, int r, DevScalars* __restr
              const double* __restrict__ b, double sigma, double c_tr, double* __restrict__ Av) {
   if (sc->flag) return;
   // scalars
-  __shared__ double red[kBlock / kWave];
   double tot3[3];
   const int sl[3] = {P_YBMA, P_EE, P_RR};
-  for (int q = 0; q < 3; ++q) {
-    double a = 0.0;
-    for (int bi = threadIdx.x; bi < nb; bi += kBlock) a += part[(long)bi * kEdgePS + sl[q]];
-    a = wave_sum(a);
-    if (threadIdx.x % kWave == 0) red[threadIdx.x / kWave] = a;
-    __syncthreads();
-    double t = 0.0;
-    for (int w = 0; w < kBlock / kWave; ++w) t += red[w];
-    tot3[q] = t;
-    __syncthreads();
-  }
+  reduce_slots<3>(part, nb, sl, tot3);
   colsum_reduce(part, nb, r, sc->colsum);
   if (threadIdx.x == 0) {
     const double rr = tot3[2];
@@ -246,20 +255,9 @@ __global__ void __launch_bounds__(kBlock)
 k_fin_edges2(const double* __restrict__ part, int nb, int r, DevScalars* __restrict__ sc, double sigma, int mode,
              double* __restrict__ f_out) {
   if (sc->flag) return;
-  __shared__ double red[kBlock / kWave];
   double tot4[4];
   const int sl[4] = {P_C0, P_GG, P_GP, P_RG};
-  for (int q = 0; q < 4; ++q) {
-    double a = 0.0;
-    for (int bi = threadIdx.x; bi < nb; bi += kBlock) a += part[(long)bi * kEdgePS + sl[q]];
-    a = wave_sum(a);
-    if (threadIdx.x % kWave == 0) red[threadIdx.x / kWave] = a;
-    __syncthreads();
-    double t = 0.0;
-    for (int w = 0; w < kBlock / kWave; ++w) t += red[w];
-    tot4[q] = t;
-    __syncthreads();
-  }
+  reduce_slots<4>(part, nb, sl, tot4);
   colsum_reduce(part, nb, r, sc->gcolsum);
   if (threadIdx.x != 0) return;
   sc->tot[P_C0] = tot4[0];
@@ -342,20 +340,9 @@ k_fin_edges3(const double* __restrict__ part, int nb, int r, DevScalars* __restr
              const double* __restrict__ b, double sigma, double c_tr, double j_coef, int mode,
              double* __restrict__ coeffs_out, double* __restrict__ t_out) {
   if (mode == 1 && sc->flag) return;
-  __shared__ double red[kBlock / kWave];
   const int sl[8] = {P_C2, P_YA1, P_YA2, P_EA1, P_EA2, P_A1A1, P_A1A2, P_A2A2};
   double tot8[8];
-  for (int q = 0; q < 8; ++q) {
-    double a = 0.0;
-    for (int bi = threadIdx.x; bi < nb; bi += kBlock) a += part[(long)bi * kEdgePS + sl[q]];
-    a = wave_sum(a);
-    if (threadIdx.x % kWave == 0) red[threadIdx.x / kWave] = a;
-    __syncthreads();
-    double t = 0.0;
-    for (int w = 0; w < kBlock / kWave; ++w) t += red[w];
-    tot8[q] = t;
-    __syncthreads();
-  }
+  reduce_slots<8>(part, nb, sl, tot8);
   if (threadIdx.x != 0) return;
   double gj2 = 0.0;
   for (int c = 0; c < r; ++c) gj2 += sc->gcolsum[c] * sc->gcolsum[c];
