@@ -271,31 +271,93 @@ TABLE2 = [(3, 10000, 0.379, 0.562), (3, 20000, 0.726, 1.040), (3, 50000, 1.409, 
           (5, 50000, 3.025, 8.745), (5, 100000, 6.762, 17.297)]
 
 
-def completion_leg(prec="f64", eps=1e-5, rank_one_upto=20000):
+def completion_leg(prec="f64", eps=1e-5, rank_one_upto=20000, sigma=0.03, rows=None):
     """The matrix completion instances of Table 2 (generated with the paper's
     recipe, seeded), solved to its tolerance from rank r (and from rank 1 on
-    the smaller ones), beside the paper's A100 times for context."""
+    the smaller ones), beside the paper's A100 times for context.  The paper
+    gives no penalty for this workload; sigma = 0.03 was the fastest of
+    0.03, 0.1, 0.3 and 1 over these instances (the subproblems' gradient
+    steps shrink about tenfold from sigma = 1, for a few more outer steps)."""
     import torch
 
     import gen
     import paper_2505_15775_amd as almbm
 
     out = []
-    for r, n, t_paper, t_paper_r1 in TABLE2:
+    for r, n, t_paper, t_paper_r1 in (TABLE2 if rows is None else rows):
         inst = gen.completion_instance(n // 2, n - n // 2, r, 1)
         p = almbm.Problem.matrix_completion(inst.n1, inst.n2, inst.rows, inst.cols, inst.vals, precision=prec,
                                             r_max=32, lanczos_kmax=60, device="cuda:0", validate=False)
-        row = {"r": r, "n": n, "m": inst.m, "paper_a100_s": t_paper, "paper_a100_rank1_s": t_paper_r1}
+        row = {"r": r, "n": n, "m": inst.m, "sigma": sigma, "paper_a100_s": t_paper, "paper_a100_rank1_s": t_paper_r1}
         starts = [("from_rank_r", r)] + ([("from_rank_1", 1)] if n <= rank_one_upto else [])
         for name, r0 in starts:
             torch.cuda.synchronize()
-            st, res, _, _ = p.solve(gen.init_factor(inst.n, r0, 1), eps_kkt=eps, max_outer=1000, time_limit_s=120)
+            st, res, _, _ = p.solve(gen.init_factor(inst.n, r0, 1), eps_kkt=eps, sigma=sigma, max_outer=1000,
+                                    time_limit_s=120)
             row[name] = {"status": int(st), "time_s": round(res["time_s"], 3), "outer": res["outer"],
+                         "inner": res["inner_total"], "lanczos_s": round(res["time_lanczos_s"], 3),
                          "rank": res["rank"], "kkt": res["kkt"], "objective": res["pobj"]}
         log(f"[bench] completion r={r} n={n} m={inst.m}: {row}")
         out.append(row)
         p.close()
         del p
+        torch.cuda.empty_cache()
+    return out
+
+
+def rmat_leg(scale=22, edge_factor=8, r=16, precs=("bf16", "f64"), reps=20):
+    """Skewed degrees: MaxCut on an R-MAT graph (2^scale vertices, about
+    edge_factor * 2^scale edges, N(0,1) weights).  Times the cost product and
+    the objective/gradient pass with the default hub rows and with none."""
+    import numpy as np
+    import torch
+
+    import gen
+    import paper_2505_15775_amd as almbm
+    from paper_2505_15775_amd import _lib, _ptr, _stream
+
+    t0 = time.time()
+    g = gen.rmat_graph(scale, edge_factor, 7, "gauss")
+    deg = np.bincount(np.concatenate([g.ei, g.ej]), minlength=g.n)
+    log(f"[bench] R-MAT 2^{scale}: E={g.m_edges} max degree {int(deg.max())} generated in {time.time() - t0:.1f}s")
+    dev = torch.device("cuda:0")
+    out = {"workload": f"MaxCut SDP on R-MAT 2^{scale} (a,b,c,d = 0.57,0.19,0.19,0.05), E={g.m_edges}, "
+                       f"N(0,1) weights, r={r}", "n": g.n, "edges": int(g.m_edges), "max_degree": int(deg.max())}
+    for prec in precs:
+        prob = almbm.Problem.maxcut(g.n, g.ei, g.ej, g.w, precision=prec, r_max=r, lanczos_kmax=0, device=dev,
+                                    validate=False)
+        X = prob.factor(torch.from_numpy(gen.init_factor(g.n, r, 1)))
+        y = torch.zeros(g.n, dtype=torch.float64, device=dev)
+        P = torch.empty(X.shape, dtype=torch.float64 if prec == "f64" else torch.float32, device=dev)
+        G = torch.empty_like(X)
+        Av = torch.empty(g.n, dtype=torch.float64, device=dev)
+        f = torch.empty(1, dtype=torch.float64, device=dev)
+        nnz = int(prob.desc.nnz)
+        rb = {"f64": 8, "f32": 4, "bf16": 2}[prec]
+
+        def cp():
+            _lib.check(_lib.lib.alm_bm_cost_apply(prob._h, r, _ptr(X), _ptr(P), None, _stream()), "cost_apply")
+
+        def og():
+            _lib.check(_lib.lib.alm_bm_objective_grad(prob._h, r, _ptr(X), _ptr(y), 1.0, _ptr(f), _ptr(G), _ptr(Av),
+                                                      _stream()), "objective_grad")
+
+        row = {}
+        for name, thr in (("hubs", 0), ("no_hubs", -1)):
+            nh = prob.set_hub_threshold(thr)
+            for fn in (cp, og):
+                fn()
+            per_cp = time_events(cp, reps) / reps
+            per_og = time_events(og, reps) / reps
+            by = spmm_bytes(g.n, nnz, r, prec)
+            lines = nnz * -(-(r * rb) // 128) + by / 128.0
+            row[name] = {"hub_rows": nh, "cost_product_ms": round(1000 * per_cp, 4),
+                         "objgrad_ms": round(1000 * per_og, 4), "line_requests_per_s": round(lines / per_cp, 0),
+                         "cost_product_gbs": round(by / per_cp / 1e9, 1)}
+            log(f"[bench] R-MAT {prec} {name}: {row[name]}")
+        out[prec] = row
+        prob.close()
+        del prob
         torch.cuda.empty_cache()
     return out
 
@@ -362,6 +424,9 @@ def main():
     ap.add_argument("--batch-eps", type=float, default=1e-4)
     ap.add_argument("--kernels", action="store_true", help="also time the edge-family and warm-start kernels")
     ap.add_argument("--completion", action="store_true", help="also the matrix completion instances of Table 2")
+    ap.add_argument("--completion-sigma", type=float, default=0.03, help="penalty for the matrix completion solves")
+    ap.add_argument("--rmat", type=int, default=0, metavar="SCALE",
+                    help="also the skewed-degree leg on an R-MAT graph with 2^SCALE vertices (e.g. 22)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true", help="run a 1 GiB copy kernel first (profiling)")
     args = ap.parse_args()
@@ -460,7 +525,8 @@ def main():
 
     batch = batch_leg(args.batch, args.batch_eps, args.sigma, "f64") if args.batch > 0 else None
     other = kernels_leg(g) if args.kernels else None
-    completion = completion_leg() if args.completion else None
+    completion = completion_leg(sigma=args.completion_sigma) if args.completion else None
+    skewed = rmat_leg(args.rmat) if args.rmat else None
 
     cpu = None if args.no_cpu_baseline else cpu_baseline(args.n, args.deg, args.rank, args.seed)
 
@@ -497,6 +563,8 @@ def main():
         line["other_kernels"] = other
     if completion is not None:
         line["matrix_completion_table2"] = completion
+    if skewed is not None:
+        line["skewed_degree"] = skewed
     print(json.dumps(line), flush=True)
 
 

@@ -252,6 +252,21 @@ alm_bm_status alm_bm_solve(alm_bm_problem* prob, const alm_bm_options* opts, voi
  * choice; different choices sum in different orders.                          */
 alm_bm_status alm_bm_set_tiles(alm_bm_problem* prob, int32_t variant, int32_t row_blocks);
 
+/* Hub rows of a MaxCut-type (DIAG family) CSR cost, for skewed degree
+ * distributions (power-law graphs, Sec. 6.1's MaxCut on general sparse C).  A
+ * row with more than min_degree stored entries is a hub: before each sparse
+ * product C X a kernel with one workgroup per hub sums that row's neighbour
+ * rows with all of the workgroup's lanes, and the row kernels read the sum
+ * instead of walking the row with one lane group.  min_degree: 0 = the
+ * default (16 x the average row length, at least 256, which is what
+ * alm_bm_create applies), > 0 = that threshold, < 0 = no hubs.  hubs: host
+ * int32 out, nullable: the number of hub rows.  Allocates the hub sums
+ * (2 x hubs x 128 values per precision kept) and frees the previous ones after
+ * a device synchronisation; not concurrently with other calls on the handle.
+ * No effect (0 hubs) for the TRACE_EDGES family or an ELL cost; rejected on a
+ * batch.  Results differ from the hub-free pass only in summation order.     */
+alm_bm_status alm_bm_set_hub_threshold(alm_bm_problem* prob, int32_t min_degree, int32_t* hubs);
+
 /* Autotuner: times reps objective/gradient passes at rank r for every
  * (variant, row_blocks) candidate with HIP events on `stream`, keeps the
  * fastest in the handle and returns it (host int32 each, nullable).  Uses the

@@ -252,6 +252,13 @@ class Problem:
     def set_tiles(self, variant=0, row_blocks=0):
         check(lib.alm_bm_set_tiles(self._h, int(variant), int(row_blocks)), "set_tiles")
 
+    def set_hub_threshold(self, min_degree=0):
+        """Rows with more than min_degree entries become hub rows (0: the
+        default threshold, < 0: none); returns the number of hub rows."""
+        h = C.c_int32(0)
+        check(lib.alm_bm_set_hub_threshold(self._h, int(min_degree), C.byref(h)), "set_hub_threshold")
+        return h.value
+
     def autotune(self, r, reps=5, stream=None):
         """Pick the fastest (tile variant, row-kernel grid) for rank r; returns it."""
         v = C.c_int32(0)

@@ -83,6 +83,7 @@ struct alm_bm_problem {
   double* ls = nullptr;
   double* lscal = nullptr;
   std::vector<void*> allocs;
+  std::vector<void*> hub_allocs;  // hub list and sums (also in allocs)
 };
 
 static size_t esize(alm_bm_precision p) { return p == ALM_BM_F64 ? 8 : (p == ALM_BM_F32 ? 4 : 2); }
@@ -115,6 +116,61 @@ template <typename T> static const Cost<typename Acc<T>::type>& cost_of(const al
 template <> const Cost<double>& cost_of<double>(const alm_bm_problem* p) { return p->C64; }
 template <> const Cost<float>& cost_of<float>(const alm_bm_problem* p) { return p->C32; }
 template <> const Cost<float>& cost_of<bf16>(const alm_bm_problem* p) { return p->C32; }
+
+// Rows of the cost with more stored entries than this are hub rows (Cost):
+// 16 times the average row length, at least 256.
+static int32_t hub_threshold(long nnz, long n) {
+  const long avg = (nnz + n - 1) / std::max<long>(1, n);
+  return (int32_t)std::min<long>(INT32_MAX, std::max<long>(256, 16 * avg));
+}
+
+// (Re)build the hub rows of a DIAG-family CSR cost.  min_degree < 0: none;
+// 0: the default threshold; > 0: rows with more than min_degree entries.
+static alm_bm_status build_hubs(alm_bm_problem* p, int32_t min_degree) {
+  const auto& d = p->d;
+  if (!p->hub_allocs.empty()) {
+    HIPCHK(hipDeviceSynchronize());
+    for (void* q : p->hub_allocs) {
+      (void)hipFree(q);
+      p->allocs.erase(std::find(p->allocs.begin(), p->allocs.end(), q));
+    }
+    p->hub_allocs.clear();
+  }
+  for (auto* c : {&p->C64.nh, &p->C32.nh}) *c = 0;
+  if (d.cons_kind != ALM_BM_CONS_DIAG || d.ell_width != 0 || d.nnz == 0 || min_degree < 0) return ALM_BM_OK;
+  const long n = d.n;
+  std::vector<int32_t> hrp(n + 1);
+  HIPCHK(hipMemcpy(hrp.data(), d.row_ptr, (n + 1) * sizeof(int32_t), hipMemcpyDeviceToHost));
+  const int32_t thr = min_degree == 0 ? hub_threshold(d.nnz, n) : min_degree;
+  std::vector<int32_t> hubs;
+  for (long i = 0; i < n; ++i)
+    if (hrp[i + 1] - hrp[i] > thr) hubs.push_back((int32_t)i);
+  if (hubs.empty()) return ALM_BM_OK;
+  const long nh = (long)hubs.size();
+  int32_t* dh = nullptr;
+  double* hs64 = nullptr;
+  STCHK(dalloc_t(p, &dh, nh));
+  p->hub_allocs.push_back(dh);
+  STCHK(dalloc_t(p, &hs64, 2 * nh * kMaxR));
+  p->hub_allocs.push_back(hs64);
+  HIPCHK(hipMemcpy(dh, hubs.data(), nh * sizeof(int32_t), hipMemcpyHostToDevice));
+  p->C64.hthr = thr;
+  p->C64.hrow = dh;
+  p->C64.hsum = hs64;
+  p->C64.hsum2 = hs64 + nh * kMaxR;
+  p->C64.nh = (int32_t)nh;
+  if (d.precision != ALM_BM_F64) {
+    float* hs32 = nullptr;
+    STCHK(dalloc_t(p, &hs32, 2 * nh * kMaxR));
+    p->hub_allocs.push_back(hs32);
+    p->C32.hthr = thr;
+    p->C32.hrow = dh;
+    p->C32.hsum = hs32;
+    p->C32.hsum2 = hs32 + nh * kMaxR;
+    p->C32.nh = (int32_t)nh;
+  }
+  return ALM_BM_OK;
+}
 
 // Run f.template operator()<T>() for the storage type of precision `prec`.
 template <typename F>
@@ -379,6 +435,9 @@ extern "C" alm_bm_status alm_bm_create(const alm_bm_problem_desc* desc, hipStrea
     }
     p->C32 = Cost<float>{n, p->C64.rp, d.col_idx, cv32, p->C64.ell, dg32};
   }
+
+  // ---- hub rows (DIAG family, CSR): skewed degrees
+  CK(build_hubs(p, 0));
 
   // ---- edge adjacency (host build, one upload)
   if (d.cons_kind == ALM_BM_CONS_TRACE_EDGES) {
@@ -747,6 +806,14 @@ extern "C" alm_bm_status alm_bm_set_tiles(alm_bm_problem* p, int32_t variant, in
                                             std::to_string(p->max_blocks) + "]");
   p->variant = variant;
   p->nblk = nb;
+  return ALM_BM_OK;
+}
+
+extern "C" alm_bm_status alm_bm_set_hub_threshold(alm_bm_problem* p, int32_t min_degree, int32_t* hubs_out) {
+  if (!p) return fail(ALM_BM_ERR_INVALID_ARG, "set_hub_threshold: null handle");
+  if (p->tab.inst) return fail(ALM_BM_ERR_UNSUPPORTED, "set_hub_threshold: not on a batch");
+  STCHK(build_hubs(p, min_degree));
+  if (hubs_out) *hubs_out = p->C64.nh;
   return ALM_BM_OK;
 }
 
@@ -1568,6 +1635,8 @@ extern "C" alm_bm_status alm_bm_batch_create(int32_t count, const alm_bm_problem
   sd.lanczos_kmax = kmax_all;
   sd.validate = 0;
   BK(alm_bm_create(&sd, st, &b->p));
+  // per-instance row widths: the hub sums (one stride r) do not apply
+  BK(build_hubs(b->p, -1));
   alm_bm_problem* p = b->p;
   // ---- block table: instance q gets ceil(n_q / rows_per_block) blocks
   const long rpb = std::max<long>(256, (N + 8191) / 8192);

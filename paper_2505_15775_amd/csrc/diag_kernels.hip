@@ -256,6 +256,8 @@ k_ls_diag(Cost<typename Acc<T>::type> C, int r, const T* __restrict__ R, const T
   const int slot = threadIdx.x / LPR;
   SplitAcc<NUM_P, LPR> acc;
   acc.zero();
+  Cost<V> CG = C;  // the product C G reads its hub sums from hsum2
+  CG.hsum = C.hsum2;
   const RowChunk ch = row_chunk(C.n);
   for (long base = ch.lo; base < ch.hi; base += RPB) {
     const long i = base + slot;
@@ -264,7 +266,7 @@ k_ls_diag(Cost<typename Acc<T>::type> C, int r, const T* __restrict__ R, const T
     load_frag<T, VEC, FULL>(R + i * r, lane, r, ri);
     load_frag<T, VEC, FULL>(G + i * r, lane, r, gi);
     spmm_row<T, LPR, VEC, FULL>(C, i, lane, r, R, ri, p);
-    spmm_row<T, LPR, VEC, FULL>(C, i, lane, r, G, gi, q);
+    spmm_row<T, LPR, VEC, FULL>(CG, i, lane, r, G, gi, q);
     V rr = 0, rp = 0, gg = 0, gp = 0, rg = 0, gq = 0;
 #pragma unroll
     for (int v = 0; v < VEC; ++v) {
@@ -305,6 +307,70 @@ k_ls_diag(Cost<typename Acc<T>::type> C, int r, const T* __restrict__ R, const T
 }
 
 // ---- launchers -----------------------------------------------------------------
+
+// Neighbour sums of the hub rows (see Cost): out[h, :] = sum_k S_ik X_k for
+// i = hrow[h], without the diagonal term.  One block per hub: its kBlock/LPR
+// lane groups take every (kBlock/LPR)-th entry of the row with kUnroll gathers
+// in flight each, and the groups' sums are added in group order, so the result
+// does not depend on timing.  The same early exits as the row kernel that
+// consumes the sums (converged flag, non-refresh iterations).
+template <typename T, int LPR, int VEC, bool FULL>
+__global__ void __launch_bounds__(kBlock)
+k_hub_rows(Cost<typename Acc<T>::type> C, int r, const T* __restrict__ X, typename Acc<T>::type* __restrict__ out,
+           const DevScalars* __restrict__ sc, int refresh_every) {
+  using V = typename Acc<T>::type;
+  if (sc && sc->flag) return;
+  if (sc && refresh_every > 1 && (sc->iter % refresh_every) != 0) return;
+  constexpr int NG = kBlock / LPR;
+  constexpr int U = kUnroll;
+  const int lane = threadIdx.x % LPR;
+  const int grp = threadIdx.x / LPR;
+  __shared__ V buf[NG][LPR * VEC];
+  for (long h = blockIdx.x; h < C.nh; h += gridDim.x) {
+    const long i = C.hrow[h];
+    const long k0 = C.rp[i], k1 = C.rp[i + 1];
+    V p[VEC];
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) p[v] = V(0);
+    for (long k = k0 + grp; k < k1; k += (long)NG * U) {
+      V x[U][VEC];
+      V c[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const long kk = k + (long)u * NG;
+        const bool in = kk < k1;
+        const int j = in ? C.ci[kk] : (int)i;
+        c[u] = in ? C.cv[kk] : V(0);
+        load_frag<T, VEC, FULL>(X + (long)j * r, lane, r, x[u]);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) p[v] += c[u] * x[u][v];
+    }
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) buf[grp][lane * VEC + v] = p[v];
+    __syncthreads();
+    for (int c = threadIdx.x; c < r; c += kBlock) {
+      V s = V(0);
+      for (int g = 0; g < NG; ++g) s += buf[g][c];
+      out[h * r + c] = s;
+    }
+    __syncthreads();
+  }
+}
+
+template <typename T, int LPR, int VEC>
+static void launch_hub_cfg(const Cost<typename Acc<T>::type>& C, int r, const T* X, typename Acc<T>::type* out,
+                           const DevScalars* sc, int refresh_every, hipStream_t st) {
+  const int nb = C.nh < 65536 ? C.nh : 65536;
+  if (r == LPR * VEC)
+    hipLaunchKernelGGL((k_hub_rows<T, LPR, VEC, true>), dim3(nb), dim3(kBlock), 0, st, C, r, X, out, sc,
+                       refresh_every);
+  else
+    hipLaunchKernelGGL((k_hub_rows<T, LPR, VEC, false>), dim3(nb), dim3(kBlock), 0, st, C, r, X, out, sc,
+                       refresh_every);
+}
 
 template <typename T, int LPR, int VEC>
 static void launch_objgrad_cfg(const Cost<typename Acc<T>::type>& C, int r, const T* R, const double* y,
@@ -397,9 +463,17 @@ static void launch_ls_cfg(const Cost<typename Acc<T>::type>& C, int r, const T* 
   } while (0)
 
 template <typename T>
+void launch_hub_rows(const Cost<typename Acc<T>::type>& C, int r, int variant, const T* X,
+                     typename Acc<T>::type* out, const DevScalars* sc, int refresh_every, hipStream_t st) {
+  if (C.nh <= 0) return;
+  ALMBM_DISPATCH_DIAG(T, launch_hub_cfg, C, r, X, out, sc, refresh_every, st);
+}
+
+template <typename T>
 void launch_objgrad_diag(const Cost<typename Acc<T>::type>& C, int r, int variant, const T* R, const double* y,
                          const double* b, double sigma, T* G, double* Av, double* part, const DevScalars* sc,
                          int refresh_every, const BlockTab& tab, int nblk, hipStream_t st) {
+  launch_hub_rows<T>(C, r, variant, R, C.hsum, sc, refresh_every, st);
   ALMBM_DISPATCH_DIAG(T, launch_objgrad_cfg, C, r, R, y, b, sigma, G, Av, part, sc, refresh_every, tab, nblk, st);
 }
 
@@ -407,6 +481,7 @@ template <typename T>
 void launch_quadq_diag(const Cost<typename Acc<T>::type>& C, int r, int variant, const T* G,
                        typename Acc<T>::type* Q, double* part, const DevScalars* sc, const BlockTab& tab, int nblk,
                        hipStream_t st) {
+  launch_hub_rows<T>(C, r, variant, G, C.hsum, sc, 0, st);
   ALMBM_DISPATCH_DIAG(T, launch_quadq_cfg, C, r, G, Q, part, sc, tab, nblk, st);
 }
 
@@ -420,12 +495,15 @@ void launch_upd_eval_diag(long n, int r, int variant, T* R, T* G, const typename
 template <typename T>
 void launch_quad_diag(const Cost<typename Acc<T>::type>& C, int r, int variant, const T* G, double* part,
                       const DevScalars* sc, int nblk, hipStream_t st) {
+  launch_hub_rows<T>(C, r, variant, G, C.hsum, sc, 0, st);
   ALMBM_DISPATCH_DIAG(T, launch_quad_cfg, C, r, G, part, sc, nblk, st);
 }
 
 template <typename T>
 void launch_ls_diag(const Cost<typename Acc<T>::type>& C, int r, int variant, const T* R, const T* G,
                     const double* y, const double* b, double* part, int nblk, hipStream_t st) {
+  launch_hub_rows<T>(C, r, variant, R, C.hsum, nullptr, 0, st);
+  launch_hub_rows<T>(C, r, variant, G, C.hsum2, nullptr, 0, st);
   ALMBM_DISPATCH_DIAG(T, launch_ls_cfg, C, r, R, G, y, b, part, nblk, st);
 }
 
@@ -441,7 +519,9 @@ void launch_ls_diag(const Cost<typename Acc<T>::type>& C, int r, int variant, co
   template void launch_quad_diag<T>(const Cost<Acc<T>::type>&, int, int, const T*, double*,               \
                                     const DevScalars*, int, hipStream_t);                                 \
   template void launch_ls_diag<T>(const Cost<Acc<T>::type>&, int, int, const T*, const T*, const double*,  \
-                                  const double*, double*, int, hipStream_t);
+                                  const double*, double*, int, hipStream_t);                              \
+  template void launch_hub_rows<T>(const Cost<Acc<T>::type>&, int, int, const T*, Acc<T>::type*,          \
+                                   const DevScalars*, int, hipStream_t);
 
 ALMBM_INST(double)
 ALMBM_INST(float)

@@ -59,7 +59,30 @@ template <typename V> struct Cost {
   const V* cv;
   int32_t ell;         // > 0: ELL width
   const V* dg;         // nullable
+  // Hub rows (CSR, single instance): the nh rows with more than hthr stored
+  // entries, in increasing order in hrow.  Before a row kernel multiplies C
+  // with X, a block-per-hub kernel writes sum_k S_ik X_k of every hub into
+  // hsum (row h of an nh x r array); the row kernel reads that sum instead of
+  // walking the long row with one lane group.  hsum2 holds the second product
+  // of a kernel that multiplies two operands.
+  int32_t nh = 0;
+  int32_t hthr = 0;
+  const int32_t* hrow = nullptr;
+  V* hsum = nullptr;
+  V* hsum2 = nullptr;
 };
+
+// Position of hub row i in C.hrow (i must be a hub).
+template <typename V>
+__device__ __forceinline__ int hub_index(const Cost<V>& C, long i) {
+  int lo = 0, hi = C.nh - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (C.hrow[mid] < i) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
 
 // Edge family adjacency: symmetric pattern with edge ids, plus the upper
 // (i < j) half in edge order (edge e sits at position e of the upper arrays).

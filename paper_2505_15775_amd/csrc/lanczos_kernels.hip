@@ -3,7 +3,7 @@
 // the matrix-free product, dot products and the full reorthogonalisation
 // (classical Gram-Schmidt applied twice) against the stored basis Q
 // (column-major, n x (k+1), leading dimension ldq).
-#include "kernels.hpp"
+#include "launch.hpp"
 
 namespace almbm {
 
@@ -27,7 +27,11 @@ k_slack_mv(Cost<double> C, int cons_kind, EdgeAdj A, const double* __restrict__ 
     k0 = C.rp[i];
     k1 = C.rp[i + 1];
   }
-  for (long k = k0 + lane; k < k1; k += L) acc += C.cv[k] * x[C.ci[k]];
+  if (C.nh > 0 && k1 - k0 > C.hthr) {  // hub row: sum precomputed by k_hub_rows
+    if (lane == 0) acc = C.hsum[hub_index(C, i)];
+  } else {
+    for (long k = k0 + lane; k < k1; k += L) acc += C.cv[k] * x[C.ci[k]];
+  }
   if (cons_kind == 1) {
     const int a0 = A.rp[i], a1 = A.rp[i + 1];
     for (int k = a0 + lane; k < a1; k += L) acc -= 0.5 * y[1 + A.eid[k]] * x[A.ci[k]];
@@ -258,6 +262,7 @@ int vec_blocks(long n) {
 
 void launch_slack_mv(const Cost<double>& C, int cons_kind, const EdgeAdj& A, const double* y, double c_tr,
                      double j_coef, const DevScalars* sc, const double* x, double* out, hipStream_t st) {
+  if (C.nh > 0) launch_hub_rows<double>(C, 1, 0, x, C.hsum, nullptr, 0, st);
   const long threads = C.n * kSpmvLpr;
   const int nb = (int)((threads + kBlock - 1) / kBlock);
   hipLaunchKernelGGL(k_slack_mv, dim3(nb), dim3(kBlock), 0, st, C, cons_kind, A, y, c_tr, j_coef, sc, x, out);

@@ -5,6 +5,10 @@
 
 namespace almbm {
 
+// Hub-row neighbour sums of C X into out (no-op when C has no hubs).
+template <typename T>
+void launch_hub_rows(const Cost<typename Acc<T>::type>& C, int r, int variant, const T* X,
+                     typename Acc<T>::type* out, const DevScalars* sc, int refresh_every, hipStream_t st);
 template <typename T>
 void launch_objgrad_diag(const Cost<typename Acc<T>::type>& C, int r, int variant, const T* R, const double* y,
                          const double* b, double sigma, T* G, double* Av, double* part, const DevScalars* sc,

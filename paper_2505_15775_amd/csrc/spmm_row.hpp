@@ -33,6 +33,15 @@ __device__ __forceinline__ void spmm_row(const Cost<typename Acc<T>::type>& C, l
     return;
   }
   if (k0 >= k1) return;
+  if (C.nh > 0 && k1 - k0 > C.hthr) {  // hub row: sum precomputed by k_hub_rows
+    const V* hs = C.hsum + (long)hub_index(C, i) * r;
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) {
+      const int c = lane * VEC + v;
+      if (FULL || c < r) p[v] += hs[c];
+    }
+    return;
+  }
   // indices and values of the first chunk; entries past the row end point at
   // row i itself with weight 0 (in bounds, no branch in the gather)
   int j[U];

@@ -1,0 +1,200 @@
+"""Skewed degree distributions (R-MAT graphs, MaxCut costs) on the GPU.
+
+Power-law graphs have a few rows far longer than the rest.  The library
+handles rows with more than 16x the average length (at least 256 entries) as
+hub rows, whose neighbour sums come from a workgroup-per-row kernel.  These
+tests check that path against the oracle in FP64 (1e-10), FP32 and BF16
+against the oracle's product of the stored factor, and that the result matches
+the same handle with hubs switched off or with many more hubs (summation order
+only).  The line search (two products in one kernel), the Lanczos slack
+product, a full solve with the oracle's KKT at the returned point, and a
+sampled full-size case (2^20 vertices) are covered.
+"""
+
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import gen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def almbm():
+    import paper_2505_15775_amd as m
+
+    return m
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+_GRAPHS = {}
+
+
+def rmat(scale):
+    if scale not in _GRAPHS:
+        _GRAPHS[scale] = gen.rmat_graph(scale, 8, 30 + scale, "gauss")
+    return _GRAPHS[scale]
+
+
+def expected_hubs(g):
+    """Rows above the default hub threshold (16x the average row length, at least 256)."""
+    deg = np.bincount(np.concatenate([g.ei, g.ej]), minlength=g.n)
+    avg = -(-2 * g.m_edges // g.n)
+    return int(np.sum(deg > max(256, 16 * avg))), int(deg.max())
+
+
+def problem(g, prec="f64", r_max=16, kmax=0):
+    return almbm().Problem.maxcut(g.n, g.ei, g.ej, g.w, precision=prec, r_max=r_max, lanczos_kmax=kmax, device=DEV,
+                                  validate=False)
+
+
+@pytest.mark.parametrize("scale", [12, 14])
+def test_hub_rows_detected(scale):
+    g = rmat(scale)
+    nh, dmax = expected_hubs(g)
+    print(f"R-MAT 2^{scale}: E={g.m_edges} max degree {dmax} hub rows {nh}", flush=True)
+    assert nh > 0
+    p = problem(g)
+    assert p.set_hub_threshold(0) == nh
+    assert p.set_hub_threshold(-1) == 0
+    assert p.set_hub_threshold(dmax) == 0
+    p.close()
+
+
+@pytest.mark.parametrize("scale,r", [(12, 5), (14, 16), (14, 3)])
+def test_objective_grad_f64(scale, r):
+    g = rmat(scale)
+    rng = np.random.default_rng(scale + r)
+    R = rng.standard_normal((g.n, r))
+    y = rng.standard_normal(g.n)
+    po = oracle.maxcut_sdp(g)
+    f_o, G_o, a_o, _ = oracle.objective_grad(po, R, y, 1.5)
+    p = problem(g)
+    f, G, Av = p.objective_grad(p.factor(R), torch.from_numpy(y).to(DEV), 1.5)
+    torch.cuda.synchronize()
+    print(f"R-MAT 2^{scale} r={r}: rel err f {abs(f.item() - f_o) / abs(f_o):.2e} G {rel(G.cpu(), G_o):.2e}")
+    assert abs(f.item() - f_o) <= 1e-10 * abs(f_o)
+    assert rel(G.cpu(), G_o) <= 1e-10 and rel(Av.cpu(), a_o) <= 1e-10
+    p.close()
+
+
+@pytest.mark.parametrize("r", [1, 8, 16, 33])
+def test_cost_apply_hub_settings_agree(r):
+    """C X with the default hubs, with none and with every row above 8 entries
+    a hub: each against the oracle's product, to 1e-10."""
+    g = rmat(14)
+    X = np.random.default_rng(r).standard_normal((g.n, r))
+    P_o = oracle.cost_apply(oracle.maxcut_sdp(g), X)
+    p = problem(g, r_max=64)
+    Xt = p.factor(X)
+    for thr in (0, -1, 8):
+        nh = p.set_hub_threshold(thr)
+        P, xpx = p.cost_apply(Xt, want_xpx=True)
+        torch.cuda.synchronize()
+        e = rel(P.cpu(), P_o)
+        print(f"cost_apply r={r} hub threshold {thr}: {nh} hubs, rel err {e:.2e}")
+        assert e <= 1e-10
+        x_o = float(np.sum(X * P_o))
+        assert abs(xpx.item() - x_o) <= 1e-10 * float(np.sum(np.abs(X * P_o)))
+    p.close()
+
+
+@pytest.mark.parametrize("prec,bound", [("f32", 1e-6), ("bf16", 1e-2)])
+def test_cost_apply_reduced_precision(prec, bound):
+    g = rmat(14)
+    p = problem(g, prec=prec)
+    Xs = p.factor(np.random.default_rng(3).standard_normal((g.n, 16)))
+    P = p.cost_apply(Xs)
+    torch.cuda.synchronize()
+    P_o = oracle.cost_apply(oracle.maxcut_sdp(g), Xs.double().cpu().numpy())
+    err = rel(P.cpu(), P_o)
+    print(f"R-MAT cost_apply {prec}: rel err vs FP64 product of the stored factor {err:.2e}")
+    assert err <= bound
+    p.close()
+
+
+def test_line_search_f64():
+    g = rmat(14)
+    rng = np.random.default_rng(8)
+    R = rng.standard_normal((g.n, 8))
+    G = rng.standard_normal((g.n, 8))
+    y = rng.standard_normal(g.n)
+    po = oracle.maxcut_sdp(g)
+    p = problem(g)
+    k, t = p.line_search(p.factor(R), p.factor(G), torch.from_numpy(y).to(DEV), 2.0)
+    torch.cuda.synchronize()
+    k_o = oracle.alm.line_search_coeffs(po, R, G, y, 2.0)
+    np.testing.assert_allclose(k.cpu().numpy(), k_o, rtol=1e-9, atol=1e-9 * float(np.max(np.abs(k_o))))
+    p.close()
+
+
+def test_lanczos_min_eig_skewed():
+    g = rmat(12)
+    po = oracle.maxcut_sdp(g)
+    rng = np.random.default_rng(5)
+    deg = np.bincount(np.concatenate([g.ei, g.ej]), minlength=g.n).astype(float)
+    y = -np.sqrt(deg) + 0.3 * rng.standard_normal(g.n)
+    S = oracle.slack_dense(po, y)
+    S = 0.5 * (S + S.T)
+    lam = np.linalg.eigvalsh(S)
+    snorm = float(max(abs(lam[0]), abs(lam[-1])))
+    p = problem(g, r_max=8, kmax=400)
+    theta, v, resid, iters = p.lanczos_min_eig(torch.from_numpy(y).to(DEV), max_iter=400, tol=1e-9 * snorm)
+    vv = v.cpu().numpy()
+    print(f"lanczos R-MAT 2^12: theta {theta:.12e} exact {lam[0]:.12e} resid {resid:.2e} iters {iters}")
+    assert theta >= lam[0] - 1e-10 * snorm
+    assert theta - lam[0] <= 1e-8 * snorm
+    assert math.isclose(resid, np.linalg.norm(S @ vv - theta * vv), rel_tol=1e-6, abs_tol=1e-12 * snorm)
+    p.close()
+
+
+def test_solve_skewed_f64():
+    g = rmat(12)
+    eps = 1e-5
+    p = problem(g, r_max=32, kmax=80)
+    st, res, R, y = p.solve(gen.init_factor(g.n, 4, 2), eps_kkt=eps, max_outer=300, time_limit_s=60)
+    print(f"solve R-MAT 2^12: status {st} outer {res['outer']} inner {res['inner_total']} rank {res['rank']} "
+          f"kkt {res['kkt']:.2e} pobj {res['pobj']:.10e} time {res['time_s']:.2f}s")
+    assert st == 0
+    k = oracle.kkt(oracle.maxcut_sdp(g), R.double().cpu().numpy(), y.cpu().numpy())
+    print(f"oracle KKT at the GPU point: {k['kkt']:.2e}")
+    assert k["kkt"] <= 2 * eps
+    p.close()
+
+
+def test_full_size_objective_grad():
+    """2^20 vertices, 8M edges, r = 16: FP64 objective and gradient against the
+    oracle (1e-10) and the BF16 product of the stored factor (1e-2)."""
+    g = rmat(20)
+    nh, dmax = expected_hubs(g)
+    print(f"R-MAT 2^20: E={g.m_edges} max degree {dmax} hub rows {nh}", flush=True)
+    rng = np.random.default_rng(20)
+    R = rng.standard_normal((g.n, 16)) / 4.0
+    y = rng.standard_normal(g.n)
+    po = oracle.maxcut_sdp(g)
+    f_o, G_o, a_o, _ = oracle.objective_grad(po, R, y, 1.0)
+    p = problem(g)
+    f, G, Av = p.objective_grad(p.factor(R), torch.from_numpy(y).to(DEV), 1.0)
+    torch.cuda.synchronize()
+    ef, eg = abs(f.item() - f_o) / abs(f_o), rel(G.cpu(), G_o)
+    print(f"R-MAT 2^20 f64: rel err f {ef:.2e} G {eg:.2e}")
+    assert ef <= 1e-10 and eg <= 1e-10 and rel(Av.cpu(), a_o) <= 1e-10
+    p.close()
+    pb = problem(g, prec="bf16")
+    Xs = pb.factor(R)
+    P = pb.cost_apply(Xs)
+    torch.cuda.synchronize()
+    err = rel(P.cpu(), oracle.cost_apply(po, Xs.double().cpu().numpy()))
+    print(f"R-MAT 2^20 bf16 cost_apply: rel err {err:.2e}")
+    assert err <= 1e-2
+    pb.close()
