@@ -258,8 +258,8 @@ alm_bm_status alm_bm_set_tiles(alm_bm_problem* prob, int32_t variant, int32_t ro
  * product C X a kernel with one workgroup per hub sums that row's neighbour
  * rows with all of the workgroup's lanes, and the row kernels read the sum
  * instead of walking the row with one lane group.  min_degree: 0 = the
- * default (16 x the average row length, at least 256, which is what
- * alm_bm_create applies), > 0 = that threshold, < 0 = no hubs.  hubs: host
+ * default (twice the average row length rounded up, at least 32, which is
+ * what alm_bm_create applies), > 0 = that threshold, < 0 = no hubs.  hubs: host
  * int32 out, nullable: the number of hub rows.  Allocates the hub sums
  * (2 x hubs x 128 values per precision kept) and frees the previous ones after
  * a device synchronisation; not concurrently with other calls on the handle.

@@ -1,7 +1,7 @@
 """Skewed degree distributions (R-MAT graphs, MaxCut costs) on the GPU.
 
 Power-law graphs have a few rows far longer than the rest.  The library
-handles rows with more than 16x the average length (at least 256 entries) as
+handles rows with more than twice the average length (at least 32 entries) as
 hub rows, whose neighbour sums come from a workgroup-per-row kernel.  These
 tests check that path against the oracle in FP64 (1e-10), FP32 and BF16
 against the oracle's product of the stored factor, and that the result matches
@@ -47,10 +47,10 @@ def rmat(scale):
 
 
 def expected_hubs(g):
-    """Rows above the default hub threshold (16x the average row length, at least 256)."""
+    """Rows above the default hub threshold (twice the average row length, at least 32)."""
     deg = np.bincount(np.concatenate([g.ei, g.ej]), minlength=g.n)
     avg = -(-2 * g.m_edges // g.n)
-    return int(np.sum(deg > max(256, 16 * avg))), int(deg.max())
+    return int(np.sum(deg > max(32, 2 * avg))), int(deg.max())
 
 
 def problem(g, prec="f64", r_max=16, kmax=0):
@@ -159,15 +159,19 @@ def test_lanczos_min_eig_skewed():
 
 
 def test_solve_skewed_f64():
-    g = rmat(12)
+    """A solve on 2^11 vertices (228 hub rows; small enough for the oracle's
+    dense eigensolver in the KKT check)."""
+    g = rmat(11)
+    assert expected_hubs(g)[0] > 0
     eps = 1e-5
-    p = problem(g, r_max=32, kmax=80)
-    st, res, R, y = p.solve(gen.init_factor(g.n, 4, 2), eps_kkt=eps, max_outer=300, time_limit_s=60)
-    print(f"solve R-MAT 2^12: status {st} outer {res['outer']} inner {res['inner_total']} rank {res['rank']} "
-          f"kkt {res['kkt']:.2e} pobj {res['pobj']:.10e} time {res['time_s']:.2f}s")
+    p = problem(g, r_max=48, kmax=80)
+    print("solve R-MAT 2^11 ...", flush=True)
+    st, res, R, y = p.solve(gen.init_factor(g.n, 4, 2), eps_kkt=eps, max_outer=300, time_limit_s=30)
+    print(f"solve R-MAT 2^11: status {st} outer {res['outer']} inner {res['inner_total']} rank {res['rank']} "
+          f"kkt {res['kkt']:.2e} pobj {res['pobj']:.10e} time {res['time_s']:.2f}s", flush=True)
     assert st == 0
     k = oracle.kkt(oracle.maxcut_sdp(g), R.double().cpu().numpy(), y.cpu().numpy())
-    print(f"oracle KKT at the GPU point: {k['kkt']:.2e}")
+    print(f"oracle KKT at the GPU point: {k['kkt']:.2e}", flush=True)
     assert k["kkt"] <= 2 * eps
     p.close()
 
