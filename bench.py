@@ -419,6 +419,8 @@ def main():
     ap.add_argument("--warm", action="store_true", help="also the solve from the learned warm start")
     ap.add_argument("--solve-time-limit", type=float, default=600.0)
     ap.add_argument("--sigma", type=float, default=16.0, help="penalty of the --solve leg")
+    ap.add_argument("--sigma-growth", type=float, default=1.0,
+                    help="penalty schedule of the --solve legs: sigma x this factor whenever pinf falls by less than 4x")
     ap.add_argument("--max-inner", type=int, default=500, help="gradient steps per subproblem in the solve legs")
     ap.add_argument("--batch", type=int, default=0, help="also the batched solve of this many instances vs a loop")
     ap.add_argument("--batch-eps", type=float, default=1e-4)
@@ -494,7 +496,7 @@ def main():
         from paper_2505_15775_amd import warmstart
 
         keys = ("outer", "inner_total", "rank", "kkt", "pinf", "dinf", "gap", "pobj", "time_s", "time_lanczos_s",
-                "promoted_at_outer")
+                "promoted_at_outer", "sigma_final", "sigma_increases")
         legs = []
         if args.solve_f64:
             legs.append(("f64_default_start", "f64", False))
@@ -508,6 +510,8 @@ def main():
                                       device="cuda:0", validate=False)
             opts = dict(eps_kkt=1e-4, sigma=args.sigma, max_inner=args.max_inner, time_limit_s=args.solve_time_limit,
                         verbose=1)
+            if args.sigma_growth != 1.0:
+                opts["sigma_growth"] = args.sigma_growth
             if warm:
                 model = warmstart.WarmStartModel.load(device="cuda:0")
                 st, res, Rf, yf, info = warmstart.solve_warm(ps, model, **opts)
@@ -516,7 +520,8 @@ def main():
             else:
                 st, res, Rf, yf = ps.solve(gen.init_factor(g.n, args.rank, args.seed), **opts)
                 extra = {}
-            solves[name] = {"status": int(st), "sigma": args.sigma, "max_inner": args.max_inner,
+            solves[name] = {"status": int(st), "sigma": args.sigma, "sigma_growth": args.sigma_growth,
+                            "max_inner": args.max_inner,
                             **{k: res[k] for k in keys}, **extra}
             log(f"[bench] {name}: {solves[name]}")
             ps.close()

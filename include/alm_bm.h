@@ -143,6 +143,14 @@ typedef struct {
                                 row keeps sigma); 0 -> sigma.  With tr X fixed the
                                 entries are O(1/n) and the edge rows need a penalty
                                 ~ n sigma to move their multipliers              */
+  double sigma_growth;       /* 1      penalty schedule (off at 1): after an outer
+                                iteration whose primal infeasibility did not fall
+                                below pinf_reduction x the previous one, sigma (and
+                                sigma_edges with it) is multiplied by sigma_growth,
+                                up to sigma_max.  The rule of the SDPLR solver that
+                                Sec. 2 cites; Alg. 1 keeps rho fixed               */
+  double sigma_max;          /* 1e6    cap of the schedule                             */
+  double pinf_reduction;     /* 0.25   required decrease of pinf per outer iteration  */
 } alm_bm_options;
 
 typedef struct {
@@ -158,6 +166,9 @@ typedef struct {
   double time_lanczos_s;     /* of which in Lanczos                                   */
   int32_t promoted_at_outer; /* BF16 ladder switch point (-1 = none)                  */
   double time_promoted_s;    /* wall time spent after the switch                       */
+  double sigma_final;        /* penalty at the end (differs from sigma only with the
+                                schedule)                                              */
+  int32_t sigma_increases;   /* schedule steps taken                                   */
 } alm_bm_result;
 
 /* --------------------------------------------------------------------------- */

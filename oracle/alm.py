@@ -60,6 +60,13 @@ class SolveOptions:
     inner_tol_decay: float = 0.7   # kappa
     expand_needs_inner: bool = False  # True: expand only after an inner solve met its tolerance
     sigma_edges: Optional[float] = None  # edges family: penalty of the edge rows (trace row keeps sigma)
+    # penalty schedule (off at growth 1): after an outer iteration whose pinf is
+    # above pinf_reduction times the previous one, sigma *= sigma_growth (every
+    # row's penalty, capped at sigma_max for the base penalty).  This is the
+    # update of the SDPLR solver the paper cites (Sec. 2); Alg. 1 keeps rho fixed.
+    sigma_growth: float = 1.0
+    sigma_max: float = 1e6
+    pinf_reduction: float = 0.25
 
 
 def line_search_coeffs(p, R, G, y, sigma, P=None, a=None):
@@ -190,13 +197,19 @@ def solve(p, R0, y0=None, opts=None, callback=None):
         y = w
         lam = theta if not expanded else min_eig(p, y)
         info = kkt(p, R, y, lam_min=lam)
+        base = float(np.atleast_1d(sigma)[0])
         info.update({"outer": k, "inner_iters": inner["iters"], "rank": R.shape[1],
-                     "expanded": expanded, "theta": theta, "f": inner["f"]})
+                     "expanded": expanded, "theta": theta, "f": inner["f"], "sigma": base})
         hist.append(info)
         if callback is not None:
             callback(info)
+        pinf_last = pinf_prev
         pinf_prev = info["pinf"]
         if info["kkt"] <= opts.eps_kkt:
             status = "converged"
             break
+        if opts.sigma_growth > 1.0 and info["pinf"] > opts.pinf_reduction * pinf_last:
+            sigma0 = float(np.atleast_1d(sigma)[0])
+            if sigma0 < opts.sigma_max:
+                sigma = sigma * (min(opts.sigma_max, sigma0 * opts.sigma_growth) / sigma0)
     return {"R": R, "y": y, "status": status, "history": hist, "kkt": info}

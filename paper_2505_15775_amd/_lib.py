@@ -78,6 +78,9 @@ class Options(C.Structure):
         ("refresh_every", C.c_int32),
         ("lanczos_restarts", C.c_int32),
         ("sigma_edges", C.c_double),
+        ("sigma_growth", C.c_double),
+        ("sigma_max", C.c_double),
+        ("pinf_reduction", C.c_double),
     ]
 
 
@@ -98,6 +101,8 @@ class Result(C.Structure):
         ("time_lanczos_s", C.c_double),
         ("promoted_at_outer", C.c_int32),
         ("time_promoted_s", C.c_double),
+        ("sigma_final", C.c_double),
+        ("sigma_increases", C.c_int32),
     ]
 
     def as_dict(self):

@@ -303,6 +303,9 @@ extern "C" void alm_bm_default_options(alm_bm_options* o) {
   o->refresh_every = 0;
   o->lanczos_restarts = 3;
   o->sigma_edges = 0.0;
+  o->sigma_growth = 1.0;
+  o->sigma_max = 1e6;
+  o->pinf_reduction = 0.25;
 }
 
 extern "C" const char* alm_bm_last_error(void) { return g_err.c_str(); }
@@ -1230,10 +1233,9 @@ template <typename T>
 static alm_bm_status solve_impl(alm_bm_problem* p, const alm_bm_options& o, T* R, double* y, hipStream_t st,
                                 int& r, int& w, int k_start, int& k_done,
                                 bool stop_on_stall, bool& stalled, double t0, double& pinf_prev, double& tol_prev,
-                                alm_bm_result& acc) {
+                                double& sigma, alm_bm_result& acc) {
   const auto& d = p->d;
   const long n = d.n;
-  const double sigma = o.sigma;
   const double tau_rank = o.tau_rank > 0.0 ? o.tau_rank : o.eps_kkt * (1.0 + p->cnorm);
   int r_cap = std::min<int>(d.r_max, bp_rank_cap(d.m));
   if (o.r_cap > 0) r_cap = std::min(r_cap, o.r_cap);
@@ -1243,6 +1245,7 @@ static alm_bm_status solve_impl(alm_bm_problem* p, const alm_bm_options& o, T* R
   stalled = false;
   std::vector<double> pinf_hist;
   for (int k = k_start; k < o.max_outer; ++k) {
+    const double pinf_last = pinf_prev;  // of the previous outer iteration (inf at the start)
     const double tol = std::max(o.eps_kkt / 10.0, std::min(o.inner_tol_scale, std::min(pinf_prev, o.inner_tol_decay * tol_prev)));
     tol_prev = tol;
     int iters = 0, flag = 0;
@@ -1318,9 +1321,16 @@ static alm_bm_status solve_impl(alm_bm_problem* p, const alm_bm_options& o, T* R
     if (o.verbose)
       std::fprintf(stderr,
                    "[almbm] k=%d inner=%d flag=%d r=%d theta=%.3e lanczos=%d pinf=%.3e dinf=%.3e gap=%.3e "
-                   "pobj=%.10e t=%.2fs\n",
-                   k, iters, flag, r, lo.theta, lo.iters, kv.pinf, kv.dinf, kv.gap, kv.pobj, now_s() - t0);
+                   "pobj=%.10e sigma=%.3e t=%.2fs\n",
+                   k, iters, flag, r, lo.theta, lo.iters, kv.pinf, kv.dinf, kv.gap, kv.pobj, sigma, now_s() - t0);
     if (kv.kkt <= o.eps_kkt) return ALM_BM_OK;
+    // penalty schedule: raise sigma when the infeasibility did not fall enough
+    if (o.sigma_growth > 1.0 && kv.pinf > o.pinf_reduction * pinf_last && sigma < o.sigma_max) {
+      sigma = std::min(o.sigma_max, sigma * o.sigma_growth);
+      acc.sigma_final = sigma;
+      acc.sigma_increases += 1;
+      gc.reset();  // the captured inner loop holds sigma as a kernel argument
+    }
     if (o.time_limit_s > 0.0 && now_s() - t0 > o.time_limit_s) return ALM_BM_NOT_CONVERGED;
     if (stop_on_stall) {
       // storage-precision floor: primal infeasibility no longer falls by 2x over 3 outer iterations
@@ -1380,6 +1390,8 @@ extern "C" alm_bm_status alm_bm_solve(alm_bm_problem* p, const alm_bm_options* o
     return fail(ALM_BM_ERR_INVALID_ARG, "solve: sigma, eps_kkt, max_outer and max_inner must be positive");
   if (p->kmax < 1) return fail(ALM_BM_ERR_INVALID_ARG, "solve: the handle has no Lanczos workspace");
   if (o.sigma_edges < 0.0) return fail(ALM_BM_ERR_INVALID_ARG, "solve: sigma_edges must be >= 0");
+  if (!(o.sigma_growth >= 1.0) || !(o.sigma_max >= o.sigma) || !(o.pinf_reduction > 0.0 && o.pinf_reduction <= 1.0))
+    return fail(ALM_BM_ERR_INVALID_ARG, "solve: need sigma_growth >= 1, sigma_max >= sigma, 0 < pinf_reduction <= 1");
   HIPCHK(hipStreamSynchronize(st_user));
   hipStream_t st = p->ss;
   // penalty of the edge rows relative to sigma, for the length of this solve
@@ -1395,12 +1407,14 @@ extern "C" alm_bm_status alm_bm_solve(alm_bm_problem* p, const alm_bm_options* o
   int w = pad_width(r, p->d.r_max);
   int k_done = 0;
   double pinf_prev = INFINITY, tol_prev = INFINITY;
+  double sigma = o.sigma;
+  acc.sigma_final = sigma;
   bool stalled = false;
   alm_bm_status s;
   if (p->d.precision == ALM_BM_BF16 && o.bf16_promote) {
     bf16* Rb = static_cast<bf16*>(R);
     STCHK(restride<bf16>(p, Rb, r, r, w, st));
-    s = solve_impl<bf16>(p, o, Rb, y, st, r, w, 0, k_done, true, stalled, t0, pinf_prev, tol_prev, acc);
+    s = solve_impl<bf16>(p, o, Rb, y, st, r, w, 0, k_done, true, stalled, t0, pinf_prev, tol_prev, sigma, acc);
     if (s >= 0 && stalled) {
       // precision ladder: continue with float storage (the float cost copy is resident)
       const long n = p->d.n;
@@ -1418,7 +1432,7 @@ extern "C" alm_bm_status alm_bm_solve(alm_bm_problem* p, const alm_bm_options* o
       p->Rtmp = p->Rt32;
       const double tp = now_s();
       acc.promoted_at_outer = k_done;
-      s = solve_impl<float>(p, o, Rf, y, st, r, w, k_done, k_done, false, stalled, t0, pinf_prev, tol_prev, acc);
+      s = solve_impl<float>(p, o, Rf, y, st, r, w, k_done, k_done, false, stalled, t0, pinf_prev, tol_prev, sigma, acc);
       alm_bm_status s2 = restride<float>(p, Rf, w, r, r, st);
       p->G = Gsave;
       p->Rtmp = Rtsave;
@@ -1436,7 +1450,7 @@ extern "C" alm_bm_status alm_bm_solve(alm_bm_problem* p, const alm_bm_options* o
       T* Rt = static_cast<T*>(R);
       alm_bm_status s1 = restride<T>(p, Rt, r, r, w, st);
       if (s1 < 0) return s1;
-      s1 = solve_impl<T>(p, o, Rt, y, st, r, w, 0, k_done, false, stalled, t0, pinf_prev, tol_prev, acc);
+      s1 = solve_impl<T>(p, o, Rt, y, st, r, w, 0, k_done, false, stalled, t0, pinf_prev, tol_prev, sigma, acc);
       const alm_bm_status s2 = restride<T>(p, Rt, w, r, r, st);
       return s1 < 0 ? s1 : (s2 < 0 ? s2 : s1);
     });
@@ -2175,6 +2189,8 @@ extern "C" alm_bm_status alm_bm_batch_solve(alm_bm_batch* b, const alm_bm_option
   else alm_bm_default_options(&o);
   if (!(o.sigma > 0.0) || !(o.eps_kkt > 0.0) || o.max_outer < 1 || o.max_inner < 1)
     return fail(ALM_BM_ERR_INVALID_ARG, "batch_solve: sigma, eps_kkt, max_outer and max_inner must be positive");
+  if (o.sigma_growth != 1.0)
+    return fail(ALM_BM_ERR_UNSUPPORTED, "batch_solve: the penalty schedule (sigma_growth) is for single solves");
   HIPCHK(hipStreamSynchronize(st_user));
   hipStream_t st = b->p->ss;
   alm_bm_status s = with_storage(b->p->d.precision, [&]<typename T>() {

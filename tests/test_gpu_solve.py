@@ -157,3 +157,43 @@ def test_solve_lovasz_random_graph_with_edge_penalty_oracle_kkt():
     k = oracle.kkt(po, R.cpu().numpy(), y.cpu().numpy())
     print(f"oracle KKT at the GPU point: {k}")
     assert k["kkt"] <= 2e-4
+
+
+@pytest.mark.parametrize("n", [9, 64])
+def test_penalty_schedule_cycles_closed_form(n):
+    """Penalty schedule from sigma = 1e-3 (x10 whenever pinf falls by less than
+    4x): the closed form is reached and the penalty only grew."""
+    g = gen.cycle_graph(n)
+    prob = _maxcut(g, r_max=8, kmax=min(n, 60))
+    st, res, R, y = prob.solve(gen.init_factor(n, 2, 1), eps_kkt=1e-8, sigma=1e-3, sigma_growth=10.0,
+                               max_outer=400, max_inner=2000)
+    val = -res["pobj"]
+    expect = n if n % 2 == 0 else n * (1 + math.cos(math.pi / n)) / 2
+    print(f"cycle {n} with schedule: status {st} value {val:.12f} expect {expect:.12f} outer {res['outer']} "
+          f"sigma {res['sigma_final']:.1e} ({res['sigma_increases']} increases)")
+    assert st == 0
+    assert math.isclose(val, expect, rel_tol=1e-6)
+    assert res["sigma_increases"] >= 1 and res["sigma_final"] > 1e-3
+
+
+def test_penalty_schedule_er_workload():
+    """G(2000, 10^4): the scheduled solve from sigma = 1e-2 and the fixed
+    sigma = 1 solve reach the same objective, and the oracle's KKT at the
+    scheduled solve's point meets the tolerance."""
+    g = gen.er_graph(2000, 10000, 1, "unit")
+    eps = 1e-6
+    out = {}
+    for name, kw in (("fixed", {}), ("schedule", {"sigma": 1e-2, "sigma_growth": 4.0})):
+        prob = _maxcut(g, r_max=48, kmax=100)
+        st, res, R, y = prob.solve(gen.init_factor(g.n, 8, 1), eps_kkt=eps, max_outer=500, **kw)
+        print(f"ER 2000 {name}: status {st} outer {res['outer']} inner {res['inner_total']} rank {res['rank']} "
+              f"pobj {res['pobj']:.12e} sigma {res['sigma_final']:.2e} time {res['time_s']:.2f}s", flush=True)
+        assert st == 0
+        out[name] = (res, R, y)
+    d = abs(out["schedule"][0]["pobj"] - out["fixed"][0]["pobj"]) / abs(out["fixed"][0]["pobj"])
+    assert d <= 1e-5
+    assert out["schedule"][0]["sigma_increases"] >= 1
+    _, R, y = out["schedule"]
+    k = _oracle_kkt(oracle.maxcut_sdp(g), R.double().cpu().numpy(), y.cpu().numpy())
+    print(f"oracle KKT at the scheduled solve's point: {k['kkt']:.2e}")
+    assert k["kkt"] <= 2 * eps

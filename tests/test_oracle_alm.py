@@ -244,3 +244,28 @@ def test_rank_step_with_one_penalty_per_constraint():
 def test_lovasz_theta_cycles_with_edge_penalty(n, expect):
     val, _ = _solve_value(oracle.lovasz_sdp(gen.cycle_graph(n)), 3, eps=1e-6, sigma_edges=float(n))
     assert math.isclose(val, expect, rel_tol=1e-5)
+
+
+@pytest.mark.parametrize("n", [7, 9])
+def test_penalty_schedule_odd_cycle(n):
+    """Started at a penalty far too small to move the multipliers, the schedule
+    (sigma x10 whenever pinf falls by less than 4x) still reaches the closed
+    form, with a non-decreasing penalty; without it the penalty stays put."""
+    p = oracle.maxcut_sdp(gen.cycle_graph(n))
+    val, out = _solve_value(p, 2, eps=1e-7, sigma=1e-3, sigma_growth=10.0)
+    assert math.isclose(val, n * (1 + math.cos(math.pi / n)) / 2, rel_tol=1e-6)
+    s = [h["sigma"] for h in out["history"]]
+    assert s[0] == 1e-3 and s[-1] > s[0]
+    assert all(b >= a for a, b in zip(s, s[1:]))
+    _, fixed = _solve_value(p, 2, eps=1e-7)
+    assert {h["sigma"] for h in fixed["history"]} == {1.0}
+
+
+def test_penalty_schedule_keeps_the_edge_ratio():
+    """Lovasz theta of C5 with one penalty for the trace row and another for
+    the edge rows: the schedule scales both, keeping their ratio (here 5)."""
+    val, out = _solve_value(oracle.lovasz_sdp(gen.cycle_graph(5)), 3, eps=1e-6, sigma=0.01, sigma_edges=0.05,
+                            sigma_growth=10.0, sigma_max=100.0)
+    assert math.isclose(val, math.sqrt(5.0), rel_tol=1e-5)
+    s = [h["sigma"] for h in out["history"]]
+    assert s[-1] > s[0] and max(s) <= 100.0
