@@ -77,7 +77,7 @@ def time_events(fn, iters):
     return s.elapsed_time(e) / 1000.0
 
 
-def bench_mode(g, prec, r, steps, warmup, seed):
+def bench_mode(g, prec, r, steps, warmup, seed, refresh_every=0):
     import torch
 
     import gen
@@ -98,10 +98,10 @@ def bench_mode(g, prec, r, steps, warmup, seed):
 
     # the solve's inner loop (graph-captured, one sparse product per step between
     # refreshes), run for a fixed number of steps (tolerance 0: never stops early)
-    prob.inner_solve(R, y, 0.0, warmup, sigma=sigma)
+    prob.inner_solve(R, y, 0.0, warmup, sigma=sigma, refresh_every=refresh_every)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    done, flag, f_last = prob.inner_solve(R, y, 0.0, steps, sigma=sigma)
+    done, flag, f_last = prob.inner_solve(R, y, 0.0, steps, sigma=sigma, refresh_every=refresh_every)
     el = time.perf_counter() - t1
     assert done == steps and flag == 2, (done, flag)
     log(f"[bench] {prec}: {steps} inner steps in {el:.3f}s, f={f_last:.6e}")
@@ -419,6 +419,8 @@ def main():
     ap.add_argument("--warm", action="store_true", help="also the solve from the learned warm start")
     ap.add_argument("--solve-time-limit", type=float, default=600.0)
     ap.add_argument("--sigma", type=float, default=16.0, help="penalty of the --solve leg")
+    ap.add_argument("--refresh-every", type=int, default=0,
+                    help="inner steps between full sparse evaluations (0: the library default for the precision)")
     ap.add_argument("--sigma-growth", type=float, default=1.0,
                     help="penalty schedule of the --solve legs: sigma x this factor whenever pinf falls by less than 4x")
     ap.add_argument("--max-inner", type=int, default=500, help="gradient steps per subproblem in the solve legs")
@@ -450,7 +452,8 @@ def main():
     g = gen.er_graph(args.n, M, args.seed, "gauss")
     log(f"[bench] graph n={g.n} M={g.m_edges} generated in {time.time() - t0:.1f}s")
 
-    prob, R, y, main_out = bench_mode(g, args.precision, args.rank, args.steps, args.warmup, args.seed)
+    prob, R, y, main_out = bench_mode(g, args.precision, args.rank, args.steps, args.warmup, args.seed,
+                                      args.refresh_every)
     per_outer = per_outer_rows(prob, y, 20)
     modes = {}
     if args.modes:
@@ -512,6 +515,8 @@ def main():
                         verbose=1)
             if args.sigma_growth != 1.0:
                 opts["sigma_growth"] = args.sigma_growth
+            if args.refresh_every:
+                opts["refresh_every"] = args.refresh_every
             if warm:
                 model = warmstart.WarmStartModel.load(device="cuda:0")
                 st, res, Rf, yf, info = warmstart.solve_warm(ps, model, **opts)

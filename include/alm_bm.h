@@ -134,7 +134,7 @@ typedef struct {
   int32_t verbose;           /* 0      1: one line per outer iteration on stderr      */
   double time_limit_s;       /* 0      > 0: stop (NOT_CONVERGED) after this wall time  */
   int32_t bf16_promote;      /* 1      BF16 handle: ladder to float storage when stalled */
-  int32_t refresh_every;     /* 0 -> 32 (F64), 16 (F32), 4 (BF16): inner steps between
+  int32_t refresh_every;     /* 0 -> 32 (F64), 16 (F32), 8 (BF16): inner steps between
                                 full sparse evaluations of C R; in between, C R is
                                 carried as C R - t C G (1 = always recompute)      */
   int32_t lanczos_restarts;  /* 3      restarts from the Ritz vector while the Ritz

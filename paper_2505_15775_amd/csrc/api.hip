@@ -598,7 +598,7 @@ static void enqueue_inner_step(alm_bm_problem* p, int r, T* R, const double* y, 
 }
 
 static int default_refresh(alm_bm_precision prec) {
-  return prec == ALM_BM_F64 ? 32 : (prec == ALM_BM_F32 ? 16 : 4);
+  return prec == ALM_BM_F64 ? 32 : (prec == ALM_BM_F32 ? 16 : 8);
 }
 
 static alm_bm_status check_r(const alm_bm_problem* p, int r) {
