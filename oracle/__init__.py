@@ -24,6 +24,7 @@ from .sdp import (  # noqa: F401
     generic_sdp,
     cost_apply,
     cost_fro_norm,
+    min_eigs,
     amap,
     amap_uv,
     adjoint_apply,
@@ -43,6 +44,7 @@ from .alm import (  # noqa: F401
     quartic_argmin,
     inner_gd,
     solve,
+    curvature_step,
 )
 from .dense_alm import dense_alm  # noqa: F401
 from . import warmstart  # noqa: F401

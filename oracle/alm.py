@@ -41,8 +41,8 @@ from typing import Optional
 
 import numpy as np
 
-from .sdp import (amap, amap_uv, cost_apply, cost_fro_norm, kkt, min_eig,
-                  objective_grad, rank_one_norm2)
+from .sdp import (amap, amap_uv, cost_apply, cost_fro_norm, kkt, min_eig, min_eigs,
+                  objective_grad, rank_one_norm2, slack_matvec)
 
 
 @dataclass
@@ -67,6 +67,10 @@ class SolveOptions:
     sigma_growth: float = 1.0
     sigma_max: float = 1e6
     pinf_reduction: float = 0.25
+    # rank step from the rank_block most negative eigenvectors of the slack at
+    # w and the small PSD subproblem of Alg. 1 (curvature_step); 1 = the
+    # closed-form one-vector step
+    rank_block: int = 1
 
 
 def line_search_coeffs(p, R, G, y, sigma, P=None, a=None):
@@ -151,6 +155,93 @@ def inner_gd(p, R, y, sigma, tol, max_inner, step_rule="exact", eta_fixed=1e-3):
     return R, {"iters": max_inner, "f": f, "gnorm": gnorm, "converged": False}
 
 
+def _psd_part(M):
+    lam, U = np.linalg.eigh(0.5 * (M + M.T))
+    return (U * np.maximum(lam, 0.0)) @ U.T
+
+
+def curvature_step(p, w, sigma, V, max_iter=200000, tol=1e-12):
+    """The negative-curvature subproblem of Alg. 1 (Sec. 5).
+
+    With X = R R^T fixed, w = y - sigma (A(X) - b) and V (n x q) orthonormal
+    directions, the augmented Lagrangian of X + V S V^T exceeds that of X by
+        phi(S) = <V^T (C - A*(w)) V, S> + 1/2 sum_i sigma_i A_i(V S V^T)^2
+    exactly (the penalty is quadratic in X).  This minimises phi over S PSD by
+    accelerated projected gradient (FISTA with monotone restarts, step 1/L,
+    projection = eigenvalue clipping) until the fixed-point residual
+    ||S - P(S - grad/L)||_F is below tol (1 + ||S||_F).  Returns (S, phi(S),
+    new columns V S^{1/2} of the factor, n x rank(S)).  When A(V S V^T)
+    vanishes for every S the subproblem is linear: S = 0 (no step).
+    """
+    V = np.asarray(V, dtype=np.float64)
+    if V.ndim == 1:
+        V = V[:, None]
+    n, q = V.shape
+    sig = np.broadcast_to(np.asarray(sigma, dtype=np.float64), (p.m,))
+    G0 = V.T @ np.column_stack([slack_matvec(p, w, V[:, j]) for j in range(q)])
+    G0 = 0.5 * (G0 + G0.T)
+    # images A(v_k v_l^T) of the matrix units (symmetric in k, l)
+    img = {(k, l): amap_uv(p, V[:, k], V[:, l]) for k in range(q) for l in range(k, q)}
+
+    def bmap(S):
+        z = np.zeros(p.m)
+        for (k, l), a_kl in img.items():
+            z += (S[k, l] if k == l else 2.0 * S[k, l]) * a_kl
+        return z
+
+    def badj(z):
+        M = np.empty((q, q))
+        for (k, l), a_kl in img.items():
+            M[k, l] = M[l, k] = float(np.dot(z, a_kl))
+        return M
+
+    def phi(S):
+        z = bmap(S)
+        return float(np.sum(G0 * S)) + 0.5 * float(np.dot(sig * z, z))
+
+    def grad(S):
+        return G0 + badj(sig * bmap(S))
+
+    # Lipschitz constant: the largest eigenvalue of the Hessian S -> B*(sigma B(S))
+    # in an orthonormal basis of the symmetric q x q matrices
+    basis = []
+    for k in range(q):
+        for l in range(k, q):
+            E = np.zeros((q, q))
+            if k == l:
+                E[k, k] = 1.0
+            else:
+                E[k, l] = E[l, k] = 1.0 / math.sqrt(2.0)
+            basis.append(E)
+    H = np.array([[float(np.sum(Ei * badj(sig * bmap(Ej)))) for Ej in basis] for Ei in basis])
+    L = float(np.max(np.linalg.eigvalsh(0.5 * (H + H.T)))) if basis else 0.0
+    if not L > 0.0:
+        S = np.zeros((q, q))
+        return S, 0.0, np.zeros((n, 0))
+    S = np.zeros((q, q))
+    Y = S.copy()
+    t = 1.0
+    f_S = phi(S)
+    for _ in range(max_iter):
+        S_new = _psd_part(Y - grad(Y) / L)
+        f_new = phi(S_new)
+        if f_new > f_S:  # restart: plain projected gradient step from S
+            Y = S.copy()
+            t = 1.0
+            S_new = _psd_part(S - grad(S) / L)
+            f_new = phi(S_new)
+        t_new = 0.5 * (1.0 + math.sqrt(1.0 + 4.0 * t * t))
+        Y = S_new + ((t - 1.0) / t_new) * (S_new - S)
+        S, f_S, t = S_new, f_new, t_new
+        res = np.linalg.norm(S - _psd_part(S - grad(S) / L))
+        if res <= tol * (1.0 + np.linalg.norm(S)):
+            break
+    lam, U = np.linalg.eigh(0.5 * (S + S.T))
+    keep = lam > 1e-14 * max(float(np.max(lam)), 1e-300)
+    cols = V @ (U[:, keep] * np.sqrt(lam[keep]))
+    return S, phi(S), cols
+
+
 def bp_rank_cap(m):
     """Largest r with r(r+1)/2 <= m (Barvinok-Pataki bound, Sec. 3.3)."""
     return int((math.isqrt(8 * m + 1) - 1) // 2)
@@ -182,7 +273,21 @@ def solve(p, R0, y0=None, opts=None, callback=None):
         a = amap(p, R)
         w = y - sigma * (a - p.b)
         expanded = False
-        if opts.rank_policy == "adapt":
+        if opts.rank_policy == "adapt" and opts.rank_block > 1:
+            q = min(opts.rank_block, p.n)
+            thetas, Vq = min_eigs(p, w, q)
+            theta = float(thetas[0])
+            gate = inner["converged"] or not opts.expand_needs_inner
+            neg = thetas < -tau_rank
+            if gate and np.any(neg) and R.shape[1] < r_cap:
+                _, _, cols = curvature_step(p, w, sigma, Vq[:, neg])
+                cols = cols[:, :r_cap - R.shape[1]]
+                if cols.shape[1] > 0:
+                    R = np.concatenate([R, cols], axis=1)
+                    a = amap(p, R)
+                    w = y - sigma * (a - p.b)
+                    expanded = True
+        elif opts.rank_policy == "adapt":
             theta, v = min_eig(p, w, want_vector=True)
             gate = inner["converged"] or not opts.expand_needs_inner
             if gate and theta < -tau_rank and R.shape[1] < r_cap:

@@ -249,6 +249,22 @@ def min_eig(p, y, want_vector=False, dense_limit=4000):
     return float(vals[0])
 
 
+def min_eigs(p, y, q, dense_limit=4000):
+    """The q smallest eigenpairs of C - A*(y), ascending: (values, n x q unit
+    eigenvectors).  Dense LAPACK up to ``dense_limit``, ARPACK above it."""
+    q = int(min(q, p.n))
+    if p.n <= dense_limit:
+        S = slack_dense(p, y)
+        vals, vecs = np.linalg.eigh(0.5 * (S + S.T))
+        return vals[:q].copy(), vecs[:, :q].copy()
+    op = spla.LinearOperator((p.n, p.n), matvec=lambda x: slack_matvec(p, y, x), dtype=np.float64)
+    rng = np.random.default_rng(12345)
+    vals, vecs = spla.eigsh(op, k=q, which="SA", tol=1e-12, v0=rng.standard_normal(p.n),
+                            ncv=min(p.n, max(64, 4 * q)), maxiter=100000)
+    order = np.argsort(vals)
+    return vals[order], vecs[:, order]
+
+
 def kkt(p, R, y, lam_min=None):
     """Relative KKT measure of Sec. 6 at X = R R^T (l2 norms):
 
