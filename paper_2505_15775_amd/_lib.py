@@ -81,6 +81,7 @@ class Options(C.Structure):
         ("sigma_growth", C.c_double),
         ("sigma_max", C.c_double),
         ("pinf_reduction", C.c_double),
+        ("rank_block", C.c_int32),
     ]
 
 

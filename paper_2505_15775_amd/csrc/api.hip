@@ -84,6 +84,9 @@ struct alm_bm_problem {
   double* lscal = nullptr;
   std::vector<void*> allocs;
   std::vector<void*> hub_allocs;  // hub list and sums (also in allocs)
+  double* vblk = nullptr;         // block rank step: n x 8 directions, their coefficients, Gram partials
+  double* ycoef = nullptr;
+  double* gpart = nullptr;
 };
 
 static size_t esize(alm_bm_precision p) { return p == ALM_BM_F64 ? 8 : (p == ALM_BM_F32 ? 4 : 2); }
@@ -306,6 +309,7 @@ extern "C" void alm_bm_default_options(alm_bm_options* o) {
   o->sigma_growth = 1.0;
   o->sigma_max = 1e6;
   o->pinf_reduction = 0.25;
+  o->rank_block = 1;
 }
 
 extern "C" const char* alm_bm_last_error(void) { return g_err.c_str(); }
@@ -974,6 +978,161 @@ static void tri_eigvec(const std::vector<double>& a, const std::vector<double>& 
   }
 }
 
+// (k+1)-th smallest eigenvalue of the symmetric tridiagonal by bisection on
+// the Sturm count.
+static double tri_kth_eig(const std::vector<double>& a, const std::vector<double>& b, int m, int k) {
+  double lo = INFINITY, hi = -INFINITY;
+  for (int i = 0; i < m; ++i) {
+    const double rad = (i > 0 ? std::fabs(b[i - 1]) : 0.0) + (i + 1 < m ? std::fabs(b[i]) : 0.0);
+    lo = std::min(lo, a[i] - rad);
+    hi = std::max(hi, a[i] + rad);
+  }
+  const double scale = std::max(std::fabs(lo), std::fabs(hi));
+  for (int it = 0; it < 300; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (hi - lo <= 2.0 * DBL_EPSILON * scale || mid <= lo || mid >= hi) break;
+    if (sturm_count(a, b, m, mid) >= k + 1) hi = mid;
+    else lo = mid;
+  }
+  return 0.5 * (lo + hi);
+}
+
+// Eigen-decomposition of a small symmetric q x q matrix (row-major) by cyclic
+// Jacobi rotations: A = U diag(lam) U^T, U row-major with eigenvectors in columns.
+static void small_sym_eig(int q, std::vector<double> A, std::vector<double>& lam, std::vector<double>& U) {
+  U.assign(q * q, 0.0);
+  for (int i = 0; i < q; ++i) U[i * q + i] = 1.0;
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int i = 0; i < q; ++i)
+      for (int j = 0; j < q; ++j) {
+        tot += A[i * q + j] * A[i * q + j];
+        if (i != j) off += A[i * q + j] * A[i * q + j];
+      }
+    if (off <= 1e-30 * std::max(tot, 1e-300)) break;
+    for (int p0 = 0; p0 < q; ++p0)
+      for (int q0 = p0 + 1; q0 < q; ++q0) {
+        const double apq = A[p0 * q + q0];
+        if (apq == 0.0) continue;
+        const double tau = (A[q0 * q + q0] - A[p0 * q + p0]) / (2.0 * apq);
+        const double t = (tau >= 0 ? 1.0 : -1.0) / (std::fabs(tau) + std::sqrt(1.0 + tau * tau));
+        const double c = 1.0 / std::sqrt(1.0 + t * t), s = t * c;
+        for (int k = 0; k < q; ++k) {  // A <- A J (columns p0, q0)
+          const double akp = A[k * q + p0], akq = A[k * q + q0];
+          A[k * q + p0] = c * akp - s * akq;
+          A[k * q + q0] = s * akp + c * akq;
+        }
+        for (int k = 0; k < q; ++k) {  // A <- J^T A (rows p0, q0)
+          const double apk = A[p0 * q + k], aqk = A[q0 * q + k];
+          A[p0 * q + k] = c * apk - s * aqk;
+          A[q0 * q + k] = s * apk + c * aqk;
+        }
+        for (int k = 0; k < q; ++k) {
+          const double ukp = U[k * q + p0], ukq = U[k * q + q0];
+          U[k * q + p0] = c * ukp - s * ukq;
+          U[k * q + q0] = s * ukp + c * ukq;
+        }
+      }
+  }
+  lam.resize(q);
+  for (int i = 0; i < q; ++i) lam[i] = A[i * q + i];
+}
+
+// Nearest PSD matrix (eigenvalues clipped at zero).
+static std::vector<double> psd_clip(int q, const std::vector<double>& M) {
+  std::vector<double> sym(q * q), lam, U, out(q * q, 0.0);
+  for (int i = 0; i < q; ++i)
+    for (int j = 0; j < q; ++j) sym[i * q + j] = 0.5 * (M[i * q + j] + M[j * q + i]);
+  small_sym_eig(q, sym, lam, U);
+  for (int k = 0; k < q; ++k) {
+    if (!(lam[k] > 0.0)) continue;
+    for (int i = 0; i < q; ++i)
+      for (int j = 0; j < q; ++j) out[i * q + j] += lam[k] * U[i * q + k] * U[j * q + k];
+  }
+  return out;
+}
+
+// The block rank step's subproblem (Alg. 1): minimise over S PSD (q x q)
+//   phi(S) = sum_a theta_a S_aa + sigma/2 sum_{abcd} S_ab S_cd M4[ab, cd],
+// M4[ab, cd] = sum_i V_ia V_ib V_ic V_id (symmetric in every index), which is
+// <Z V, V> S plus the penalty of A(V S V^T) for Ritz directions V of Z (then
+// V^T Z V = diag(theta)).  Accelerated projected gradient with monotone
+// restarts, step 1 / L (L from power iteration on the Hessian map).
+static std::vector<double> block_subproblem(int q, const std::vector<double>& theta,
+                                            const std::vector<double>& M4, int np, double sigma) {
+  std::vector<int> pid(q * q);
+  for (int a = 0, k = 0; a < q; ++a)
+    for (int b = a; b < q; ++b, ++k) pid[a * q + b] = pid[b * q + a] = k;
+  auto hess = [&](const std::vector<double>& S) {  // S -> sigma M4 . S (Frobenius gradient of the quadratic)
+    std::vector<double> out(q * q, 0.0);
+    for (int a = 0; a < q; ++a)
+      for (int b = 0; b < q; ++b) {
+        double s = 0.0;
+        for (int c = 0; c < q; ++c)
+          for (int d = 0; d < q; ++d) s += M4[(size_t)pid[a * q + b] * np + pid[c * q + d]] * S[c * q + d];
+        out[a * q + b] = sigma * s;
+      }
+    return out;
+  };
+  auto dot = [&](const std::vector<double>& X, const std::vector<double>& Y) {
+    double s = 0.0;
+    for (int i = 0; i < q * q; ++i) s += X[i] * Y[i];
+    return s;
+  };
+  auto phi = [&](const std::vector<double>& S) {
+    double lin = 0.0;
+    for (int a = 0; a < q; ++a) lin += theta[a] * S[a * q + a];
+    return lin + 0.5 * dot(S, hess(S));
+  };
+  auto grad = [&](const std::vector<double>& S) {
+    std::vector<double> g = hess(S);
+    for (int a = 0; a < q; ++a) g[a * q + a] += theta[a];
+    return g;
+  };
+  // largest eigenvalue of the Hessian map on symmetric matrices
+  std::vector<double> X(q * q, 0.0);
+  for (int i = 0; i < q; ++i)
+    for (int j = 0; j < q; ++j) X[i * q + j] = (i == j ? 1.0 : 0.1) / q;
+  double L = 0.0;
+  for (int it = 0; it < 300; ++it) {
+    std::vector<double> Y = hess(X);
+    const double nrm = std::sqrt(dot(Y, Y));
+    if (!(nrm > 0.0)) break;
+    L = dot(X, Y) / dot(X, X);
+    for (int i = 0; i < q * q; ++i) X[i] = Y[i] / nrm;
+  }
+  std::vector<double> S(q * q, 0.0);
+  if (!(L > 0.0)) return S;
+  L *= 1.05;
+  std::vector<double> Yk = S;
+  double t = 1.0, fS = phi(S);
+  for (int it = 0; it < 20000; ++it) {
+    std::vector<double> g = grad(Yk), Sn(q * q);
+    for (int i = 0; i < q * q; ++i) Sn[i] = Yk[i] - g[i] / L;
+    Sn = psd_clip(q, Sn);
+    double fn = phi(Sn);
+    if (fn > fS) {  // restart from S with a plain projected step
+      g = grad(S);
+      for (int i = 0; i < q * q; ++i) Sn[i] = S[i] - g[i] / L;
+      Sn = psd_clip(q, Sn);
+      fn = phi(Sn);
+      t = 1.0;
+    }
+    const double tn = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * t * t));
+    for (int i = 0; i < q * q; ++i) Yk[i] = Sn[i] + ((t - 1.0) / tn) * (Sn[i] - S[i]);
+    double ds = 0.0, ns = 0.0;
+    for (int i = 0; i < q * q; ++i) {
+      ds += (Sn[i] - S[i]) * (Sn[i] - S[i]);
+      ns += Sn[i] * Sn[i];
+    }
+    S = Sn;
+    fS = fn;
+    t = tn;
+    if (std::sqrt(ds) <= 1e-13 * (1.0 + std::sqrt(ns)) && it > 10) break;
+  }
+  return S;
+}
+
 struct LanczosOut {
   double theta = 0.0;
   double resid = 0.0;
@@ -1229,6 +1388,101 @@ static alm_bm_status restride(alm_bm_problem* p, T* R, int ss, int nc, int rd, h
   return ALM_BM_OK;
 }
 
+// Block rank step (Alg. 1 with several directions, DIAG family): the
+// smallest Ritz pairs below -tau_rank of a full Lanczos pass on Z(w) from a
+// random start give V (n x qv, orthonormal, V^T Z V = diag(theta)); k_gram4
+// gives the fourth moments of its columns, the host solves the qv x qv PSD
+// subproblem, and the columns of V S^{1/2} are appended to R.
+constexpr int kMaxBlockDirHost = 8;
+template <typename T>
+static alm_bm_status block_rank_step(alm_bm_problem* p, T* R, int& r, int& w, int r_cap, int rank_block,
+                                     double sigma, int kmax, double tau_rank, uint64_t seed, GraphCache& gc,
+                                     int& added, hipStream_t st) {
+  const auto& d = p->d;
+  const long n = d.n;
+  added = 0;
+  const int q = std::min(rank_block, r_cap - r);
+  if (q < 1) return ALM_BM_OK;
+  if (!p->vblk) {
+    STCHK(dalloc_t(p, &p->vblk, (size_t)n * kMaxBlockDirHost));
+    STCHK(dalloc_t(p, &p->ycoef, (size_t)kMaxBlockDirHost * (p->kmax + 1)));
+    STCHK(dalloc_t(p, &p->gpart, (size_t)p->lnb * 666));
+  }
+  LanczosOut lf;
+  STCHK(lanczos_pass(p, p->ybuf, kmax, 0.0, seed, false, p->lv, lf, st));
+  const int m = lf.iters;
+  std::vector<double> ha(m), hb(m);
+  HIPCHK(hipMemcpyAsync(ha.data(), p->lalpha, m * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(hb.data(), p->lbeta, m * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  std::vector<double> th;
+  std::vector<double> Y;  // column j at j * m
+  for (int k = 0; k < std::min(q, m); ++k) {
+    const double t = tri_kth_eig(ha, hb, m, k);
+    if (!(t < -tau_rank)) break;
+    std::vector<double> z;
+    tri_eigvec(ha, hb, m, t, z);
+    for (size_t j = 0; j < th.size(); ++j) {  // keep the Ritz vectors orthonormal (close Ritz values)
+      double s = 0.0;
+      for (int i = 0; i < m; ++i) s += z[i] * Y[j * m + i];
+      for (int i = 0; i < m; ++i) z[i] -= s * Y[j * m + i];
+    }
+    double nz = 0.0;
+    for (double v : z) nz += v * v;
+    nz = std::sqrt(nz);
+    if (!(nz > 1e-8)) break;
+    for (double& v : z) v /= nz;
+    th.push_back(t);
+    Y.insert(Y.end(), z.begin(), z.end());
+  }
+  const int qv = (int)th.size();
+  if (qv == 0) return ALM_BM_OK;
+  HIPCHK(hipMemcpyAsync(p->ycoef, Y.data(), Y.size() * sizeof(double), hipMemcpyHostToDevice, st));
+  for (int j = 0; j < qv; ++j)
+    launch_combine(n, m, p->Q, n, p->ycoef + (long)j * m, p->vblk + (long)j * n, p->lpart2, p->lnb, st);
+  const int np = qv * (qv + 1) / 2, ne = np * (np + 1) / 2;
+  launch_gram4(n, qv, p->vblk, p->gpart, p->lnb, st);
+  std::vector<double> gp((size_t)p->lnb * ne);
+  HIPCHK(hipMemcpyAsync(gp.data(), p->gpart, gp.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  std::vector<double> M4((size_t)np * np, 0.0);
+  for (int e = 0, p1 = 0, p2 = 0; e < ne; ++e) {
+    double s = 0.0;
+    for (int b = 0; b < p->lnb; ++b) s += gp[(size_t)b * ne + e];
+    M4[(size_t)p1 * np + p2] = M4[(size_t)p2 * np + p1] = s;
+    if (++p2 == np) p2 = ++p1;
+  }
+  const std::vector<double> S = block_subproblem(qv, th, M4, np, sigma);
+  std::vector<double> lam, U;
+  small_sym_eig(qv, S, lam, U);
+  double lmax = 0.0;
+  for (double v : lam) lmax = std::max(lmax, v);
+  std::vector<double> coef;
+  for (int k = 0; k < qv && r + added < r_cap; ++k) {
+    if (!(lam[k] > 1e-14 * std::max(lmax, 1e-300))) continue;
+    for (int i = 0; i < qv; ++i) coef.push_back(U[i * qv + k] * std::sqrt(lam[k]));
+    ++added;
+  }
+  if (added == 0) return ALM_BM_OK;
+  HIPCHK(hipMemcpyAsync(p->ycoef, coef.data(), coef.size() * sizeof(double), hipMemcpyHostToDevice, st));
+  for (int j = 0; j < added; ++j) {
+    launch_combine(n, qv, p->vblk, n, p->ycoef + (long)j * qv, p->lw, p->lpart2, p->lnb, st);
+    if (r + 1 <= w) {
+      launch_set_column<T>(n, w, r, R, p->lw, 1.0, st);
+    } else {
+      const int w2 = pad_width(r + 1, d.r_max);
+      T* Rt = static_cast<T*>(p->Rtmp);
+      launch_relayout<T>(n, w, r, w2, R, Rt, p->lw, 1.0, st);
+      HIPCHK(hipMemcpyAsync(R, Rt, (size_t)n * w2 * sizeof(T), hipMemcpyDeviceToDevice, st));
+      w = w2;
+      gc.reset();
+    }
+    r += 1;
+  }
+  HIPCHK(hipStreamSynchronize(st));
+  return ALM_BM_OK;
+}
+
 template <typename T>
 static alm_bm_status solve_impl(alm_bm_problem* p, const alm_bm_options& o, T* R, double* y, hipStream_t st,
                                 int& r, int& w, int k_start, int& k_done,
@@ -1261,7 +1515,18 @@ static alm_bm_status solve_impl(alm_bm_problem* p, const alm_bm_options& o, T* R
     acc.time_lanczos_s += now_s() - tl;
     bool expanded = false;
     const bool gate = (flag == 1) || !o.expand_needs_inner;
-    if (o.rank_policy == ALM_BM_RANK_ADAPT && gate && lo.theta < -tau_rank && r < r_cap) {
+    if (o.rank_policy == ALM_BM_RANK_ADAPT && gate && lo.theta < -tau_rank && r < r_cap && o.rank_block > 1) {
+      int added = 0;
+      STCHK(block_rank_step<T>(p, R, r, w, r_cap, o.rank_block, sigma, kmax, tau_rank,
+                               o.seed * 1000003ull + (uint64_t)k + 3333333ull, gc, added, st));
+      if (added > 0) {
+        expanded = true;
+        acc.expansions += 1;
+        enqueue_objgrad<T>(p, w, R, y, sigma, nullptr, p->Av, p->sc_api, 0, nullptr, st);
+        launch_dual(d.m, p->Av, d.b, y, p->ybuf, sigma, p->part_vec, p->sc_solve, p->bnorm, nullptr, st,
+                    sigma * p->rho);
+      }
+    } else if (o.rank_policy == ALM_BM_RANK_ADAPT && gate && lo.theta < -tau_rank && r < r_cap) {
       // ||A(v v^T)||^2 for the unit Ritz vector
       launch_quartic_norm(n, d.cons_kind == ALM_BM_CONS_DIAG ? 0 : 1, p->adj, p->lv, p->lpart2, p->lnb, st);
       launch_fin_sum(p->lpart2, p->lnb, p->lscal + 3, 0, st);
@@ -1392,6 +1657,10 @@ extern "C" alm_bm_status alm_bm_solve(alm_bm_problem* p, const alm_bm_options* o
   if (o.sigma_edges < 0.0) return fail(ALM_BM_ERR_INVALID_ARG, "solve: sigma_edges must be >= 0");
   if (!(o.sigma_growth >= 1.0) || !(o.sigma_max >= o.sigma) || !(o.pinf_reduction > 0.0 && o.pinf_reduction <= 1.0))
     return fail(ALM_BM_ERR_INVALID_ARG, "solve: need sigma_growth >= 1, sigma_max >= sigma, 0 < pinf_reduction <= 1");
+  if (o.rank_block < 1 || o.rank_block > kMaxBlockDirHost)
+    return fail(ALM_BM_ERR_INVALID_ARG, "solve: rank_block must be in 1..8");
+  if (o.rank_block > 1 && p->d.cons_kind != ALM_BM_CONS_DIAG)
+    return fail(ALM_BM_ERR_UNSUPPORTED, "solve: rank_block > 1 is for the DIAG family");
   HIPCHK(hipStreamSynchronize(st_user));
   hipStream_t st = p->ss;
   // penalty of the edge rows relative to sigma, for the length of this solve
@@ -2191,6 +2460,7 @@ extern "C" alm_bm_status alm_bm_batch_solve(alm_bm_batch* b, const alm_bm_option
     return fail(ALM_BM_ERR_INVALID_ARG, "batch_solve: sigma, eps_kkt, max_outer and max_inner must be positive");
   if (o.sigma_growth != 1.0)
     return fail(ALM_BM_ERR_UNSUPPORTED, "batch_solve: the penalty schedule (sigma_growth) is for single solves");
+  if (o.rank_block != 1) return fail(ALM_BM_ERR_UNSUPPORTED, "batch_solve: rank_block > 1 is for single solves");
   HIPCHK(hipStreamSynchronize(st_user));
   hipStream_t st = b->p->ss;
   alm_bm_status s = with_storage(b->p->d.precision, [&]<typename T>() {

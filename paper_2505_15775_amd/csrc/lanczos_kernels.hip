@@ -251,7 +251,67 @@ k_quartic_norm(long n, int cons_kind, EdgeAdj A, const double* __restrict__ x, d
   block_sum_store<1>(acc, part + part_slot(tab));
 }
 
+// Fourth moments of q directions over the rows (DIAG family), for the block
+// rank step: with the pairs (a <= b) numbered in row-major order and the
+// pairs of pairs (P1 <= P2) likewise, entry e of block b is
+//   part[b * ne + e] = sum over the block's rows i of V_ia V_ib V_ic V_id,
+// ne = np (np + 1) / 2, np = q (q + 1) / 2.  V is n x q column-major.  The
+// block's rows go through LDS kBlock at a time; thread t owns the entries
+// t, t + kBlock, ... (at most kGramPerThread of them for q <= kMaxBlockDir).
+constexpr int kMaxBlockDir = 8;
+constexpr int kGramPerThread = 3;
+__device__ __forceinline__ void pair_of(int pidx, int q, int& a, int& b) {
+  a = 0;
+  while (pidx >= q - a) {
+    pidx -= q - a;
+    ++a;
+  }
+  b = a + pidx;
+}
+__global__ void __launch_bounds__(kBlock)
+k_gram4(long n, int q, const double* __restrict__ V, double* __restrict__ part) {
+  __shared__ double tile[kBlock][kMaxBlockDir];
+  const int np = q * (q + 1) / 2;
+  const int ne = np * (np + 1) / 2;
+  int ia[kGramPerThread], ib[kGramPerThread], ic[kGramPerThread], id[kGramPerThread];
+  int cnt = 0;
+  for (int e = threadIdx.x; e < ne && cnt < kGramPerThread; e += kBlock) {
+    int p1 = 0, rem = e;
+    while (rem >= np - p1) {
+      rem -= np - p1;
+      ++p1;
+    }
+    pair_of(p1, q, ia[cnt], ib[cnt]);
+    pair_of(p1 + rem, q, ic[cnt], id[cnt]);
+    ++cnt;
+  }
+  double acc[kGramPerThread] = {0.0, 0.0, 0.0};
+  const long per = (n + gridDim.x - 1) / gridDim.x;
+  const long lo = (long)blockIdx.x * per < n ? (long)blockIdx.x * per : n;
+  const long hi = lo + per < n ? lo + per : n;
+  for (long base = lo; base < hi; base += kBlock) {
+    const long i = base + threadIdx.x;
+    for (int k = 0; k < q; ++k) tile[threadIdx.x][k] = (i < hi) ? V[(long)k * n + i] : 0.0;
+    __syncthreads();
+    const int rows = hi - base < kBlock ? (int)(hi - base) : kBlock;
+    for (int t = 0; t < cnt; ++t) {
+      double s = 0.0;
+      for (int rr = 0; rr < rows; ++rr) {
+        const double* v = tile[rr];
+        s += v[ia[t]] * v[ib[t]] * v[ic[t]] * v[id[t]];
+      }
+      acc[t] += s;
+    }
+    __syncthreads();
+  }
+  for (int t = 0; t < cnt; ++t) part[(long)blockIdx.x * ne + threadIdx.x + t * kBlock] = acc[t];
+}
+
 // ---- launchers (single instance: empty table, count 1, strides 0) ---------------
+
+void launch_gram4(long n, int q, const double* V, double* part, int nb, hipStream_t st) {
+  hipLaunchKernelGGL(k_gram4, dim3(nb), dim3(kBlock), 0, st, n, q, V, part);
+}
 
 int vec_blocks(long n) {
   long nb = (n + kBlock * 16 - 1) / (kBlock * 16);

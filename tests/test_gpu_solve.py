@@ -197,3 +197,40 @@ def test_penalty_schedule_er_workload():
     k = _oracle_kkt(oracle.maxcut_sdp(g), R.double().cpu().numpy(), y.cpu().numpy())
     print(f"oracle KKT at the scheduled solve's point: {k['kkt']:.2e}")
     assert k["kkt"] <= 2 * eps
+
+
+@pytest.mark.parametrize("n,q", [(9, 3), (64, 4)])
+def test_block_rank_step_cycles_closed_form(n, q):
+    """Rank steps with q directions (Ritz vectors of a full Lanczos pass and the
+    small PSD subproblem) from rank 1: the closed forms are reached."""
+    g = gen.cycle_graph(n)
+    prob = _maxcut(g, r_max=16, kmax=min(n, 60))
+    st, res, R, y = prob.solve(gen.init_factor(n, 1, 1), eps_kkt=1e-8, rank_block=q, max_outer=400, max_inner=2000)
+    val = -res["pobj"]
+    expect = n if n % 2 == 0 else n * (1 + math.cos(math.pi / n)) / 2
+    print(f"cycle {n} rank_block {q}: status {st} value {val:.12f} expect {expect:.12f} outer {res['outer']} "
+          f"rank {res['rank']} expansions {res['expansions']}", flush=True)
+    assert st == 0
+    assert math.isclose(val, expect, rel_tol=1e-6)
+
+
+def test_block_rank_step_er_workload():
+    """G(2000, 10^4) from rank 1 with 4 directions per rank step: the same
+    objective as the one-vector steps and the oracle's KKT at the returned
+    point."""
+    g = gen.er_graph(2000, 10000, 1, "unit")
+    eps = 1e-6
+    out = {}
+    for q in (1, 4):
+        prob = _maxcut(g, r_max=48, kmax=100)
+        st, res, R, y = prob.solve(gen.init_factor(g.n, 1, 1), eps_kkt=eps, rank_block=q, max_outer=500)
+        print(f"ER 2000 from rank 1, rank_block {q}: status {st} outer {res['outer']} inner {res['inner_total']} "
+              f"rank {res['rank']} pobj {res['pobj']:.12e} time {res['time_s']:.2f}s", flush=True)
+        assert st == 0
+        out[q] = (res, R, y)
+    d = abs(out[4][0]["pobj"] - out[1][0]["pobj"]) / abs(out[1][0]["pobj"])
+    assert d <= 1e-5
+    _, R, y = out[4]
+    k = _oracle_kkt(oracle.maxcut_sdp(g), R.double().cpu().numpy(), y.cpu().numpy())
+    print(f"oracle KKT at the block-step solve's point: {k['kkt']:.2e}", flush=True)
+    assert k["kkt"] <= 2 * eps
