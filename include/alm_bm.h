@@ -153,7 +153,7 @@ typedef struct {
   double pinf_reduction;     /* 0.25   required decrease of pinf per outer iteration  */
   int32_t rank_block;        /* 1      rank step directions (Alg. 1's negative-curvature
                                 step): 1 = the closed-form one-vector step; 2..8
-                                (DIAG family) = the smallest Ritz vectors below
+                                = the smallest Ritz vectors below
                                 -tau_rank of a full Lanczos pass, S of the small PSD
                                 subproblem, and the columns of V S^(1/2)           */
 } alm_bm_options;

@@ -1388,11 +1388,12 @@ static alm_bm_status restride(alm_bm_problem* p, T* R, int ss, int nc, int rd, h
   return ALM_BM_OK;
 }
 
-// Block rank step (Alg. 1 with several directions, DIAG family): the
+// Block rank step (Alg. 1 with several directions): the
 // smallest Ritz pairs below -tau_rank of a full Lanczos pass on Z(w) from a
 // random start give V (n x qv, orthonormal, V^T Z V = diag(theta)); k_gram4
-// gives the fourth moments of its columns, the host solves the qv x qv PSD
-// subproblem, and the columns of V S^{1/2} are appended to R.
+// (rows, DIAG) or k_gram4_edges (edge rows, weighted by rho, plus the trace
+// row's c_tr^2 tr(S)^2) gives the penalty's quadratic form, the host solves
+// the qv x qv PSD subproblem, and the columns of V S^{1/2} are appended to R.
 constexpr int kMaxBlockDirHost = 8;
 template <typename T>
 static alm_bm_status block_rank_step(alm_bm_problem* p, T* R, int& r, int& w, int r_cap, int rank_block,
@@ -1441,7 +1442,9 @@ static alm_bm_status block_rank_step(alm_bm_problem* p, T* R, int& r, int& w, in
   for (int j = 0; j < qv; ++j)
     launch_combine(n, m, p->Q, n, p->ycoef + (long)j * m, p->vblk + (long)j * n, p->lpart2, p->lnb, st);
   const int np = qv * (qv + 1) / 2, ne = np * (np + 1) / 2;
-  launch_gram4(n, qv, p->vblk, p->gpart, p->lnb, st);
+  const bool edges = d.cons_kind != ALM_BM_CONS_DIAG;
+  if (edges) launch_gram4_edges(d.n_edges, n, qv, d.edge_i, d.edge_j, p->vblk, p->gpart, p->lnb, st);
+  else launch_gram4(n, qv, p->vblk, p->gpart, p->lnb, st);
   std::vector<double> gp((size_t)p->lnb * ne);
   HIPCHK(hipMemcpyAsync(gp.data(), p->gpart, gp.size() * sizeof(double), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
@@ -1449,8 +1452,16 @@ static alm_bm_status block_rank_step(alm_bm_problem* p, T* R, int& r, int& w, in
   for (int e = 0, p1 = 0, p2 = 0; e < ne; ++e) {
     double s = 0.0;
     for (int b = 0; b < p->lnb; ++b) s += gp[(size_t)b * ne + e];
-    M4[(size_t)p1 * np + p2] = M4[(size_t)p2 * np + p1] = s;
+    M4[(size_t)p1 * np + p2] = M4[(size_t)p2 * np + p1] = (edges ? p->rho : 1.0) * s;
     if (++p2 == np) p2 = ++p1;
+  }
+  if (edges && d.trace_coef != 0.0) {
+    // trace row: c_tr tr(V S V^T) = c_tr tr(S) for orthonormal V
+    for (int a0 = 0; a0 < qv; ++a0)
+      for (int c0 = 0; c0 < qv; ++c0) {
+        const int pa = a0 * qv - a0 * (a0 - 1) / 2, pc = c0 * qv - c0 * (c0 - 1) / 2;  // index of (a, a), (c, c)
+        M4[(size_t)pa * np + pc] += d.trace_coef * d.trace_coef;
+      }
   }
   const std::vector<double> S = block_subproblem(qv, th, M4, np, sigma);
   std::vector<double> lam, U;
@@ -1659,8 +1670,6 @@ extern "C" alm_bm_status alm_bm_solve(alm_bm_problem* p, const alm_bm_options* o
     return fail(ALM_BM_ERR_INVALID_ARG, "solve: need sigma_growth >= 1, sigma_max >= sigma, 0 < pinf_reduction <= 1");
   if (o.rank_block < 1 || o.rank_block > kMaxBlockDirHost)
     return fail(ALM_BM_ERR_INVALID_ARG, "solve: rank_block must be in 1..8");
-  if (o.rank_block > 1 && p->d.cons_kind != ALM_BM_CONS_DIAG)
-    return fail(ALM_BM_ERR_UNSUPPORTED, "solve: rank_block > 1 is for the DIAG family");
   HIPCHK(hipStreamSynchronize(st_user));
   hipStream_t st = p->ss;
   // penalty of the edge rows relative to sigma, for the length of this solve

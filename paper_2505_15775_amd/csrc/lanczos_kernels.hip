@@ -307,7 +307,60 @@ k_gram4(long n, int q, const double* __restrict__ V, double* __restrict__ part) 
   for (int t = 0; t < cnt; ++t) part[(long)blockIdx.x * ne + threadIdx.x + t * kBlock] = acc[t];
 }
 
+// The same moments for the edge rows of the trace + edge family: with
+// K_e(ab) = (V_ia V_jb + V_ja V_ib) / 2 for edge e = (i, j) (the edge row of
+// A(v_a v_b^T)), part[b * ne + e'] = sum over the block's edges of
+// K_e(P1) K_e(P2) for the pair of pairs e' = (P1, P2).  Edges go through LDS
+// kEdgeChunk at a time.
+constexpr int kEdgeChunk = 128;
+__global__ void __launch_bounds__(kBlock)
+k_gram4_edges(long E, long n, int q, const int32_t* __restrict__ ei, const int32_t* __restrict__ ej,
+              const double* __restrict__ V, double* __restrict__ part) {
+  __shared__ double tile[kEdgeChunk][kMaxBlockDir * (kMaxBlockDir + 1) / 2];
+  const int np = q * (q + 1) / 2;
+  const int ne = np * (np + 1) / 2;
+  int p1s[kGramPerThread], p2s[kGramPerThread];
+  int cnt = 0;
+  for (int e = threadIdx.x; e < ne && cnt < kGramPerThread; e += kBlock) {
+    int p1 = 0, rem = e;
+    while (rem >= np - p1) {
+      rem -= np - p1;
+      ++p1;
+    }
+    p1s[cnt] = p1;
+    p2s[cnt] = p1 + rem;
+    ++cnt;
+  }
+  double acc[kGramPerThread] = {0.0, 0.0, 0.0};
+  const long per = (E + gridDim.x - 1) / gridDim.x;
+  const long lo = (long)blockIdx.x * per < E ? (long)blockIdx.x * per : E;
+  const long hi = lo + per < E ? lo + per : E;
+  for (long base = lo; base < hi; base += kEdgeChunk) {
+    const int rows = hi - base < kEdgeChunk ? (int)(hi - base) : kEdgeChunk;
+    for (int idx = threadIdx.x; idx < rows * np; idx += kBlock) {
+      const int el = idx / np, pp = idx % np;
+      int a, b;
+      pair_of(pp, q, a, b);
+      const long i = ei[base + el], j = ej[base + el];
+      tile[el][pp] = 0.5 * (V[(long)a * n + i] * V[(long)b * n + j] + V[(long)a * n + j] * V[(long)b * n + i]);
+    }
+    __syncthreads();
+    for (int t = 0; t < cnt; ++t) {
+      double s = 0.0;
+      for (int rr = 0; rr < rows; ++rr) s += tile[rr][p1s[t]] * tile[rr][p2s[t]];
+      acc[t] += s;
+    }
+    __syncthreads();
+  }
+  for (int t = 0; t < cnt; ++t) part[(long)blockIdx.x * ne + threadIdx.x + t * kBlock] = acc[t];
+}
+
 // ---- launchers (single instance: empty table, count 1, strides 0) ---------------
+
+void launch_gram4_edges(long E, long n, int q, const int32_t* ei, const int32_t* ej, const double* V, double* part,
+                        int nb, hipStream_t st) {
+  hipLaunchKernelGGL(k_gram4_edges, dim3(nb), dim3(kBlock), 0, st, E, n, q, ei, ej, V, part);
+}
 
 void launch_gram4(long n, int q, const double* V, double* part, int nb, hipStream_t st) {
   hipLaunchKernelGGL(k_gram4, dim3(nb), dim3(kBlock), 0, st, n, q, V, part);

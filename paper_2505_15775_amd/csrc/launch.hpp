@@ -106,6 +106,9 @@ void launch_rand(long n, uint64_t seed, double* x, double* part, int nb, hipStre
 // Fourth moments of q <= 8 directions (V n x q column-major) per block of the
 // nb-block grid: part[b * ne + e], ne = np (np + 1) / 2, np = q (q + 1) / 2.
 void launch_gram4(long n, int q, const double* V, double* part, int nb, hipStream_t st);
+// The edge-row moments of the trace + edge family (edges ei[e] < ej[e], E of them).
+void launch_gram4_edges(long E, long n, int q, const int32_t* ei, const int32_t* ej, const double* V, double* part,
+                        int nb, hipStream_t st);
 void launch_combine(long n, int ncol, const double* Q, long ldq, const double* s, double* v, double* part, int nb,
                     hipStream_t st, const VecBatch& vb = VecBatch{});
 void launch_resid(long n, const double* z, const double* v, double theta, const double* thetas, double* part, int nb,

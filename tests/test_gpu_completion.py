@@ -84,3 +84,23 @@ def test_completion_solve_small_penalty(r, r0):
     k = oracle.kkt(oracle.completion_sdp(inst), R.double().cpu().numpy(), y.cpu().numpy())
     print(f"oracle KKT at the GPU point: {k['kkt']:.2e}")
     assert k["kkt"] <= 2 * eps
+
+
+def test_completion_block_rank_step_from_rank_one():
+    """From rank 1 with 3 directions per rank step (trace + edge family: the
+    edge rows' fourth moments): the nuclear norm, at a point the oracle's KKT
+    measure accepts."""
+    eps = 1e-5
+    inst = gen.completion_instance(1000, 1000, 3, 13)
+    nuc = float(np.sum(np.linalg.svd(inst.U @ inst.V.T, compute_uv=False)))
+    p = _problem(inst, r_max=32)
+    st, res, R, y = p.solve(gen.init_factor(inst.n, 1, 1), eps_kkt=eps, sigma=0.03, rank_block=3, max_outer=500,
+                            time_limit_s=60)
+    print(f"completion 1000x1000 r=3 from rank 1, rank_block 3: status {st} outer {res['outer']} "
+          f"inner {res['inner_total']} rank {res['rank']} kkt {res['kkt']:.2e} value {res['pobj']:.10e} "
+          f"nuclear norm {nuc:.10e} time {res['time_s']:.3f}s", flush=True)
+    assert st == 0
+    assert math.isclose(res["pobj"], nuc, rel_tol=1e-4)
+    k = oracle.kkt(oracle.completion_sdp(inst), R.double().cpu().numpy(), y.cpu().numpy())
+    print(f"oracle KKT at the GPU point: {k['kkt']:.2e}", flush=True)
+    assert k["kkt"] <= 2 * eps

@@ -234,3 +234,16 @@ def test_block_rank_step_er_workload():
     k = _oracle_kkt(oracle.maxcut_sdp(g), R.double().cpu().numpy(), y.cpu().numpy())
     print(f"oracle KKT at the block-step solve's point: {k['kkt']:.2e}", flush=True)
     assert k["kkt"] <= 2 * eps
+
+
+def test_block_rank_step_lovasz_c5():
+    """Lovasz theta of C5 (trace row + edge rows, C = -J) from rank 1 with 2
+    directions per rank step and the edge penalty: sqrt(5)."""
+    g = gen.cycle_graph(5)
+    prob = almbm().Problem.lovasz(5, g.ei, g.ej, precision="f64", r_max=8, lanczos_kmax=5, device=DEV)
+    st, res, R, y = prob.solve(gen.init_factor(5, 1, 1), eps_kkt=1e-6, sigma_edges=5.0, rank_block=2,
+                               max_outer=400, max_inner=2000)
+    print(f"lovasz C5 rank_block 2: status {st} value {-res['pobj']:.10f} outer {res['outer']} rank {res['rank']}",
+          flush=True)
+    assert st == 0
+    assert math.isclose(-res["pobj"], math.sqrt(5.0), rel_tol=1e-5)
