@@ -5,8 +5,10 @@ y0 (zero by default, as Alg. 1 initialises it); each outer iteration
 approximately minimises the BM subproblem eq. (AL-BM) by gradient descent
 (eq. GD, Sec. 4.2), then looks at the smallest eigenpair of
 grad_X L = C - A*(y + sigma (b - A(RR^T))), expands the factor by one column
-when that eigenvalue is sufficiently negative (p = 1 case of the rank step of Alg. 1),
-then updates y (eq. ALM) and tests the relative KKT measure of Sec. 6.
+when that eigenvalue is sufficiently negative (p = 1 case of the rank step of Alg. 1)
+or, with rank_block > 1, by the columns of V S^{1/2} for the most negative
+eigenvectors V and the small PSD subproblem (curvature_step), then updates y
+(eq. ALM) and tests the relative KKT measure of Sec. 6.
 
 Readings where the paper is silent (shared with the HIP path through the
 solve options):
@@ -25,12 +27,18 @@ solve options):
   floor((sqrt(8m+1)-1)/2) of Sec. 3.3), whether or not the inner solve met its
   tolerance, as Alg. 1 does (an optional gate waits for inner convergence; it
   stalls the rank, hence the dual infeasibility, once max_inner binds);
-* fixed penalty sigma; the edges family may give its edge rows their own penalty
-  sigma_edges (the trace row keeps sigma), one penalty per constraint throughout.
+* penalty sigma fixed by default; the edges family may give its edge rows their
+  own penalty sigma_edges (the trace row keeps sigma), one penalty per
+  constraint throughout; an optional schedule multiplies every penalty by
+  sigma_growth after an outer iteration whose pinf did not fall below
+  pinf_reduction times the previous one (the update of the SDPLR solver the
+  paper cites in Sec. 2).
 
 Pins: the quartic coefficients against direct evaluation of the objective at
 R - tG (tests/test_oracle_alm.py); solve values against closed-form MaxCut and
-Lovasz-theta values, brute-force max cuts and an independent dense convex ALM.
+Lovasz-theta values, brute-force max cuts and an independent dense convex ALM;
+the curvature step against the closed-form one-vector step, the objective
+change, PSD perturbations and a brute-force grid (tests/test_oracle_rankstep.py).
 Trajectory-level agreement with the HIP solve is parity unpinned beyond
 final invariants (discrete rank/root decisions may differ near ties).
 """
