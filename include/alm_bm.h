@@ -283,6 +283,16 @@ alm_bm_status alm_bm_set_tiles(alm_bm_problem* prob, int32_t variant, int32_t ro
  * batch.  Results differ from the hub-free pass only in summation order.     */
 alm_bm_status alm_bm_set_hub_threshold(alm_bm_problem* prob, int32_t min_degree, int32_t* hubs);
 
+/* The small PSD subproblem of the block rank step (Alg. 1, Sec. 5), host
+ * only: minimise over S PSD (q x q, 1 <= q <= 8)
+ *   sum_a theta_a S_aa + sigma/2 sum_{abcd} S_ab S_cd M4[pair(a,b), pair(c,d)]
+ * where pair(a,b) numbers the pairs a <= b row-major (np = q(q+1)/2 of them)
+ * and M4 (host, np x np row-major, symmetric) holds the penalty's quadratic
+ * form of A(V S V^T) for orthonormal Ritz directions V of the slack with
+ * Ritz values theta (host, q).  S: host out, q x q row-major.  This is the
+ * solver alm_bm_solve uses with rank_block > 1; it needs no device.         */
+alm_bm_status alm_bm_psd_step(int32_t q, const double* theta, const double* M4, double sigma, double* S);
+
 /* Autotuner: times reps objective/gradient passes at rank r for every
  * (variant, row_blocks) candidate with HIP events on `stream`, keeps the
  * fastest in the handle and returns it (host int32 each, nullable).  Uses the

@@ -48,6 +48,18 @@ def maxcut_cost(n, ei, ej, w):
     return rp, ci[:k].copy(), cv[:k].copy(), dg
 
 
+def psd_step(theta, M4, sigma):
+    """The block rank step's small PSD subproblem (alm_bm_psd_step, host only):
+    theta (q Ritz values), M4 (np x np, np = q(q+1)/2, pairs a <= b row-major),
+    sigma.  Returns S (q x q)."""
+    theta = np.ascontiguousarray(theta, dtype=np.float64)
+    M4 = np.ascontiguousarray(M4, dtype=np.float64)
+    q = theta.shape[0]
+    S = np.empty((q, q), dtype=np.float64)
+    check(lib.alm_bm_psd_step(q, theta.ctypes.data, M4.ctypes.data, float(sigma), S.ctypes.data), "psd_step")
+    return S
+
+
 class Problem:
     """One SDP instance resident on the GPU plus its library handle.
 

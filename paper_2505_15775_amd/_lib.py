@@ -113,7 +113,7 @@ class Result(C.Structure):
 EXPORTS = [
     "alm_bm_create", "alm_bm_destroy", "alm_bm_objective_grad", "alm_bm_cost_apply", "alm_bm_line_search",
     "alm_bm_dual_update", "alm_bm_lanczos_min_eig", "alm_bm_solve", "alm_bm_kkt", "alm_bm_default_options", "alm_bm_last_error",
-    "alm_bm_maxcut_cost_host", "alm_bm_abi_sizes", "alm_bm_gd_step", "alm_bm_set_tiles", "alm_bm_set_hub_threshold",
+    "alm_bm_maxcut_cost_host", "alm_bm_abi_sizes", "alm_bm_gd_step", "alm_bm_set_tiles", "alm_bm_set_hub_threshold", "alm_bm_psd_step",
     "alm_bm_autotune",
     "alm_bm_inner_solve", "alm_bm_ws_features", "alm_bm_ws_pool", "alm_bm_ws_param_count", "alm_bm_ws_work_size",
     "alm_bm_ws_forward", "alm_bm_ws_loss_grad", "alm_bm_ws_adam", "alm_bm_ws_ridge_fit",
@@ -148,6 +148,7 @@ def _load():
         "alm_bm_abi_sizes": (None, [C.POINTER(i64)]),
         "alm_bm_set_tiles": (i32, [vp, i32, i32]),
         "alm_bm_set_hub_threshold": (i32, [vp, i32, vp]),
+        "alm_bm_psd_step": (i32, [i32, vp, vp, C.c_double, vp]),
         "alm_bm_ws_features": (i32, [vp, vp, vp, vp]),
         "alm_bm_ws_pool": (i32, [vp, i64, vp, vp, vp]),
         "alm_bm_ws_param_count": (i64, [i32, i32]),

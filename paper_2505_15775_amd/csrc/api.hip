@@ -1133,6 +1133,19 @@ static std::vector<double> block_subproblem(int q, const std::vector<double>& th
   return S;
 }
 
+extern "C" alm_bm_status alm_bm_psd_step(int32_t q, const double* theta, const double* M4, double sigma,
+                                         double* S) {
+  if (q < 1 || q > 8 || !theta || !M4 || !S) return fail(ALM_BM_ERR_INVALID_ARG, "psd_step: bad arguments");
+  if (!(sigma > 0.0)) return fail(ALM_BM_ERR_INVALID_ARG, "psd_step: sigma must be positive");
+  const int np = q * (q + 1) / 2;
+  const std::vector<double> th(theta, theta + q), m4(M4, M4 + (size_t)np * np);
+  for (double v : m4)
+    if (!std::isfinite(v)) return fail(ALM_BM_ERR_NUMERIC, "psd_step: non-finite M4");
+  const std::vector<double> out = block_subproblem(q, th, m4, np, sigma);
+  std::copy(out.begin(), out.end(), S);
+  return ALM_BM_OK;
+}
+
 struct LanczosOut {
   double theta = 0.0;
   double resid = 0.0;

@@ -113,3 +113,48 @@ def test_set_tiles_rejects_bad_values_without_device():
     from paper_2505_15775_amd import _lib
 
     assert _lib.lib.alm_bm_set_tiles(None, 0, 0) == -1
+
+
+def _pairs(q):
+    return [(a, b) for a in range(q) for b in range(a, q)]
+
+
+@pytest.mark.parametrize("kind,q", [("maxcut", 1), ("maxcut", 3), ("maxcut", 5), ("lovasz", 2), ("lovasz", 4)])
+def test_psd_step_matches_the_oracle_curvature_step(kind, q):
+    """The host solver of the block rank step's q x q PSD subproblem against the
+    oracle's curvature step, on exact eigenvectors of the slack (so that
+    V^T Z V = diag(theta)); M4 is the penalty's quadratic form of A(V S V^T)
+    built from its definition (rows for MaxCut; edge rows weighted by the edge
+    penalty ratio plus the trace row for Lovasz)."""
+    import gen
+    import oracle
+    import paper_2505_15775_amd as m
+
+    rng = np.random.default_rng(17 + q)
+    if kind == "maxcut":
+        po = oracle.maxcut_sdp(gen.er_graph(80, 300, 5, "gauss"))
+        sigma, rho = 1.3, 1.0
+    else:
+        po = oracle.lovasz_sdp(gen.er_graph(50, 150, 6, "unit"))
+        sigma, rho = 2.0, 4.0
+    sig_vec = np.full(po.m, sigma * rho)
+    sig_vec[0] = sigma if kind == "lovasz" else sigma * rho
+    R = rng.standard_normal((po.n, 2)) / np.sqrt(po.n)
+    y = rng.standard_normal(po.m)
+    if kind == "lovasz":
+        y[0] = 5.0  # the trace multiplier shifts the slack down: several negative eigenvalues
+    w = y - sig_vec * (oracle.amap(po, R) - po.b)
+    theta, V = oracle.min_eigs(po, w, q)
+    assert np.all(theta < 0)
+    P = _pairs(q)
+    if kind == "maxcut":
+        K = np.column_stack([V[:, a] * V[:, b] for a, b in P])            # rows of A(v_a v_b^T)
+        M4 = K.T @ K
+    else:
+        ei, ej = po.ei, po.ej
+        K = np.column_stack([0.5 * (V[ei, a] * V[ej, b] + V[ej, a] * V[ei, b]) for a, b in P])
+        tr = np.array([1.0 if a == b else 0.0 for a, b in P])              # trace row: c_tr tr(S)
+        M4 = rho * (K.T @ K) + po.c_tr ** 2 * np.outer(tr, tr)
+    S = m.psd_step(theta, M4, sigma)
+    S_o, phi_o, _ = oracle.curvature_step(po, w, sig_vec, V)
+    assert np.linalg.norm(S - S_o) <= 1e-7 * max(1.0, np.linalg.norm(S_o))
