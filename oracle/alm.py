@@ -79,6 +79,10 @@ class SolveOptions:
     # w and the small PSD subproblem of Alg. 1 (curvature_step); 1 = the
     # closed-form one-vector step
     rank_block: int = 1
+    # subproblem solver: 'gd' (eq. GD, the paper's) or 'lbfgs' (limited-memory
+    # BFGS with the same exact line search, the SDPLR solver of Sec. 2)
+    inner_solver: str = "gd"
+    lbfgs_memory: int = 8
 
 
 def line_search_coeffs(p, R, G, y, sigma, P=None, a=None):
@@ -250,6 +254,58 @@ def curvature_step(p, w, sigma, V, max_iter=200000, tol=1e-12):
     return S, phi(S), cols
 
 
+def inner_lbfgs(p, R, y, sigma, tol, max_inner, memory=8):
+    """L-BFGS on eq. (AL-BM) with the exact minimiser of the quartic along each
+    direction, until ||G||_F ||R||_F <= tol (1 + |<C, RR^T>|) (the stopping
+    rule of inner_gd).  Directions by the two-loop recursion over the last
+    `memory` pairs (s, g_new - g) with positive curvature, scaled by
+    s.y / y.y; a direction that is not a descent direction, or a zero step,
+    clears the memory and falls back to -G."""
+    R = np.array(R, dtype=np.float64, copy=True)
+    S_mem, Y_mem = [], []
+    f, G, a, P = objective_grad(p, R, y, sigma)
+    for it in range(max_inner):
+        gnorm = float(np.linalg.norm(G))
+        c0 = float(np.sum(R * P))
+        if gnorm * float(np.linalg.norm(R)) <= tol * (1.0 + abs(c0)):
+            return R, {"iters": it, "f": f, "gnorm": gnorm, "converged": True}
+        # two-loop recursion: D = -H G
+        q = G.copy()
+        alphas = []
+        for s, yv in zip(reversed(S_mem), reversed(Y_mem)):
+            rho = 1.0 / float(np.sum(yv * s))
+            al = rho * float(np.sum(s * q))
+            alphas.append((al, rho))
+            q -= al * yv
+        if S_mem:
+            q *= float(np.sum(S_mem[-1] * Y_mem[-1])) / float(np.sum(Y_mem[-1] * Y_mem[-1]))
+        for (al, rho), s, yv in zip(reversed(alphas), S_mem, Y_mem):
+            be = rho * float(np.sum(yv * q))
+            q += (al - be) * s
+        D = -q
+        if float(np.sum(D * G)) >= 0.0:
+            S_mem, Y_mem = [], []
+            D = -G
+        t = quartic_argmin(line_search_coeffs(p, R, -D, y, sigma, P, a))
+        if t == 0.0 and S_mem:
+            S_mem, Y_mem = [], []
+            D = -G
+            t = quartic_argmin(line_search_coeffs(p, R, G, y, sigma, P, a))
+        if t == 0.0:
+            return R, {"iters": it, "f": f, "gnorm": gnorm, "converged": False}
+        R_new = R + t * D
+        f, G_new, a, P = objective_grad(p, R_new, y, sigma)
+        s, yv = R_new - R, G_new - G
+        if float(np.sum(s * yv)) > 1e-12 * float(np.linalg.norm(s)) * float(np.linalg.norm(yv)):
+            S_mem.append(s)
+            Y_mem.append(yv)
+            if len(S_mem) > memory:
+                S_mem.pop(0)
+                Y_mem.pop(0)
+        R, G = R_new, G_new
+    return R, {"iters": max_inner, "f": f, "gnorm": float(np.linalg.norm(G)), "converged": False}
+
+
 def bp_rank_cap(m):
     """Largest r with r(r+1)/2 <= m (Barvinok-Pataki bound, Sec. 3.3)."""
     return int((math.isqrt(8 * m + 1) - 1) // 2)
@@ -277,7 +333,10 @@ def solve(p, R0, y0=None, opts=None, callback=None):
         tol = max(opts.eps_kkt / 10.0, min(opts.inner_tol_scale, pinf_prev,
                                                  opts.inner_tol_decay * tol_prev))
         tol_prev = tol
-        R, inner = inner_gd(p, R, y, sigma, tol, opts.max_inner, opts.step_rule, opts.eta_fixed)
+        if opts.inner_solver == "lbfgs":
+            R, inner = inner_lbfgs(p, R, y, sigma, tol, opts.max_inner, opts.lbfgs_memory)
+        else:
+            R, inner = inner_gd(p, R, y, sigma, tol, opts.max_inner, opts.step_rule, opts.eta_fixed)
         a = amap(p, R)
         w = y - sigma * (a - p.b)
         expanded = False

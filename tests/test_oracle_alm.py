@@ -269,3 +269,30 @@ def test_penalty_schedule_keeps_the_edge_ratio():
     assert math.isclose(val, math.sqrt(5.0), rel_tol=1e-5)
     s = [h["sigma"] for h in out["history"]]
     assert s[-1] > s[0] and max(s) <= 100.0
+
+
+@pytest.mark.parametrize("n", [7, 9])
+def test_lbfgs_inner_solver_odd_cycles(n):
+    """The L-BFGS subproblem solver (exact quartic line search along its
+    directions) reaches the same closed forms as gradient descent."""
+    val, _ = _solve_value(oracle.maxcut_sdp(gen.cycle_graph(n)), 2, inner_solver="lbfgs")
+    assert math.isclose(val, n * (1 + math.cos(math.pi / n)) / 2, rel_tol=1e-6)
+
+
+def test_lbfgs_inner_solver_complete_graph_and_lovasz():
+    val, _ = _solve_value(oracle.maxcut_sdp(gen.complete_graph(6)), 3, inner_solver="lbfgs")
+    assert math.isclose(val, 9.0, rel_tol=1e-6)
+    val, _ = _solve_value(oracle.lovasz_sdp(gen.cycle_graph(5)), 3, eps=1e-6, sigma_edges=5.0, inner_solver="lbfgs")
+    assert math.isclose(val, math.sqrt(5.0), rel_tol=1e-5)
+
+
+def test_lbfgs_and_gd_solves_agree_on_a_random_graph():
+    """Both subproblem solvers reach one SDP value on G(300, 1200) with N(0,1)
+    weights, and L-BFGS does not need more gradient evaluations."""
+    p = oracle.maxcut_sdp(gen.er_graph(300, 1200, 3, "gauss"))
+    vals = {}
+    for solver in ("gd", "lbfgs"):
+        val, out = _solve_value(p, 4, eps=1e-7, inner_solver=solver)
+        vals[solver] = (val, sum(h["inner_iters"] for h in out["history"]))
+    assert math.isclose(vals["gd"][0], vals["lbfgs"][0], rel_tol=1e-6)
+    assert vals["lbfgs"][1] <= vals["gd"][1]
