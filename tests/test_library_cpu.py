@@ -158,3 +158,17 @@ def test_psd_step_matches_the_oracle_curvature_step(kind, q):
     S = m.psd_step(theta, M4, sigma)
     S_o, phi_o, _ = oracle.curvature_step(po, w, sig_vec, V)
     assert np.linalg.norm(S - S_o) <= 1e-7 * max(1.0, np.linalg.norm(S_o))
+
+
+def test_psd_step_rejects_bad_arguments():
+    import paper_2505_15775_amd as m
+
+    with pytest.raises(m.AlmBmError):
+        m.psd_step(np.zeros(9), np.eye(45), 1.0)           # q > 8
+    with pytest.raises(m.AlmBmError):
+        m.psd_step(np.array([-1.0]), np.eye(1), 0.0)       # sigma must be positive
+    with pytest.raises(m.AlmBmError):
+        m.psd_step(np.array([-1.0]), np.array([[np.nan]]), 1.0)
+    # a positive Ritz value gives no step; a negative one the closed form -theta / (sigma M4)
+    assert m.psd_step(np.array([0.5]), np.array([[2.0]]), 1.0)[0, 0] == 0.0
+    assert abs(m.psd_step(np.array([-0.5]), np.array([[2.0]]), 1.0)[0, 0] - 0.25) <= 1e-12
