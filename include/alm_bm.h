@@ -196,6 +196,28 @@ alm_bm_status alm_bm_objective_grad(alm_bm_problem* prob, int32_t r, const void*
                                     const double* y, double sigma, double* f, void* G,
                                     double* Av, hipStream_t stream);
 
+/* alm_bm_objective_grad without a handle and without any device allocation,
+ * for callers that cannot allocate: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc.  desc (host) describes a DIAG
+ * family problem in ALM_BM_F64 storage with j_coef = 0; only n, nnz, row_ptr,
+ * col_idx, val, ell_width, diag, m and b are read (no validation of the
+ * pattern, no hub rows).  r: 1..128.  R, y, f, G (nullable), Av (nullable):
+ * device doubles, as for alm_bm_objective_grad.  The per-block partial sums
+ * live in a static device array of the library, one per GPU (4096 x 15 doubles
+ * plus one scalar block, about 0.5 MB, held until the process ends), whose
+ * address is resolved on the first call on each device (the runtime then loads
+ * the array's code object, a one-time set-up: make that first call outside
+ * graph capture and before memory is budgeted); every call on one GPU
+ * shares it, so calls that overlap on one GPU (other streams or threads) race,
+ * while calls in order on one stream do not.  The stream must belong to the
+ * current device.  Results equal those of alm_bm_objective_grad on a handle
+ * with default tiles.  Errors: ALM_BM_ERR_INVALID_ARG (null pointer, n or r out
+ * of range, inconsistent sizes), ALM_BM_ERR_UNSUPPORTED (TRACE_EDGES, F32 or
+ * BF16, j_coef != 0).                                                          */
+alm_bm_status alm_bm_objective_grad_noalloc(const alm_bm_problem_desc* desc, int32_t r, const double* R,
+                                            const double* y, double sigma, double* f, double* G, double* Av,
+                                            hipStream_t stream);
+
 /* Cost product P = C X with C = S + Diag(d) (the sparse product that dominates
  * the gradient evaluation and the exact line search, Sec. 6): X device n x r in
  * the storage precision, P device n x r in the arithmetic precision (double for

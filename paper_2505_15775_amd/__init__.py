@@ -14,7 +14,8 @@ import torch
 from . import _lib
 from ._lib import AlmBmError, check, default_options, lib  # noqa: F401
 
-__all__ = ["Problem", "Batch", "AlmBmError", "default_options", "maxcut_cost", "TORCH_DTYPES"]
+__all__ = ["Problem", "Batch", "AlmBmError", "default_options", "maxcut_cost", "objective_grad_noalloc",
+           "TORCH_DTYPES"]
 
 TORCH_DTYPES = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16}
 
@@ -46,6 +47,18 @@ def maxcut_cost(n, ei, ej, w):
           "maxcut_cost_host")
     k = nnz.value
     return rp, ci[:k].copy(), cv[:k].copy(), dg
+
+
+def objective_grad_noalloc(desc, R, y, sigma, f, G=None, Av=None, stream=None):
+    """alm_bm_objective_grad_noalloc: eq. (AL-BM) objective, gradient and
+    A(RR^T) of a DIAG-family FP64 problem described by ``desc`` (an
+    ``_lib.Desc``, e.g. ``Problem.desc``), with no handle and no allocation.
+    Every output is caller-owned: f (1 double), G (n x r double, or None), Av
+    (n doubles, or None), all on R's device."""
+    if R.dtype != torch.float64 or R.dim() != 2 or not R.is_contiguous():
+        raise ValueError("R must be a contiguous n x r float64 tensor")
+    check(lib.alm_bm_objective_grad_noalloc(C.byref(desc), R.shape[1], _ptr(R), _ptr(y), float(sigma), _ptr(f),
+                                            _ptr(G), _ptr(Av), _stream(stream)), "objective_grad_noalloc")
 
 
 def psd_step(theta, M4, sigma):

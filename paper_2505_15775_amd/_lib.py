@@ -118,6 +118,7 @@ EXPORTS = [
     "alm_bm_inner_solve", "alm_bm_ws_features", "alm_bm_ws_pool", "alm_bm_ws_param_count", "alm_bm_ws_work_size",
     "alm_bm_ws_forward", "alm_bm_ws_loss_grad", "alm_bm_ws_adam", "alm_bm_ws_ridge_fit",
     "alm_bm_batch_create", "alm_bm_batch_destroy", "alm_bm_batch_offsets", "alm_bm_batch_solve",
+    "alm_bm_objective_grad_noalloc",
 ]
 
 vp = C.c_void_p
@@ -135,6 +136,7 @@ def _load():
         "alm_bm_create": (i32, [C.POINTER(Desc), vp, C.POINTER(vp)]),
         "alm_bm_destroy": (i32, [vp]),
         "alm_bm_objective_grad": (i32, [vp, i32, vp, vp, f64, vp, vp, vp, vp]),
+        "alm_bm_objective_grad_noalloc": (i32, [C.POINTER(Desc), i32, vp, vp, f64, vp, vp, vp, vp]),
         "alm_bm_cost_apply": (i32, [vp, i32, vp, vp, vp, vp]),
         "alm_bm_line_search": (i32, [vp, i32, vp, vp, vp, f64, vp, vp, vp]),
         "alm_bm_dual_update": (i32, [vp, vp, f64, vp, vp, vp]),

@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "alm_bm.h"
+#include "api_internal.hpp"
 #include "launch.hpp"
 
 using namespace almbm;
@@ -24,6 +25,8 @@ static alm_bm_status fail(alm_bm_status s, const std::string& msg) {
   g_err = msg;
   return s;
 }
+
+alm_bm_status almbm::set_error(alm_bm_status s, const std::string& msg) { return fail(s, msg); }
 
 #define HIPCHK(x)                                                                                         \
   do {                                                                                                    \
@@ -323,7 +326,7 @@ extern "C" void alm_bm_abi_sizes(int64_t* out) {
 
 // --------------------------------------------------------------------- create / destroy
 
-static int row_blocks(long n) {
+int almbm::row_blocks(long n) {
   long nb = (n + 63) / 64;
   if (nb < 8) nb = 8;
   if (nb > 4096) nb = 4096;

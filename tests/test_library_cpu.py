@@ -109,6 +109,31 @@ def test_create_rejects_bad_arguments_before_any_launch():
     assert st == -1
 
 
+def test_objective_grad_noalloc_rejects_bad_arguments_before_any_launch():
+    """The no-allocation objective/gradient call checks its descriptor on the
+    host (nothing is dereferenced or launched before the checks pass)."""
+    from paper_2505_15775_amd import _lib
+
+    fake = C.c_void_p(0x1000)  # never dereferenced: every call below fails its checks first
+    d = _lib.Desc()
+    d.n, d.m, d.b, d.precision, d.cons_kind = 10, 10, 0x1000, 0, 0
+    lib = _lib.lib
+    assert lib.alm_bm_objective_grad_noalloc(None, 4, fake, fake, 1.0, fake, None, None, None) == -1
+    assert lib.alm_bm_objective_grad_noalloc(C.byref(d), 4, None, fake, 1.0, fake, None, None, None) == -1
+    assert lib.alm_bm_objective_grad_noalloc(C.byref(d), 129, fake, fake, 1.0, fake, None, None, None) == -1
+    assert b"r must be" in lib.alm_bm_last_error()
+    d.precision = 1
+    assert lib.alm_bm_objective_grad_noalloc(C.byref(d), 4, fake, fake, 1.0, fake, None, None, None) == -6
+    d.precision, d.cons_kind = 0, 1
+    assert lib.alm_bm_objective_grad_noalloc(C.byref(d), 4, fake, fake, 1.0, fake, None, None, None) == -6
+    d.cons_kind, d.j_coef = 0, 1.0
+    assert lib.alm_bm_objective_grad_noalloc(C.byref(d), 4, fake, fake, 1.0, fake, None, None, None) == -6
+    d.j_coef, d.m = 0.0, 9
+    assert lib.alm_bm_objective_grad_noalloc(C.byref(d), 4, fake, fake, 1.0, fake, None, None, None) == -1
+    d.m, d.nnz, d.ell_width = 10, 7, 2  # ELL needs nnz = n * ell_width
+    assert lib.alm_bm_objective_grad_noalloc(C.byref(d), 4, fake, fake, 1.0, fake, None, None, None) == -1
+
+
 def test_set_tiles_rejects_bad_values_without_device():
     from paper_2505_15775_amd import _lib
 
