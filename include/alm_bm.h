@@ -166,7 +166,9 @@ typedef struct {
   double pobj;               /* <C, RR^T>                                             */
   double dobj;               /* b^T y                                                 */
   double pinf, dinf, gap, kkt; /* relative KKT terms (Sec. 6) at (RR^T, y)            */
-  double lam_min;            /* lambda_min(C - A* y) estimate (Lanczos, an upper bound) */
+  double lam_min;            /* lambda_min(C - A* y) estimate: the smaller of the Ritz
+                                value and the Rayleigh quotient of RR^T, both upper
+                                bounds; dinf is computed from it                    */
   double time_s;             /* wall time of the solve                                */
   double time_lanczos_s;     /* of which in Lanczos                                   */
   int32_t promoted_at_outer; /* BF16 ladder switch point (-1 = none)                  */
@@ -174,6 +176,12 @@ typedef struct {
   double sigma_final;        /* penalty at the end (differs from sigma only with the
                                 schedule)                                              */
   int32_t sigma_increases;   /* schedule steps taken                                   */
+  double lanczos_resid;      /* Ritz residual ||Z v - theta v|| of the Lanczos run
+                                behind lam_min.  A solve returns ALM_BM_OK only when
+                                this met the Lanczos tolerance and theta did not
+                                exceed the Rayleigh quotient <Z, RR^T>/||R||_F^2
+                                (else the Ritz value is not the bottom of the
+                                spectrum and dinf is not certified)               */
 } alm_bm_result;
 
 /* --------------------------------------------------------------------------- */

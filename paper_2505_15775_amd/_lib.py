@@ -104,6 +104,7 @@ class Result(C.Structure):
         ("time_promoted_s", C.c_double),
         ("sigma_final", C.c_double),
         ("sigma_increases", C.c_int32),
+        ("lanczos_resid", C.c_double),
     ]
 
     def as_dict(self):

@@ -1144,6 +1144,8 @@ extern "C" alm_bm_status alm_bm_psd_step(int32_t q, const double* theta, const d
   const std::vector<double> th(theta, theta + q), m4(M4, M4 + (size_t)np * np);
   for (double v : m4)
     if (!std::isfinite(v)) return fail(ALM_BM_ERR_NUMERIC, "psd_step: non-finite M4");
+  for (double v : th)
+    if (!std::isfinite(v)) return fail(ALM_BM_ERR_NUMERIC, "psd_step: non-finite theta");
   const std::vector<double> out = block_subproblem(q, th, m4, np, sigma);
   std::copy(out.begin(), out.end(), S);
   return ALM_BM_OK;
@@ -1269,25 +1271,53 @@ extern "C" alm_bm_status alm_bm_lanczos_min_eig(alm_bm_problem* p, const double*
 
 struct KktVals {
   double pinf, dinf, gap, kkt, pobj, dobj;
+  double rq;  // <Z(y), RR^T> / ||R||_F^2, an upper bound on lambda_min(Z(y)) (+inf when R = 0)
 };
 
-// pobj and pinf at R, dobj at y (device y), lambda_min given.
+// Rayleigh quotient of X = RR^T for the slack Z(y) = C - A*(y), from the totals
+// of an objective pass at (R, y): <Z, X> = <C, X> - y^T A(X) and
+// y^T A(X) = b^T y - <y, b - A(X)>.  lambda_min(Z) is at most the
+// X-weighted mean of Z's Rayleigh quotients, i.e. this value.
+static double slack_rq(double pobj, double dobj, double ybma, double rr) {
+  return rr > 0.0 ? (pobj - dobj + ybma) / rr : INFINITY;
+}
+
+// Relative KKT terms of Sec. 6 at (RR^T, y).  lam is the caller's estimate of
+// lambda_min(Z(y)) (a Ritz value, so an upper bound); the dual infeasibility
+// uses min(lam, rq), the tighter of two upper bounds.
+static void kkt_terms(double pobj, double dobj, double pinf, double lam, double rq, double cnorm, KktVals& k) {
+  k.pobj = pobj;
+  k.dobj = dobj;
+  k.pinf = pinf;
+  k.rq = rq;
+  k.dinf = std::fabs(std::min(0.0, std::min(lam, rq))) / (1.0 + cnorm);
+  k.gap = std::fabs(pobj - dobj) / (1.0 + std::fabs(pobj) + std::fabs(dobj));
+  k.kkt = std::max(k.pinf, std::max(k.dinf, k.gap));
+}
+
+// pobj and pinf at R, dobj at y (device y), lambda_min given.  tighten: the
+// dual term takes min(lam, rq) (inside the solve); otherwise lam as given
+// (alm_bm_kkt, the plain Sec. 6 measure for a supplied lambda_min).
 template <typename T>
 static alm_bm_status kkt_eval(alm_bm_problem* p, int r, const T* R, const double* y, double lam, KktVals& k,
-                              hipStream_t st) {
+                              hipStream_t st, bool tighten = true) {
   enqueue_objgrad<T>(p, r, R, y, 0.0, nullptr, p->Av, p->sc_api, 0, nullptr, st);
   launch_dual(p->d.m, p->Av, p->d.b, y, nullptr, 0.0, p->part_vec, p->sc_api, p->bnorm, nullptr, st);
   HIPCHK(hipMemcpyAsync(p->sc_host, p->sc_api, sizeof(DevScalars), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   HIPCHK(hipGetLastError());
   const DevScalars& s = *p->sc_host;
-  k.pobj = s.tot[P_C0];
-  k.dobj = s.dobj;
-  k.pinf = s.pinf;
-  k.dinf = std::fabs(std::min(0.0, lam)) / (1.0 + p->cnorm);
-  k.gap = std::fabs(k.pobj - k.dobj) / (1.0 + std::fabs(k.pobj) + std::fabs(k.dobj));
-  k.kkt = std::max(k.pinf, std::max(k.dinf, k.gap));
+  const double rq = slack_rq(s.tot[P_C0], s.dobj, s.tot[P_YBMA], s.tot[P_RR]);
+  kkt_terms(s.tot[P_C0], s.dobj, s.pinf, lam, tighten ? rq : INFINITY, p->cnorm, k);
+  k.rq = rq;
   return ALM_BM_OK;
+}
+
+// A Ritz value certifies the dual infeasibility term only if its residual met
+// the Lanczos tolerance and it does not exceed the Rayleigh quotient of X (a
+// Ritz value above it belongs to an eigenvalue other than the smallest).
+static bool lanczos_certifies(double theta, double resid, double ltol, double rq) {
+  return std::isfinite(theta) && resid <= ltol && theta <= rq + ltol;
 }
 
 extern "C" alm_bm_status alm_bm_kkt(alm_bm_problem* p, int32_t r, const void* R, const double* y, double lam_min,
@@ -1296,7 +1326,7 @@ extern "C" alm_bm_status alm_bm_kkt(alm_bm_problem* p, int32_t r, const void* R,
   STCHK(check_r(p, r));
   KktVals k{};
   alm_bm_status s = with_storage(p->d.precision, [&]<typename T>() {
-    return kkt_eval<T>(p, r, static_cast<const T*>(R), y, lam_min, k, st);
+    return kkt_eval<T>(p, r, static_cast<const T*>(R), y, lam_min, k, st, false);
   });
   if (s < 0) return s;
   kkt_out[0] = k.pinf;
@@ -1583,7 +1613,7 @@ static alm_bm_status solve_impl(alm_bm_problem* p, const alm_bm_options& o, T* R
       }
     }
     HIPCHK(hipMemcpyAsync(y, p->ybuf, d.m * sizeof(double), hipMemcpyDeviceToDevice, st));
-    double lam = lo.theta;
+    double lam = lo.theta, lres = lo.resid;
     if (expanded) {
       LanczosOut l2;
       const double tl2 = now_s();
@@ -1591,6 +1621,7 @@ static alm_bm_status solve_impl(alm_bm_problem* p, const alm_bm_options& o, T* R
                         o.lanczos_restarts));
       acc.time_lanczos_s += now_s() - tl2;
       lam = l2.theta;
+      lres = l2.resid;
     }
     KktVals kv{};
     STCHK(kkt_eval<T>(p, w, R, y, lam, kv, st));
@@ -1607,15 +1638,18 @@ static alm_bm_status solve_impl(alm_bm_problem* p, const alm_bm_options& o, T* R
     acc.dinf = kv.dinf;
     acc.gap = kv.gap;
     acc.kkt = kv.kkt;
-    acc.lam_min = lam;
+    acc.lam_min = std::min(lam, kv.rq);
+    acc.lanczos_resid = lres;
     pinf_prev = kv.pinf;
     k_done = k + 1;
+    const bool cert = lanczos_certifies(lam, lres, ltol, kv.rq);
     if (o.verbose)
       std::fprintf(stderr,
-                   "[almbm] k=%d inner=%d flag=%d r=%d theta=%.3e lanczos=%d pinf=%.3e dinf=%.3e gap=%.3e "
-                   "pobj=%.10e sigma=%.3e t=%.2fs\n",
-                   k, iters, flag, r, lo.theta, lo.iters, kv.pinf, kv.dinf, kv.gap, kv.pobj, sigma, now_s() - t0);
-    if (kv.kkt <= o.eps_kkt) return ALM_BM_OK;
+                   "[almbm] k=%d inner=%d flag=%d r=%d theta=%.3e rq=%.3e lres=%.2e%s lanczos=%d pinf=%.3e "
+                   "dinf=%.3e gap=%.3e pobj=%.10e sigma=%.3e t=%.2fs\n",
+                   k, iters, flag, r, lam, kv.rq, lres, cert ? "" : "(uncertified)", lo.iters, kv.pinf, kv.dinf,
+                   kv.gap, kv.pobj, sigma, now_s() - t0);
+    if (kv.kkt <= o.eps_kkt && cert) return ALM_BM_OK;
     // penalty schedule: raise sigma when the infeasibility did not fall enough
     if (o.sigma_growth > 1.0 && kv.pinf > o.pinf_reduction * pinf_last && sigma < o.sigma_max) {
       sigma = std::min(o.sigma_max, sigma * o.sigma_growth);
@@ -2409,7 +2443,7 @@ static alm_bm_status batch_solve_impl(alm_bm_batch* b, const alm_bm_options& o, 
       }
     }
     launch_copy_active(N, p->ybuf, y, b->active_dev, p->tab, p->nblk, st);
-    std::vector<double> lam(L.theta);
+    std::vector<double> lam(L.theta), lres(L.resid);
     double tlan2 = 0.0;
     if (any) {
       BatchLanczos L2;
@@ -2418,7 +2452,10 @@ static alm_bm_status batch_solve_impl(alm_bm_batch* b, const alm_bm_options& o, 
                           o.lanczos_restarts));
       tlan2 = now_s() - t2;
       for (int q = 0; q < count; ++q)
-        if (expanded[q]) lam[q] = L2.theta[q];
+        if (expanded[q]) {
+          lam[q] = L2.theta[q];
+          lres[q] = L2.resid[q];
+        }
     }
     // KKT per instance: <C, RR^T> and pinf at R, b^T y at y
     batch_enqueue_objgrad<T>(b, R, y, 0.0, st);
@@ -2430,23 +2467,24 @@ static alm_bm_status batch_solve_impl(alm_bm_batch* b, const alm_bm_options& o, 
     HIPCHK(hipGetLastError());
     for (int q = 0; q < count; ++q) {
       if (!active[q]) continue;
-      const double pobj = hs[q].tot[P_C0], dobj = hs[q].dobj, pinf = hs[q].pinf;
-      const double dinf = std::fabs(std::min(0.0, lam[q])) / (1.0 + b->cnorm[q]);
-      const double gap = std::fabs(pobj - dobj) / (1.0 + std::fabs(pobj) + std::fabs(dobj));
-      const double kkt = std::max(pinf, std::max(dinf, gap));
-      if (!std::isfinite(kkt)) return fail(ALM_BM_ERR_NUMERIC, "batch_solve: non-finite KKT in instance " + std::to_string(q));
+      KktVals kv{};
+      const double rq = slack_rq(hs[q].tot[P_C0], hs[q].dobj, hs[q].tot[P_YBMA], hs[q].tot[P_RR]);
+      kkt_terms(hs[q].tot[P_C0], hs[q].dobj, hs[q].pinf, lam[q], rq, b->cnorm[q], kv);
+      if (!std::isfinite(kv.kkt))
+        return fail(ALM_BM_ERR_NUMERIC, "batch_solve: non-finite KKT in instance " + std::to_string(q));
       res[q].outer = k + 1;
       res[q].rank = r[q];
-      res[q].pobj = pobj;
-      res[q].dobj = dobj;
-      res[q].pinf = pinf;
-      res[q].dinf = dinf;
-      res[q].gap = gap;
-      res[q].kkt = kkt;
-      res[q].lam_min = lam[q];
+      res[q].pobj = kv.pobj;
+      res[q].dobj = kv.dobj;
+      res[q].pinf = kv.pinf;
+      res[q].dinf = kv.dinf;
+      res[q].gap = kv.gap;
+      res[q].kkt = kv.kkt;
+      res[q].lam_min = std::min(lam[q], rq);
+      res[q].lanczos_resid = lres[q];
       res[q].time_lanczos_s += (tlan + tlan2) / nactive;
-      pinf_prev[q] = pinf;
-      if (kkt <= o.eps_kkt) {
+      pinf_prev[q] = kv.pinf;
+      if (kv.kkt <= o.eps_kkt && lanczos_certifies(lam[q], lres[q], ltol[q], rq)) {
         active[q] = 0;
         st_q[q] = ALM_BM_OK;
         res[q].time_s = now_s() - t0;

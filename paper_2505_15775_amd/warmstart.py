@@ -166,24 +166,41 @@ class WarmStartModel:
 
 
 def solve_warm(prob, model, r_max=None, fallback_outer=5, seed=1, **opts):
-    """Solve from the learned start, falling back to the default start (y = 0,
-    rank 16 unit rows) when the warm run hits a numerical error, or when after
-    `fallback_outer` outer iterations its KKT measure is worse than at its own
-    start.  Returns (status, result, R, y, info)."""
+    """Solve from the learned start (predicted y0 and rank r0), with the
+    fallback of solve_from.  Returns (status, result, R, y, info)."""
     import gen
 
-    opts = dict(opts)
-    max_outer = int(opts.pop("max_outer", 1000))
     t0 = time.perf_counter()
     F = features(prob)
     y0 = model.predict_y0(prob, F)
     r0 = model.predict_r0(pooled(F), prob.n, r_max or prob.r_max)
     R0 = gen.init_factor(prob.n, r0, seed)
     t_pred = time.perf_counter() - t0
-    info = {"r0": r0, "predict_s": t_pred, "fallback": False}
+    st, res, R, y, info = solve_from(prob, R0, y0, fallback_outer=fallback_outer, seed=seed, **opts)
+    info["r0"] = r0
+    info["predict_s"] = t_pred
+    info["total_s"] = time.perf_counter() - t0
+    return st, res, R, y, info
+
+
+def solve_from(prob, R0, y0, fallback_outer=5, seed=1, **opts):
+    """Solve from a proposed start (R0 host n x r0, y0 device m), falling back
+    to the default start (y = 0, rank min(16, r_max) unit rows) when the warm
+    run hits a numerical error or a rejected argument, or when after
+    `fallback_outer` outer iterations its KKT measure is worse than at its own
+    start.  Returns (status, result, R, y, info); info["fallback"] tells
+    whether the default start was used."""
+    import gen
+
+    opts = dict(opts)
+    max_outer = int(opts.pop("max_outer", 1000))
+    t0 = time.perf_counter()
+    info = {"fallback": False}
     try:
         theta, _, _, _ = prob.lanczos_min_eig(y0, max_iter=min(40, prob.desc.lanczos_kmax), tol=0.0, want_vector=False)
-        k0 = prob.kkt(prob.factor(torch.from_numpy(R0)), y0, theta)["kkt"]
+        k0 = prob.kkt(prob.factor(torch.from_numpy(np.ascontiguousarray(R0))), y0, theta)["kkt"]
+        if not math.isfinite(k0):
+            raise FloatingPointError(f"KKT measure at the proposed start is {k0}")
         st, res, R, y = prob.solve(R0, y0, max_outer=min(fallback_outer, max_outer), **opts)
         if st != 0 and not (res["kkt"] < k0):
             raise FloatingPointError(f"warm start not improving: kkt {res['kkt']:.3e} vs start {k0:.3e}")
@@ -193,10 +210,11 @@ def solve_warm(prob, model, r_max=None, fallback_outer=5, seed=1, **opts):
             res2["inner_total"] += res["inner_total"]
             res2["time_s"] += res["time_s"]
             res = res2
-    except (FloatingPointError, _lib.AlmBmError) as e:
+    except (FloatingPointError, ValueError, _lib.AlmBmError) as e:
         info["fallback"] = True
         info["reason"] = str(e)
-        st, res, R, y = prob.solve(gen.init_factor(prob.n, 16, seed), None, max_outer=max_outer, **opts)
+        r_fb = min(16, prob.r_max)
+        st, res, R, y = prob.solve(gen.init_factor(prob.n, r_fb, seed), None, max_outer=max_outer, **opts)
     info["total_s"] = time.perf_counter() - t0
     return st, res, R, y, info
 

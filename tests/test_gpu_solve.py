@@ -102,6 +102,26 @@ def test_solve_max_outer_exit_returns_valid_outputs():
     assert res["outer"] == 2 and np.all(np.isfinite(R.cpu().numpy())) and np.all(np.isfinite(y.cpu().numpy()))
 
 
+def test_solve_refuses_ok_without_a_certified_lanczos_value():
+    """dinf needs lambda_min of the slack.  A solve restarted at a converged
+    point with a 2-vector Krylov space and no restarts measures a KKT value
+    below eps, but its Ritz residual misses the Lanczos tolerance, so the
+    value is not certified and the solve must not return OK; the residual is
+    reported."""
+    g = gen.er_graph(700, 4000, 21, "gauss")
+    prob = _maxcut(g, r_max=32, kmax=80)
+    st, res, R, y = prob.solve(gen.init_factor(700, 4, 3), eps_kkt=1e-5, max_outer=300)
+    assert st == 0
+    cn = float(np.linalg.norm(oracle.maxcut_sdp(g).C.toarray()))
+    ltol = 0.1 * 1e-5 * (1.0 + cn)
+    assert res["lanczos_resid"] <= ltol
+    st2, res2, _, _ = prob.solve(R.clone(), y, eps_kkt=1e-5, max_outer=3, lanczos_kmax=2, lanczos_restarts=0)
+    print(f"kmax 2: status {st2} kkt {res2['kkt']:.3e} lanczos resid {res2['lanczos_resid']:.3e} (tol {ltol:.3e})")
+    assert st2 == 1 and res2["lanczos_resid"] > ltol
+    assert res2["kkt"] <= 1e-5  # only the missing certificate keeps it from OK
+    prob.close()
+
+
 def test_solve_gpu_matches_oracle_trajectory_short():
     """Same start, same options, a few outer iterations: final objective and
     dual agree with the oracle's run (discrete decisions coincide on this case)."""

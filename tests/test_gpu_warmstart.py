@@ -137,7 +137,9 @@ def test_trained_warm_start_beats_default_start_on_held_out_graphs():
               f"({info['total_s']:.2f}s, r0 {info['r0']}, fallback {info['fallback']}) "
               f"pobj {rd['pobj']:.8e} vs {rw['pobj']:.8e}")
         assert st == 0 and stw == 0
-        assert abs(rd["pobj"] - rw["pobj"]) <= 1e-4 * abs(rd["pobj"])
+        # both meet 1e-5 relative KKT, whose gap term alone allows each objective
+        # about 2e-5 relative from its dual bound
+        assert abs(rd["pobj"] - rw["pobj"]) <= 3e-5 * abs(rd["pobj"])
         tot_d += rd["outer"]
         tot_w += rw["outer"]
         t_d += rd["time_s"]
@@ -145,3 +147,34 @@ def test_trained_warm_start_beats_default_start_on_held_out_graphs():
         prob.close()
     print(f"total outer iterations: default {tot_d}, warm {tot_w}; time {t_d:.2f}s vs {t_w:.2f}s")
     assert tot_w < tot_d
+
+
+@pytest.mark.parametrize("corrupt", ["nan", "huge"])
+def test_warm_start_fallback_on_corrupted_dual(corrupt):
+    """A corrupted proposed dual (NaN entries, or 1e6 everywhere) must not stop
+    the solve: a NaN start falls back to the default start (y = 0, rank
+    min(16, r_max), here below 16), a huge one either recovers or falls back;
+    both end at a point whose KKT measure the oracle (exact lambda_min)
+    confirms, at the default-start solve's objective."""
+    ws = _ws()
+    import paper_2505_15775_amd as almbm
+
+    g = gen.er_graph(1500, 6000, 31, "gauss")
+    po = oracle.maxcut_sdp(g)
+    prob = almbm.Problem.maxcut(g.n, g.ei, g.ej, g.w, precision="f64", r_max=12, lanczos_kmax=60, device=DEV)
+    st_d, rd, _, _ = prob.solve(gen.init_factor(g.n, 8, 1), eps_kkt=1e-6, max_outer=300)
+    assert st_d == 0
+    y0 = torch.full((g.n,), float("nan") if corrupt == "nan" else 1e6, dtype=torch.float64, device=DEV)
+    if corrupt == "nan":
+        y0[::2] = 0.0  # NaN in part of the entries
+    st, res, R, y, info = ws.solve_from(prob, gen.init_factor(g.n, 8, 1), y0, eps_kkt=1e-6, max_outer=300)
+    print(f"{corrupt}: fallback {info['fallback']} ({info.get('reason', '')}) status {st} outer {res['outer']} "
+          f"pobj {res['pobj']:.10e} vs default {rd['pobj']:.10e}")
+    if corrupt == "nan":
+        assert info["fallback"]
+    assert st == 0
+    yh = y.cpu().numpy()
+    kk = oracle.kkt(po, R.cpu().numpy(), yh, lam_min=oracle.min_eig(po, yh))
+    assert kk["kkt"] <= 2e-6
+    assert abs(res["pobj"] - rd["pobj"]) <= 1e-5 * abs(rd["pobj"])
+    prob.close()

@@ -194,6 +194,10 @@ def test_psd_step_rejects_bad_arguments():
         m.psd_step(np.array([-1.0]), np.eye(1), 0.0)       # sigma must be positive
     with pytest.raises(m.AlmBmError):
         m.psd_step(np.array([-1.0]), np.array([[np.nan]]), 1.0)
+    with pytest.raises(m.AlmBmError):
+        m.psd_step(np.array([np.nan, -1.0]), np.eye(3), 1.0)    # a NaN Ritz value is an error, not S = 0
+    with pytest.raises(m.AlmBmError):
+        m.psd_step(np.array([-np.inf]), np.eye(1), 1.0)
     # a positive Ritz value gives no step; a negative one the closed form -theta / (sigma M4)
     assert m.psd_step(np.array([0.5]), np.array([[2.0]]), 1.0)[0, 0] == 0.0
     assert abs(m.psd_step(np.array([-0.5]), np.array([[2.0]]), 1.0)[0, 0] - 0.25) <= 1e-12
