@@ -39,13 +39,18 @@
  *     storage precision (double, float or bfloat16).  y, b, Av and every scalar
  *     are double in every precision mode.
  *   - Indices are 0-based int32.
- *   - All work is enqueued on the given stream; only alm_bm_solve and
- *     alm_bm_lanczos_min_eig synchronise it (the latter to run the small
- *     tridiagonal eigensolve on the host).
+ *   - All work is enqueued on the given stream.  Calls that return host
+ *     results synchronise it: alm_bm_solve, alm_bm_inner_solve,
+ *     alm_bm_lanczos_min_eig (its small tridiagonal eigensolve runs on the
+ *     host), alm_bm_kkt, alm_bm_autotune and alm_bm_batch_solve;
+ *     alm_bm_set_hub_threshold synchronises the device.
  *   - A handle is not thread-safe.  Calls that overlap on one handle race.
- *   - The handle owns its workspace (allocated in alm_bm_create and sized for
- *     r_max and lanczos_kmax); no other call allocates device memory except
- *     alm_bm_solve, which builds HIP graphs of its inner loop.
+ *   - The handle owns its workspace, allocated in alm_bm_create and sized by the
+ *     descriptor (r_max, lanczos_kmax, rank_block_max, lbfgs_memory_max,
+ *     hub_min_degree; BF16 handles also reserve the float factor of the
+ *     precision ladder).  No other call allocates device memory, except that
+ *     alm_bm_solve, alm_bm_inner_solve and alm_bm_batch_solve instantiate HIP
+ *     graphs of their inner loops (runtime-owned).
  */
 #ifndef ALM_BM_H
 #define ALM_BM_H
@@ -105,11 +110,23 @@ typedef struct {
   int32_t r_max;             /* largest rank any call will use (1..128)              */
   int32_t lanczos_kmax;      /* largest Lanczos basis (0 disables Lanczos; <= 512)   */
   int32_t validate;          /* 1: check CSR/ELL and edge list on create (D2H copy)  */
+  /* workspace reserved by alm_bm_create for optional solve features (no later
+     call allocates):                                                                  */
+  int32_t rank_block_max;    /* largest alm_bm_options.rank_block (0 or 1: one-vector
+                                rank steps only; up to 8: n x rank_block_max doubles) */
+  int32_t lbfgs_memory_max;  /* largest alm_bm_options.lbfgs_memory (0: no L-BFGS;
+                                1..8: DIAG family only, two rings of memory + 1
+                                n x r_max vectors, float-sized for BF16 handles)     */
+  int32_t hub_min_degree;    /* DIAG CSR costs: rows with more stored entries are hub
+                                rows (0: twice the average row length, at least 32;
+                                < 0: none).  alm_bm_set_hub_threshold can later
+                                only choose thresholds with at most this many hubs */
 } alm_bm_problem_desc;
 
 typedef struct alm_bm_problem alm_bm_problem;
 
 typedef enum { ALM_BM_STEP_EXACT = 0, ALM_BM_STEP_FIXED = 1 } alm_bm_step_rule;
+typedef enum { ALM_BM_INNER_GD = 0, ALM_BM_INNER_LBFGS = 1 } alm_bm_inner_solver;
 typedef enum { ALM_BM_RANK_ADAPT = 0, ALM_BM_RANK_FIXED = 1 } alm_bm_rank_policy;
 
 /* Options of alm_bm_solve.  alm_bm_default_options() fills the defaults given
@@ -155,7 +172,13 @@ typedef struct {
                                 step): 1 = the closed-form one-vector step; 2..8
                                 = the smallest Ritz vectors below
                                 -tau_rank of a full Lanczos pass, S of the small PSD
-                                subproblem, and the columns of V S^(1/2)           */
+                                subproblem, and the columns of V S^(1/2); at most the
+                                handle's rank_block_max                            */
+  alm_bm_inner_solver inner_solver; /* GD  subproblem solver: gradient descent (eq. GD)
+                                or L-BFGS (the solver of the SDPLR code Sec. 2 names;
+                                DIAG family, needs lbfgs_memory_max >= lbfgs_memory),
+                                both with the exact quartic line search           */
+  int32_t lbfgs_memory;      /* 3      L-BFGS pairs kept (1..8)                       */
 } alm_bm_options;
 
 typedef struct {
@@ -304,12 +327,15 @@ alm_bm_status alm_bm_set_tiles(alm_bm_problem* prob, int32_t variant, int32_t ro
  * product C X a kernel with one workgroup per hub sums that row's neighbour
  * rows with all of the workgroup's lanes, and the row kernels read the sum
  * instead of walking the row with one lane group.  min_degree: 0 = the
- * default (twice the average row length rounded up, at least 32, which is
- * what alm_bm_create applies), > 0 = that threshold, < 0 = no hubs.  hubs: host
- * int32 out, nullable: the number of hub rows.  Allocates the hub sums
- * (2 x hubs x 128 values per precision kept) and frees the previous ones after
- * a device synchronisation; not concurrently with other calls on the handle.
- * No effect (0 hubs) for the TRACE_EDGES family or an ELL cost; rejected on a
+ * default (twice the average row length rounded up, at least 32), > 0 = that
+ * threshold, < 0 = no hubs.  alm_bm_create applies desc.hub_min_degree and
+ * reserves the hub list and sums (2 x hubs x r_max values per precision kept)
+ * for exactly the hubs of that threshold; this call rewrites them in place
+ * after a device synchronisation, allocates nothing, and returns
+ * ALM_BM_ERR_INVALID_ARG for a threshold with more hubs than reserved (a
+ * larger threshold never has more).  Not concurrently with other calls on
+ * the handle.  hubs: host int32 out, nullable: the number of hub rows.  No
+ * effect (0 hubs) for the TRACE_EDGES family or an ELL cost; rejected on a
  * batch.  Results differ from the hub-free pass only in summation order.     */
 alm_bm_status alm_bm_set_hub_threshold(alm_bm_problem* prob, int32_t min_degree, int32_t* hubs);
 

@@ -43,6 +43,7 @@ from .alm import (  # noqa: F401
     line_search_coeffs,
     quartic_argmin,
     inner_gd,
+    inner_lbfgs,
     solve,
     curvature_step,
 )

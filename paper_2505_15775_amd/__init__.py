@@ -101,8 +101,11 @@ class Problem:
 
     @classmethod
     def maxcut(cls, n, ei, ej, w, precision="f64", r_max=32, lanczos_kmax=100, device="cuda", ell=False,
-               validate=True):
-        """MaxCut SDP relaxation (Sec. 6.1): min <C, X>, X_ii = 1, X PSD, C = -L/4."""
+               validate=True, rank_block_max=0, lbfgs_memory_max=0, hub_min_degree=0):
+        """MaxCut SDP relaxation (Sec. 6.1): min <C, X>, X_ii = 1, X PSD, C = -L/4.
+        rank_block_max, lbfgs_memory_max, hub_min_degree: workspace the handle
+        reserves for the block rank step, the L-BFGS inner solver and hub rows
+        (fields of alm_bm_problem_desc)."""
         rp, ci, cv, dg = maxcut_cost(n, ei, ej, w)
         dev = torch.device(device)
         ell_width = 0
@@ -126,12 +129,13 @@ class Problem:
                   col_idx=t_ci.data_ptr(), val=t_cv.data_ptr(), ell_width=ell_width, diag=t_dg.data_ptr(),
                   j_coef=0.0, cons_kind=_lib.CONS_DIAG, m=n, b=t_b.data_ptr(), trace_coef=0.0, n_edges=0,
                   edge_i=0, edge_j=0, precision=_lib.PRECISIONS[precision], r_max=r_max,
-                  lanczos_kmax=lanczos_kmax, validate=int(validate))
+                  lanczos_kmax=lanczos_kmax, validate=int(validate), rank_block_max=int(rank_block_max),
+                  lbfgs_memory_max=int(lbfgs_memory_max), hub_min_degree=int(hub_min_degree))
         return cls(kw, arrays, precision, dev)
 
     @classmethod
     def edges(cls, n, ei, ej, b, trace_coef, j_coef=0.0, cost_csr=None, cost_diag=None, precision="f64",
-              r_max=32, lanczos_kmax=100, device="cuda", validate=True):
+              r_max=32, lanczos_kmax=100, device="cuda", validate=True, rank_block_max=0):
         """Trace row + entry constraints: <c_tr I, X> = b[0], X_ij = b[1+e] for the
         sorted edge list (i < j); cost C = S + Diag(d) - j_coef J with S given as
         (row_ptr, col_idx, val) numpy arrays (off-diagonal) or None."""
@@ -159,7 +163,8 @@ class Problem:
         kw = dict(n=n, nnz=nnz, row_ptr=rp_p, col_idx=ci_p, val=cv_p, ell_width=0, diag=dg_p, j_coef=float(j_coef),
                   cons_kind=_lib.CONS_TRACE_EDGES, m=E + 1, b=t_b.data_ptr(), trace_coef=float(trace_coef),
                   n_edges=E, edge_i=t_ei.data_ptr(), edge_j=t_ej.data_ptr(), precision=_lib.PRECISIONS[precision],
-                  r_max=r_max, lanczos_kmax=lanczos_kmax, validate=int(validate))
+                  r_max=r_max, lanczos_kmax=lanczos_kmax, validate=int(validate),
+                  rank_block_max=int(rank_block_max), lbfgs_memory_max=0, hub_min_degree=-1)
         return cls(kw, arrays, precision, dev)
 
     @classmethod

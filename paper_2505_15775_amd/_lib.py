@@ -21,6 +21,7 @@ PRECISIONS = {"f64": 0, "f32": 1, "bf16": 2}
 CONS_DIAG = 0
 CONS_TRACE_EDGES = 1
 STEP_EXACT, STEP_FIXED = 0, 1
+INNER_GD, INNER_LBFGS = 0, 1
 RANK_ADAPT, RANK_FIXED = 0, 1
 
 
@@ -51,6 +52,9 @@ class Desc(C.Structure):
         ("r_max", C.c_int32),
         ("lanczos_kmax", C.c_int32),
         ("validate", C.c_int32),
+        ("rank_block_max", C.c_int32),
+        ("lbfgs_memory_max", C.c_int32),
+        ("hub_min_degree", C.c_int32),
     ]
 
 
@@ -82,6 +86,8 @@ class Options(C.Structure):
         ("sigma_max", C.c_double),
         ("pinf_reduction", C.c_double),
         ("rank_block", C.c_int32),
+        ("inner_solver", C.c_int32),
+        ("lbfgs_memory", C.c_int32),
     ]
 
 

@@ -42,6 +42,8 @@ alm_bm_status almbm::set_error(alm_bm_status s, const std::string& msg) { return
 
 // --------------------------------------------------------------------- handle
 
+constexpr int kMaxBlockDirHost = 8;  // largest rank_block (directions of a block rank step)
+
 struct alm_bm_problem {
   alm_bm_problem_desc d{};
   double cnorm = 0.0;  // ||C||_F
@@ -86,11 +88,24 @@ struct alm_bm_problem {
   double* ls = nullptr;
   double* lscal = nullptr;
   std::vector<void*> allocs;
-  std::vector<void*> hub_allocs;  // hub list and sums (also in allocs)
-  double* vblk = nullptr;         // block rank step: n x 8 directions, their coefficients, Gram partials
-  double* ycoef = nullptr;
+  double* vblk = nullptr;         // block rank step: n x rank_block_max directions, their coefficients,
+  double* ycoef = nullptr;        //   fourth-moment partials (reserved at create)
   double* gpart = nullptr;
+  int32_t* hub_list = nullptr;    // hub rows: capacity hub_cap rows, sums 2 x hub_cap x r_max per precision
+  double* hub_sum64 = nullptr;
+  float* hub_sum32 = nullptr;
+  long hub_cap = 0;
+  LbfgsState* lbs = nullptr;      // L-BFGS state and rings (lbfgs_memory_max + 1 slots each)
+  void* lb_e = nullptr;
+  void* lb_y = nullptr;
+  long lb_stride = 0;             // elements per ring slot
+  int lb_m = 0;                   // memory of the running solve (0: gradient descent)
 };
+
+template <typename T> static LbfgsRing<T> lbfgs_ring(const alm_bm_problem* p) {
+  if (p->lb_m <= 0) return LbfgsRing<T>{};
+  return LbfgsRing<T>{p->lbs, static_cast<T*>(p->lb_e), static_cast<T*>(p->lb_y), p->lb_stride};
+}
 
 static size_t esize(alm_bm_precision p) { return p == ALM_BM_F64 ? 8 : (p == ALM_BM_F32 ? 4 : 2); }
 
@@ -132,18 +147,13 @@ static int32_t hub_threshold(long nnz, long n) {
   return (int32_t)std::min<long>(INT32_MAX, std::max<long>(32, 2 * avg));
 }
 
-// (Re)build the hub rows of a DIAG-family CSR cost.  min_degree < 0: none;
-// 0: the default threshold; > 0: rows with more than min_degree entries.
-static alm_bm_status build_hubs(alm_bm_problem* p, int32_t min_degree) {
+// Hub rows of a DIAG-family CSR cost.  min_degree < 0: none; 0: the default
+// threshold; > 0: rows with more than min_degree entries.  reserve: allocate
+// the hub list and sums for exactly this many hubs (alm_bm_create); otherwise
+// the hubs must fit the capacity reserved then, and the arrays are rewritten
+// in place after a device synchronisation (no allocation).
+static alm_bm_status build_hubs(alm_bm_problem* p, int32_t min_degree, bool reserve) {
   const auto& d = p->d;
-  if (!p->hub_allocs.empty()) {
-    HIPCHK(hipDeviceSynchronize());
-    for (void* q : p->hub_allocs) {
-      (void)hipFree(q);
-      p->allocs.erase(std::find(p->allocs.begin(), p->allocs.end(), q));
-    }
-    p->hub_allocs.clear();
-  }
   for (auto* c : {&p->C64.nh, &p->C32.nh}) *c = 0;
   if (d.cons_kind != ALM_BM_CONS_DIAG || d.ell_width != 0 || d.nnz == 0 || min_degree < 0) return ALM_BM_OK;
   const long n = d.n;
@@ -153,28 +163,32 @@ static alm_bm_status build_hubs(alm_bm_problem* p, int32_t min_degree) {
   std::vector<int32_t> hubs;
   for (long i = 0; i < n; ++i)
     if (hrp[i + 1] - hrp[i] > thr) hubs.push_back((int32_t)i);
-  if (hubs.empty()) return ALM_BM_OK;
   const long nh = (long)hubs.size();
-  int32_t* dh = nullptr;
-  double* hs64 = nullptr;
-  STCHK(dalloc_t(p, &dh, nh));
-  p->hub_allocs.push_back(dh);
-  STCHK(dalloc_t(p, &hs64, 2 * nh * kMaxR));
-  p->hub_allocs.push_back(hs64);
-  HIPCHK(hipMemcpy(dh, hubs.data(), nh * sizeof(int32_t), hipMemcpyHostToDevice));
+  if (reserve) {
+    p->hub_cap = nh;
+    if (nh == 0) return ALM_BM_OK;
+    STCHK(dalloc_t(p, &p->hub_list, nh));
+    STCHK(dalloc_t(p, &p->hub_sum64, 2 * nh * d.r_max));
+    if (d.precision != ALM_BM_F64) STCHK(dalloc_t(p, &p->hub_sum32, 2 * nh * d.r_max));
+  } else if (nh > p->hub_cap) {
+    return fail(ALM_BM_ERR_INVALID_ARG, "set_hub_threshold: " + std::to_string(nh) + " hub rows at threshold " +
+                                            std::to_string(thr) + ", the handle reserved " +
+                                            std::to_string(p->hub_cap) + " (desc.hub_min_degree)");
+  } else {
+    HIPCHK(hipDeviceSynchronize());  // earlier launches may still read the list
+  }
+  if (nh == 0) return ALM_BM_OK;
+  HIPCHK(hipMemcpy(p->hub_list, hubs.data(), nh * sizeof(int32_t), hipMemcpyHostToDevice));
   p->C64.hthr = thr;
-  p->C64.hrow = dh;
-  p->C64.hsum = hs64;
-  p->C64.hsum2 = hs64 + nh * kMaxR;
+  p->C64.hrow = p->hub_list;
+  p->C64.hsum = p->hub_sum64;
+  p->C64.hsum2 = p->hub_sum64 + nh * d.r_max;
   p->C64.nh = (int32_t)nh;
   if (d.precision != ALM_BM_F64) {
-    float* hs32 = nullptr;
-    STCHK(dalloc_t(p, &hs32, 2 * nh * kMaxR));
-    p->hub_allocs.push_back(hs32);
     p->C32.hthr = thr;
-    p->C32.hrow = dh;
-    p->C32.hsum = hs32;
-    p->C32.hsum2 = hs32 + nh * kMaxR;
+    p->C32.hrow = p->hub_list;
+    p->C32.hsum = p->hub_sum32;
+    p->C32.hsum2 = p->hub_sum32 + nh * d.r_max;
     p->C32.nh = (int32_t)nh;
   }
   return ALM_BM_OK;
@@ -313,6 +327,8 @@ extern "C" void alm_bm_default_options(alm_bm_options* o) {
   o->sigma_max = 1e6;
   o->pinf_reduction = 0.25;
   o->rank_block = 1;
+  o->inner_solver = ALM_BM_INNER_GD;
+  o->lbfgs_memory = 3;
 }
 
 extern "C" const char* alm_bm_last_error(void) { return g_err.c_str(); }
@@ -349,6 +365,12 @@ extern "C" alm_bm_status alm_bm_create(const alm_bm_problem_desc* desc, hipStrea
   if (d.r_max < 1 || d.r_max > kMaxR) return fail(ALM_BM_ERR_INVALID_ARG, "create: r_max must be in 1..128");
   if (d.lanczos_kmax < 0 || d.lanczos_kmax > 512)
     return fail(ALM_BM_ERR_INVALID_ARG, "create: lanczos_kmax must be in 0..512");
+  if (d.rank_block_max < 0 || d.rank_block_max > kMaxBlockDirHost)
+    return fail(ALM_BM_ERR_INVALID_ARG, "create: rank_block_max must be in 0..8");
+  if (d.lbfgs_memory_max < 0 || d.lbfgs_memory_max > kMaxLbfgs)
+    return fail(ALM_BM_ERR_INVALID_ARG, "create: lbfgs_memory_max must be in 0..8");
+  if (d.lbfgs_memory_max > 0 && d.cons_kind != ALM_BM_CONS_DIAG)
+    return fail(ALM_BM_ERR_UNSUPPORTED, "create: the L-BFGS inner solver is for the DIAG family");
   if (d.precision != ALM_BM_F64 && d.precision != ALM_BM_F32 && d.precision != ALM_BM_BF16)
     return fail(ALM_BM_ERR_INVALID_ARG, "create: unknown precision");
   if (!d.b) return fail(ALM_BM_ERR_INVALID_ARG, "create: b is null");
@@ -449,7 +471,7 @@ extern "C" alm_bm_status alm_bm_create(const alm_bm_problem_desc* desc, hipStrea
   }
 
   // ---- hub rows (DIAG family, CSR): skewed degrees
-  CK(build_hubs(p, 0));
+  CK(build_hubs(p, d.hub_min_degree, true));
 
   // ---- edge adjacency (host build, one upload)
   if (d.cons_kind == ALM_BM_CONS_TRACE_EDGES) {
@@ -537,6 +559,32 @@ extern "C" alm_bm_status alm_bm_create(const alm_bm_problem_desc* desc, hipStrea
     CK(dalloc_t(p, &p->lpart, (size_t)p->lnb * (p->kmax + 1)));
     CK(dalloc_t(p, &p->lpart2, (size_t)p->lnb));
   }
+  // ---- workspace of optional solve features, reserved here so that no later
+  // call allocates: block rank step, L-BFGS rings, the BF16 ladder's float factor
+  if (d.rank_block_max > 1 && p->kmax > 0) {
+    const int q = d.rank_block_max;
+    const int np = q * (q + 1) / 2, ne = np * (np + 1) / 2;
+    CK(dalloc_t(p, &p->vblk, (size_t)n * q));
+    CK(dalloc_t(p, &p->ycoef, (size_t)q * std::max(p->kmax + 1, q)));
+    CK(dalloc_t(p, &p->gpart, (size_t)p->lnb * ne));
+  }
+  if (d.lbfgs_memory_max > 0) {
+    // float-sized elements for BF16 handles: the ladder's float phase uses the same rings
+    const size_t lbe = d.precision == ALM_BM_BF16 ? sizeof(float) : es;
+    p->lb_stride = ((long)n * d.r_max + 63) / 64 * 64;
+    const size_t bytes = (size_t)(d.lbfgs_memory_max + 1) * (size_t)p->lb_stride * lbe;
+    CK(dalloc(p, &p->lb_e, bytes));
+    CK(dalloc(p, &p->lb_y, bytes));
+    CK(dalloc_t(p, &p->lbs, 1));
+    HK(hipMemset(p->lb_e, 0, bytes));
+    HK(hipMemset(p->lb_y, 0, bytes));
+  }
+  if (d.precision == ALM_BM_BF16) {
+    const size_t bytes = (size_t)n * d.r_max * sizeof(float);
+    CK(dalloc(p, &p->R32, bytes));
+    CK(dalloc(p, &p->G32, bytes));
+    CK(dalloc(p, &p->Rt32, bytes));
+  }
   HK(hipStreamCreateWithFlags(&p->ss, hipStreamNonBlocking));
   HK(hipStreamSynchronize(st));
   HK(hipGetLastError());
@@ -588,12 +636,20 @@ static void enqueue_inner_step(alm_bm_problem* p, int r, T* R, const double* y, 
   DevScalars* sc = p->sc_solve;
   if (d.cons_kind == ALM_BM_CONS_DIAG) {
     V* Q = static_cast<V*>(p->Qbuf);
+    const LbfgsRing<T> lb = lbfgs_ring<T>(p);  // empty: gradient descent
     launch_upd_eval_diag<T>(d.n, r, p->variant, R, G, Q, y, d.b, sigma, p->Av, p->part, sc, refresh, p->tab, p->nblk,
-                            st);
+                            st, lb);
     launch_objgrad_diag<T>(cost_of<T>(p), r, p->variant, R, y, d.b, sigma, G, p->Av, p->part, sc, refresh, p->tab,
-                           p->nblk, st);
+                           p->nblk, st, lb);
     launch_fin_objgrad(p->part, p->nblk, sc, sigma, 1, nullptr, st, p->tab, p->count);
-    launch_quadq_diag<T>(cost_of<T>(p), r, p->variant, G, Q, p->part_c2, sc, p->tab, p->nblk, st);
+    if (lb.s) {
+      // L-BFGS: the direction E = H G and its line-search totals replace G's
+      launch_lbfgs_dots<T>((long)d.n * r, G, lb, p->part, p->nblk, sc, st);
+      launch_fin_lbfgs(p->part, p->nblk, sc, lb.s, st);
+      launch_lbfgs_combine<T>(d.n, r, p->variant, R, G, y, d.b, sigma, p->Av, lb, p->part, sc, p->nblk, st);
+      launch_fin_lsdir(p->part, p->nblk, sc, lb.s, st);
+    }
+    launch_quadq_diag<T>(cost_of<T>(p), r, p->variant, G, Q, p->part_c2, sc, p->tab, p->nblk, st, lb);
     launch_fin_step(p->part_c2, p->nblk, 1, sc, sigma, 0.0, 1, nullptr, nullptr, st, p->tab, p->count);
   } else {
     enqueue_objgrad<T>(p, r, R, y, sigma, G, p->Av, sc, 1, nullptr, st);
@@ -607,6 +663,28 @@ static void enqueue_inner_step(alm_bm_problem* p, int r, T* R, const double* y, 
 static int default_refresh(alm_bm_precision prec) {
   return prec == ALM_BM_F64 ? 32 : (prec == ALM_BM_F32 ? 16 : 8);
 }
+
+// Subproblem solver of a solve: checks the options against the handle's
+// workspace; the returned memory is 0 for gradient descent.
+static alm_bm_status check_inner(const alm_bm_problem* p, const alm_bm_options& o, int& lb_m) {
+  lb_m = 0;
+  if (o.inner_solver == ALM_BM_INNER_GD) return ALM_BM_OK;
+  if (o.inner_solver != ALM_BM_INNER_LBFGS) return fail(ALM_BM_ERR_INVALID_ARG, "unknown inner_solver");
+  if (p->d.cons_kind != ALM_BM_CONS_DIAG || p->tab.inst)
+    return fail(ALM_BM_ERR_UNSUPPORTED, "the L-BFGS inner solver is for single DIAG-family problems");
+  if (o.lbfgs_memory < 1 || o.lbfgs_memory > p->d.lbfgs_memory_max)
+    return fail(ALM_BM_ERR_INVALID_ARG, "lbfgs_memory must be in 1..lbfgs_memory_max of the handle (" +
+                                            std::to_string(p->d.lbfgs_memory_max) + ")");
+  lb_m = o.lbfgs_memory;
+  return ALM_BM_OK;
+}
+
+// Sets the handle's L-BFGS memory for the length of one solve.
+struct InnerScope {
+  alm_bm_problem* p;
+  InnerScope(alm_bm_problem* p_, int m) : p(p_) { p->lb_m = m; }
+  ~InnerScope() { p->lb_m = 0; }
+};
 
 static alm_bm_status check_r(const alm_bm_problem* p, int r) {
   if (r < 1 || r > p->d.r_max) return fail(ALM_BM_ERR_INVALID_ARG, "r must be in 1..r_max");
@@ -824,7 +902,7 @@ extern "C" alm_bm_status alm_bm_set_tiles(alm_bm_problem* p, int32_t variant, in
 extern "C" alm_bm_status alm_bm_set_hub_threshold(alm_bm_problem* p, int32_t min_degree, int32_t* hubs_out) {
   if (!p) return fail(ALM_BM_ERR_INVALID_ARG, "set_hub_threshold: null handle");
   if (p->tab.inst) return fail(ALM_BM_ERR_UNSUPPORTED, "set_hub_threshold: not on a batch");
-  STCHK(build_hubs(p, min_degree));
+  STCHK(build_hubs(p, min_degree, false));
   if (hubs_out) *hubs_out = p->C64.nh;
   return ALM_BM_OK;
 }
@@ -1347,6 +1425,7 @@ struct GraphCache {
   hipGraph_t graph = nullptr;
   int r = -1;
   int refresh = -1;
+  int lb_m = -1;
   const void* R = nullptr;
   void reset() {
     if (exec) (void)hipGraphExecDestroy(exec);
@@ -1379,13 +1458,14 @@ static alm_bm_status inner_solve(alm_bm_problem* p, int r, T* R, const double* y
   const int refresh = o.refresh_every > 0 ? o.refresh_every : default_refresh(sizeof(T) == 8 ? ALM_BM_F64
                                                                   : (sizeof(T) == 4 ? ALM_BM_F32 : ALM_BM_BF16));
   launch_inner_reset(p->sc_solve, tol, o.max_inner, (int)o.step_rule, o.eta_fixed, st);
+  if (p->lb_m > 0) launch_lbfgs_reset(p->lbs, p->lb_m, st);  // each subproblem starts with an empty memory
   const int U = std::max(0, o.graph_unroll);
   int32_t hflag = 0;
   const int max_launch = o.max_inner + 2;
   int launched = 0;
   while (true) {
     if (U > 0) {
-      if (gc.r != r || gc.R != (const void*)R || gc.refresh != refresh) {
+      if (gc.r != r || gc.R != (const void*)R || gc.refresh != refresh || gc.lb_m != p->lb_m) {
         gc.reset();
         HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
         for (int u = 0; u < U; ++u) enqueue_inner_step<T>(p, r, R, y, sigma, G, refresh, st);
@@ -1394,6 +1474,7 @@ static alm_bm_status inner_solve(alm_bm_problem* p, int r, T* R, const double* y
         gc.r = r;
         gc.R = R;
         gc.refresh = refresh;
+        gc.lb_m = p->lb_m;
       }
       HIPCHK(hipGraphLaunch(gc.exec, st));
       launched += U;
@@ -1440,7 +1521,6 @@ static alm_bm_status restride(alm_bm_problem* p, T* R, int ss, int nc, int rd, h
 // (rows, DIAG) or k_gram4_edges (edge rows, weighted by rho, plus the trace
 // row's c_tr^2 tr(S)^2) gives the penalty's quadratic form, the host solves
 // the qv x qv PSD subproblem, and the columns of V S^{1/2} are appended to R.
-constexpr int kMaxBlockDirHost = 8;
 template <typename T>
 static alm_bm_status block_rank_step(alm_bm_problem* p, T* R, int& r, int& w, int r_cap, int rank_block,
                                      double sigma, int kmax, double tau_rank, uint64_t seed, GraphCache& gc,
@@ -1450,11 +1530,8 @@ static alm_bm_status block_rank_step(alm_bm_problem* p, T* R, int& r, int& w, in
   added = 0;
   const int q = std::min(rank_block, r_cap - r);
   if (q < 1) return ALM_BM_OK;
-  if (!p->vblk) {
-    STCHK(dalloc_t(p, &p->vblk, (size_t)n * kMaxBlockDirHost));
-    STCHK(dalloc_t(p, &p->ycoef, (size_t)kMaxBlockDirHost * (p->kmax + 1)));
-    STCHK(dalloc_t(p, &p->gpart, (size_t)p->lnb * 666));
-  }
+  if (!p->vblk || rank_block > d.rank_block_max)
+    return fail(ALM_BM_ERR_INVALID_ARG, "block rank step: rank_block exceeds the handle's rank_block_max");
   LanczosOut lf;
   STCHK(lanczos_pass(p, p->ybuf, kmax, 0.0, seed, false, p->lv, lf, st));
   const int m = lf.iters;
@@ -1690,6 +1767,9 @@ extern "C" alm_bm_status alm_bm_inner_solve(alm_bm_problem* p, const alm_bm_opti
     ~RhoScope() { p->rho = 1.0; }
   } rho_scope{p};
   p->rho = (p->d.cons_kind != ALM_BM_CONS_DIAG && o.sigma_edges > 0.0) ? o.sigma_edges / o.sigma : 1.0;
+  int lb_m = 0;
+  STCHK(check_inner(p, o, lb_m));
+  InnerScope inner_scope(p, lb_m);
   int iters = 0, flag = 0;
   GraphCache gc;
   alm_bm_status s = with_storage(p->d.precision, [&]<typename T>() {
@@ -1718,10 +1798,14 @@ extern "C" alm_bm_status alm_bm_solve(alm_bm_problem* p, const alm_bm_options* o
   if (o.sigma_edges < 0.0) return fail(ALM_BM_ERR_INVALID_ARG, "solve: sigma_edges must be >= 0");
   if (!(o.sigma_growth >= 1.0) || !(o.sigma_max >= o.sigma) || !(o.pinf_reduction > 0.0 && o.pinf_reduction <= 1.0))
     return fail(ALM_BM_ERR_INVALID_ARG, "solve: need sigma_growth >= 1, sigma_max >= sigma, 0 < pinf_reduction <= 1");
-  if (o.rank_block < 1 || o.rank_block > kMaxBlockDirHost)
-    return fail(ALM_BM_ERR_INVALID_ARG, "solve: rank_block must be in 1..8");
+  if (o.rank_block < 1 || o.rank_block > std::max(1, p->d.rank_block_max))
+    return fail(ALM_BM_ERR_INVALID_ARG, "solve: rank_block must be in 1..rank_block_max of the handle (" +
+                                            std::to_string(std::max(1, p->d.rank_block_max)) + ")");
+  int lb_m = 0;
+  STCHK(check_inner(p, o, lb_m));
   HIPCHK(hipStreamSynchronize(st_user));
   hipStream_t st = p->ss;
+  InnerScope inner_scope(p, lb_m);
   // penalty of the edge rows relative to sigma, for the length of this solve
   struct RhoScope {
     alm_bm_problem* p;
@@ -1746,12 +1830,6 @@ extern "C" alm_bm_status alm_bm_solve(alm_bm_problem* p, const alm_bm_options* o
     if (s >= 0 && stalled) {
       // precision ladder: continue with float storage (the float cost copy is resident)
       const long n = p->d.n;
-      const size_t bytes = (size_t)n * p->d.r_max * sizeof(float);
-      if (!p->R32) {
-        STCHK(dalloc(p, &p->R32, bytes));
-        STCHK(dalloc(p, &p->G32, bytes));
-        STCHK(dalloc(p, &p->Rt32, bytes));
-      }
       float* Rf = static_cast<float*>(p->R32);
       launch_convert<bf16, float>((long)n * w, Rb, Rf, st);
       void* Gsave = p->G;
@@ -1978,9 +2056,10 @@ extern "C" alm_bm_status alm_bm_batch_create(int32_t count, const alm_bm_problem
   sd.r_max = rank_stride;
   sd.lanczos_kmax = kmax_all;
   sd.validate = 0;
+  sd.rank_block_max = 0;
+  sd.lbfgs_memory_max = 0;
+  sd.hub_min_degree = -1;  // per-instance row widths: the hub sums (one stride r) do not apply
   BK(alm_bm_create(&sd, st, &b->p));
-  // per-instance row widths: the hub sums (one stride r) do not apply
-  BK(build_hubs(b->p, -1));
   alm_bm_problem* p = b->p;
   // ---- block table: instance q gets ceil(n_q / rows_per_block) blocks
   const long rpb = std::max<long>(256, (N + 8191) / 8192);
@@ -2524,6 +2603,8 @@ extern "C" alm_bm_status alm_bm_batch_solve(alm_bm_batch* b, const alm_bm_option
   if (o.sigma_growth != 1.0)
     return fail(ALM_BM_ERR_UNSUPPORTED, "batch_solve: the penalty schedule (sigma_growth) is for single solves");
   if (o.rank_block != 1) return fail(ALM_BM_ERR_UNSUPPORTED, "batch_solve: rank_block > 1 is for single solves");
+  if (o.inner_solver != ALM_BM_INNER_GD)
+    return fail(ALM_BM_ERR_UNSUPPORTED, "batch_solve: the L-BFGS inner solver is for single solves");
   HIPCHK(hipStreamSynchronize(st_user));
   hipStream_t st = b->p->ss;
   alm_bm_status s = with_storage(b->p->d.precision, [&]<typename T>() {

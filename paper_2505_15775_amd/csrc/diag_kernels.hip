@@ -20,13 +20,15 @@ __global__ void __launch_bounds__(kBlock)
 k_objgrad_diag(Cost<typename Acc<T>::type> C, int r, const T* __restrict__ R,
                const double* __restrict__ y, const double* __restrict__ b, double sigma,
                T* __restrict__ G, double* __restrict__ Av, double* __restrict__ part,
-               const DevScalars* __restrict__ sc_base, int refresh_every, BlockTab tab) {
+               const DevScalars* __restrict__ sc_base, int refresh_every, BlockTab tab, LbfgsRing<T> lb) {
   using V = typename Acc<T>::type;
   const Rows ch = rows_of(C.n, tab);
   const DevScalars* sc = sc_base ? sc_base + ch.inst : nullptr;
   if (sc && sc->flag) return;
   // inside the inner loop this full pass runs only on refresh iterations
   if (sc && refresh_every > 1 && (sc->iter % refresh_every) != 0) return;
+  // L-BFGS: y_k = G_new - G_old into the current y slot (not on the first step)
+  T* __restrict__ yk = (lb.s && sc && sc->iter > 0) ? lb.y + (long)lb.s->cur * lb.stride : nullptr;
   constexpr int RPB = kBlock / LPR;
   const int lane = threadIdx.x % LPR;
   const int slot = threadIdx.x / LPR;
@@ -57,6 +59,13 @@ k_objgrad_diag(Cost<typename Acc<T>::type> C, int r, const T* __restrict__ R,
     V g[VEC];
 #pragma unroll
     for (int v = 0; v < VEC; ++v) g[v] = round_st<T>(V(2) * (p[v] - wv * ri[v]));
+    if (yk) {
+      V go[VEC], dy[VEC];
+      load_frag<T, VEC, FULL>(G + i * r, lane, r, go);
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) dy[v] = g[v] - go[v];
+      store_frag<T, VEC, FULL>(yk + i * r, lane, r, dy);
+    }
     if (G) store_frag<T, VEC, FULL>(G + i * r, lane, r, g);
     V gg = 0, gp = 0, rg = 0;
 #pragma unroll
@@ -123,10 +132,11 @@ k_quad_diag(Cost<typename Acc<T>::type> C, int r, const T* __restrict__ G,
 template <typename T, int LPR, int VEC, bool FULL>
 __global__ void __launch_bounds__(kBlock)
 k_quadq_diag(Cost<typename Acc<T>::type> C, int r, const T* __restrict__ G, typename Acc<T>::type* __restrict__ Q,
-             double* __restrict__ part, const DevScalars* __restrict__ sc_base, BlockTab tab) {
+             double* __restrict__ part, const DevScalars* __restrict__ sc_base, BlockTab tab, LbfgsRing<T> lb) {
   using V = typename Acc<T>::type;
   const Rows ch = rows_of(C.n, tab);
   if (sc_base && sc_base[ch.inst].flag) return;
+  if (lb.s) G = lb.e + (long)lb.s->cur * lb.stride;  // L-BFGS: the product of the direction E
   constexpr int RPB = kBlock / LPR;
   const int lane = threadIdx.x % LPR;
   const int slot = threadIdx.x / LPR;
@@ -161,13 +171,18 @@ template <typename T, int LPR, int VEC, bool FULL>
 __global__ void __launch_bounds__(kBlock)
 k_upd_eval_diag(long n, int r, T* __restrict__ R, T* __restrict__ G, const typename Acc<T>::type* __restrict__ Q,
                 const double* __restrict__ y, const double* __restrict__ b, double sigma, double* __restrict__ Av,
-                double* __restrict__ part, const DevScalars* __restrict__ sc_base, int refresh_every, BlockTab tab) {
+                double* __restrict__ part, const DevScalars* __restrict__ sc_base, int refresh_every, BlockTab tab,
+                LbfgsRing<T> lb) {
   using V = typename Acc<T>::type;
   const Rows ch = rows_of(n, tab);
   const DevScalars* sc = sc_base + ch.inst;
   if (sc->flag) return;
   const int e = sc->iter;
   if (e == 0) return;
+  // the step is R <- R - t D with D = G (gradient descent) or D = E (L-BFGS,
+  // which also writes y_k = G_new - G_old into the current y slot)
+  const T* __restrict__ D = lb.s ? lb.e + (long)lb.s->cur * lb.stride : G;
+  T* __restrict__ yk = lb.s ? lb.y + (long)lb.s->cur * lb.stride : nullptr;
   const bool update_only = refresh_every <= 1 || (e % refresh_every) == 0;
   const V t = static_cast<V>(sc->t);
   constexpr int RPB = kBlock / LPR;
@@ -182,12 +197,17 @@ k_upd_eval_diag(long n, int r, T* __restrict__ R, T* __restrict__ G, const typen
   for (long base = ch.lo; base < ch.hi; base += RPB) {
     const long i = base + slot;
     if (i >= ch.hi) break;
-    V ri[VEC], gi[VEC];
+    V ri[VEC], gi[VEC], di[VEC];
     load_frag<T, VEC, FULL>(R + i * r, lane, r, ri);
     load_frag<T, VEC, FULL>(G + i * r, lane, r, gi);
+    if (yk) load_frag<T, VEC, FULL>(D + i * r, lane, r, di);
+    else {
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) di[v] = gi[v];
+    }
     V rn[VEC];
 #pragma unroll
-    for (int v = 0; v < VEC; ++v) rn[v] = round_st<T>(ri[v] - t * gi[v]);
+    for (int v = 0; v < VEC; ++v) rn[v] = round_st<T>(ri[v] - t * di[v]);
     store_frag<T, VEC, FULL>(R + i * r, lane, r, rn);
     if (update_only) continue;
     V qi[VEC];
@@ -211,6 +231,12 @@ k_upd_eval_diag(long n, int r, T* __restrict__ R, T* __restrict__ G, const typen
     V g[VEC];
 #pragma unroll
     for (int v = 0; v < VEC; ++v) g[v] = round_st<T>(V(2) * (p[v] - wv * rn[v]));
+    if (yk) {
+      V dy[VEC];
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) dy[v] = g[v] - gi[v];
+      store_frag<T, VEC, FULL>(yk + i * r, lane, r, dy);
+    }
     store_frag<T, VEC, FULL>(G + i * r, lane, r, g);
     V gg = 0, gp = 0, rg = 0;
 #pragma unroll
@@ -317,10 +343,11 @@ k_ls_diag(Cost<typename Acc<T>::type> C, int r, const T* __restrict__ R, const T
 template <typename T, int LPR, int VEC, bool FULL>
 __global__ void __launch_bounds__(kBlock)
 k_hub_rows(Cost<typename Acc<T>::type> C, int r, const T* __restrict__ X, typename Acc<T>::type* __restrict__ out,
-           const DevScalars* __restrict__ sc, int refresh_every) {
+           const DevScalars* __restrict__ sc, int refresh_every, LbfgsRing<T> lb) {
   using V = typename Acc<T>::type;
   if (sc && sc->flag) return;
   if (sc && refresh_every > 1 && (sc->iter % refresh_every) != 0) return;
+  if (lb.s) X = lb.e + (long)lb.s->cur * lb.stride;  // L-BFGS line-search product: the direction E
   constexpr int NG = kBlock / LPR;
   constexpr int U = kUnroll;
   const int lane = threadIdx.x % LPR;
@@ -362,49 +389,52 @@ k_hub_rows(Cost<typename Acc<T>::type> C, int r, const T* __restrict__ X, typena
 
 template <typename T, int LPR, int VEC>
 static void launch_hub_cfg(const Cost<typename Acc<T>::type>& C, int r, const T* X, typename Acc<T>::type* out,
-                           const DevScalars* sc, int refresh_every, hipStream_t st) {
+                           const DevScalars* sc, int refresh_every, hipStream_t st, const LbfgsRing<T>& lb) {
   const int nb = C.nh < 65536 ? C.nh : 65536;
   if (r == LPR * VEC)
     hipLaunchKernelGGL((k_hub_rows<T, LPR, VEC, true>), dim3(nb), dim3(kBlock), 0, st, C, r, X, out, sc,
-                       refresh_every);
+                       refresh_every, lb);
   else
     hipLaunchKernelGGL((k_hub_rows<T, LPR, VEC, false>), dim3(nb), dim3(kBlock), 0, st, C, r, X, out, sc,
-                       refresh_every);
+                       refresh_every, lb);
 }
 
 template <typename T, int LPR, int VEC>
 static void launch_objgrad_cfg(const Cost<typename Acc<T>::type>& C, int r, const T* R, const double* y,
                                const double* b, double sigma, T* G, double* Av, double* part,
                                const DevScalars* sc, int refresh_every, const BlockTab& tab, int nblk,
-                               hipStream_t st) {
+                               hipStream_t st, const LbfgsRing<T>& lb) {
   if (r == LPR * VEC)
     hipLaunchKernelGGL((k_objgrad_diag<T, LPR, VEC, true>), dim3(nblk), dim3(kBlock), 0, st, C, r, R, y, b,
-                       sigma, G, Av, part, sc, refresh_every, tab);
+                       sigma, G, Av, part, sc, refresh_every, tab, lb);
   else
     hipLaunchKernelGGL((k_objgrad_diag<T, LPR, VEC, false>), dim3(nblk), dim3(kBlock), 0, st, C, r, R, y, b,
-                       sigma, G, Av, part, sc, refresh_every, tab);
+                       sigma, G, Av, part, sc, refresh_every, tab, lb);
 }
 
 template <typename T, int LPR, int VEC>
 static void launch_quadq_cfg(const Cost<typename Acc<T>::type>& C, int r, const T* G, typename Acc<T>::type* Q,
-                             double* part, const DevScalars* sc, const BlockTab& tab, int nblk, hipStream_t st) {
+                             double* part, const DevScalars* sc, const BlockTab& tab, int nblk, hipStream_t st,
+                             const LbfgsRing<T>& lb) {
   if (r == LPR * VEC)
-    hipLaunchKernelGGL((k_quadq_diag<T, LPR, VEC, true>), dim3(nblk), dim3(kBlock), 0, st, C, r, G, Q, part, sc, tab);
+    hipLaunchKernelGGL((k_quadq_diag<T, LPR, VEC, true>), dim3(nblk), dim3(kBlock), 0, st, C, r, G, Q, part, sc, tab,
+                       lb);
   else
     hipLaunchKernelGGL((k_quadq_diag<T, LPR, VEC, false>), dim3(nblk), dim3(kBlock), 0, st, C, r, G, Q, part, sc,
-                       tab);
+                       tab, lb);
 }
 
 template <typename T, int LPR, int VEC>
 static void launch_upd_eval_cfg(long n, int r, T* R, T* G, const typename Acc<T>::type* Q, const double* y,
                                 const double* b, double sigma, double* Av, double* part, const DevScalars* sc,
-                                int refresh_every, const BlockTab& tab, int nblk, hipStream_t st) {
+                                int refresh_every, const BlockTab& tab, int nblk, hipStream_t st,
+                                const LbfgsRing<T>& lb) {
   if (r == LPR * VEC)
     hipLaunchKernelGGL((k_upd_eval_diag<T, LPR, VEC, true>), dim3(nblk), dim3(kBlock), 0, st, n, r, R, G, Q, y, b,
-                       sigma, Av, part, sc, refresh_every, tab);
+                       sigma, Av, part, sc, refresh_every, tab, lb);
   else
     hipLaunchKernelGGL((k_upd_eval_diag<T, LPR, VEC, false>), dim3(nblk), dim3(kBlock), 0, st, n, r, R, G, Q, y, b,
-                       sigma, Av, part, sc, refresh_every, tab);
+                       sigma, Av, part, sc, refresh_every, tab, lb);
 }
 
 template <typename T, int LPR, int VEC>
@@ -425,103 +455,71 @@ static void launch_ls_cfg(const Cost<typename Acc<T>::type>& C, int r, const T* 
     hipLaunchKernelGGL((k_ls_diag<T, LPR, VEC, false>), dim3(nblk), dim3(kBlock), 0, st, C, r, R, G, y, b, part);
 }
 
-// Tile (lanes per row, columns per lane) for a rank r.  `variant` selects an
-// alternative tile for the same r (autotuner); 0 is the default.
-#define ALMBM_DISPATCH_DIAG(T, FN, ...)                                                   \
-  do {                                                                                    \
-    if constexpr (sizeof(T) == 8) {                                                       \
-      if (r <= 4) FN<T, 4, 1>(__VA_ARGS__);                                               \
-      else if (r <= 8) { if (variant == 1) FN<T, 4, 2>(__VA_ARGS__); else FN<T, 8, 1>(__VA_ARGS__); } \
-      else if (r <= 16) {                                                                 \
-        if (variant == 1) FN<T, 16, 1>(__VA_ARGS__);                                      \
-        else if (variant == 2) FN<T, 4, 4>(__VA_ARGS__);                                  \
-        else FN<T, 8, 2>(__VA_ARGS__);                                                    \
-      } else if (r <= 32) { if (variant == 1) FN<T, 16, 2>(__VA_ARGS__); else FN<T, 8, 4>(__VA_ARGS__); } \
-      else if (r <= 64) FN<T, 16, 4>(__VA_ARGS__);                                        \
-      else FN<T, 32, 4>(__VA_ARGS__);                                                     \
-    } else if constexpr (sizeof(T) == 4) {                                                \
-      if (r <= 4) FN<T, 4, 1>(__VA_ARGS__);                                               \
-      else if (r <= 8) { if (variant == 1) FN<T, 8, 1>(__VA_ARGS__); else FN<T, 4, 2>(__VA_ARGS__); } \
-      else if (r <= 16) {                                                                 \
-        if (variant == 1) FN<T, 8, 2>(__VA_ARGS__);                                       \
-        else if (variant == 2) FN<T, 2, 8>(__VA_ARGS__);                                  \
-        else FN<T, 4, 4>(__VA_ARGS__);                                                    \
-      } else if (r <= 32) { if (variant == 1) FN<T, 4, 8>(__VA_ARGS__); else FN<T, 8, 4>(__VA_ARGS__); } \
-      else if (r <= 64) FN<T, 16, 4>(__VA_ARGS__);                                        \
-      else FN<T, 32, 4>(__VA_ARGS__);                                                     \
-    } else {                                                                              \
-      if (r <= 4) FN<T, 2, 2>(__VA_ARGS__);                                               \
-      else if (r <= 8) { if (variant == 1) FN<T, 1, 8>(__VA_ARGS__); else FN<T, 2, 4>(__VA_ARGS__); } \
-      else if (r <= 16) {                                                                 \
-        if (variant == 1) FN<T, 4, 4>(__VA_ARGS__);                                       \
-        else if (variant == 2) FN<T, 1, 16>(__VA_ARGS__);                                 \
-        else FN<T, 2, 8>(__VA_ARGS__);                                                    \
-      } else if (r <= 32) { if (variant == 1) FN<T, 8, 4>(__VA_ARGS__); else FN<T, 4, 8>(__VA_ARGS__); } \
-      else if (r <= 64) FN<T, 8, 8>(__VA_ARGS__);                                         \
-      else FN<T, 16, 8>(__VA_ARGS__);                                                     \
-    }                                                                                     \
-  } while (0)
 
 template <typename T>
 void launch_hub_rows(const Cost<typename Acc<T>::type>& C, int r, int variant, const T* X,
-                     typename Acc<T>::type* out, const DevScalars* sc, int refresh_every, hipStream_t st) {
+                     typename Acc<T>::type* out, const DevScalars* sc, int refresh_every, hipStream_t st,
+                     const LbfgsRing<T>& lb) {
   if (C.nh <= 0) return;
-  ALMBM_DISPATCH_DIAG(T, launch_hub_cfg, C, r, X, out, sc, refresh_every, st);
+  ALMBM_DISPATCH_DIAG(T, launch_hub_cfg, C, r, X, out, sc, refresh_every, st, lb);
 }
 
 template <typename T>
 void launch_objgrad_diag(const Cost<typename Acc<T>::type>& C, int r, int variant, const T* R, const double* y,
                          const double* b, double sigma, T* G, double* Av, double* part, const DevScalars* sc,
-                         int refresh_every, const BlockTab& tab, int nblk, hipStream_t st) {
-  launch_hub_rows<T>(C, r, variant, R, C.hsum, sc, refresh_every, st);
-  ALMBM_DISPATCH_DIAG(T, launch_objgrad_cfg, C, r, R, y, b, sigma, G, Av, part, sc, refresh_every, tab, nblk, st);
+                         int refresh_every, const BlockTab& tab, int nblk, hipStream_t st, const LbfgsRing<T>& lb) {
+  launch_hub_rows<T>(C, r, variant, R, C.hsum, sc, refresh_every, st, LbfgsRing<T>{});
+  ALMBM_DISPATCH_DIAG(T, launch_objgrad_cfg, C, r, R, y, b, sigma, G, Av, part, sc, refresh_every, tab, nblk, st,
+                      lb);
 }
 
 template <typename T>
 void launch_quadq_diag(const Cost<typename Acc<T>::type>& C, int r, int variant, const T* G,
                        typename Acc<T>::type* Q, double* part, const DevScalars* sc, const BlockTab& tab, int nblk,
-                       hipStream_t st) {
-  launch_hub_rows<T>(C, r, variant, G, C.hsum, sc, 0, st);
-  ALMBM_DISPATCH_DIAG(T, launch_quadq_cfg, C, r, G, Q, part, sc, tab, nblk, st);
+                       hipStream_t st, const LbfgsRing<T>& lb) {
+  launch_hub_rows<T>(C, r, variant, G, C.hsum, sc, 0, st, lb);
+  ALMBM_DISPATCH_DIAG(T, launch_quadq_cfg, C, r, G, Q, part, sc, tab, nblk, st, lb);
 }
 
 template <typename T>
 void launch_upd_eval_diag(long n, int r, int variant, T* R, T* G, const typename Acc<T>::type* Q, const double* y,
                           const double* b, double sigma, double* Av, double* part, const DevScalars* sc,
-                          int refresh_every, const BlockTab& tab, int nblk, hipStream_t st) {
-  ALMBM_DISPATCH_DIAG(T, launch_upd_eval_cfg, n, r, R, G, Q, y, b, sigma, Av, part, sc, refresh_every, tab, nblk, st);
+                          int refresh_every, const BlockTab& tab, int nblk, hipStream_t st, const LbfgsRing<T>& lb) {
+  ALMBM_DISPATCH_DIAG(T, launch_upd_eval_cfg, n, r, R, G, Q, y, b, sigma, Av, part, sc, refresh_every, tab, nblk, st,
+                      lb);
 }
 
 template <typename T>
 void launch_quad_diag(const Cost<typename Acc<T>::type>& C, int r, int variant, const T* G, double* part,
                       const DevScalars* sc, int nblk, hipStream_t st) {
-  launch_hub_rows<T>(C, r, variant, G, C.hsum, sc, 0, st);
+  launch_hub_rows<T>(C, r, variant, G, C.hsum, sc, 0, st, LbfgsRing<T>{});
   ALMBM_DISPATCH_DIAG(T, launch_quad_cfg, C, r, G, part, sc, nblk, st);
 }
 
 template <typename T>
 void launch_ls_diag(const Cost<typename Acc<T>::type>& C, int r, int variant, const T* R, const T* G,
                     const double* y, const double* b, double* part, int nblk, hipStream_t st) {
-  launch_hub_rows<T>(C, r, variant, R, C.hsum, nullptr, 0, st);
-  launch_hub_rows<T>(C, r, variant, G, C.hsum2, nullptr, 0, st);
+  launch_hub_rows<T>(C, r, variant, R, C.hsum, nullptr, 0, st, LbfgsRing<T>{});
+  launch_hub_rows<T>(C, r, variant, G, C.hsum2, nullptr, 0, st, LbfgsRing<T>{});
   ALMBM_DISPATCH_DIAG(T, launch_ls_cfg, C, r, R, G, y, b, part, nblk, st);
 }
 
 #define ALMBM_INST(T)                                                                                     \
   template void launch_objgrad_diag<T>(const Cost<Acc<T>::type>&, int, int, const T*, const double*,      \
                                        const double*, double, T*, double*, double*, const DevScalars*, int, \
-                                       const BlockTab&, int, hipStream_t);                                \
+                                       const BlockTab&, int, hipStream_t, const LbfgsRing<T>&);           \
   template void launch_quadq_diag<T>(const Cost<Acc<T>::type>&, int, int, const T*, Acc<T>::type*, double*, \
-                                     const DevScalars*, const BlockTab&, int, hipStream_t);                \
+                                     const DevScalars*, const BlockTab&, int, hipStream_t,                 \
+                                     const LbfgsRing<T>&);                                                 \
   template void launch_upd_eval_diag<T>(long, int, int, T*, T*, const Acc<T>::type*, const double*,          \
                                         const double*, double, double*, double*, const DevScalars*, int,     \
-                                        const BlockTab&, int, hipStream_t);                                \
+                                        const BlockTab&, int, hipStream_t, const LbfgsRing<T>&);            \
   template void launch_quad_diag<T>(const Cost<Acc<T>::type>&, int, int, const T*, double*,               \
                                     const DevScalars*, int, hipStream_t);                                 \
   template void launch_ls_diag<T>(const Cost<Acc<T>::type>&, int, int, const T*, const T*, const double*,  \
                                   const double*, double*, int, hipStream_t);                              \
   template void launch_hub_rows<T>(const Cost<Acc<T>::type>&, int, int, const T*, Acc<T>::type*,          \
-                                   const DevScalars*, int, hipStream_t);
+                                   const DevScalars*, int, hipStream_t, const LbfgsRing<T>&);
 
 ALMBM_INST(double)
 ALMBM_INST(float)

@@ -51,6 +51,45 @@ struct DevScalars {
   int32_t pad;
 };
 
+// ---- L-BFGS subproblem solver (limited-memory BFGS with the exact quartic
+// line search; the solver of the SDPLR code that Sec. 2 names) ---------------
+//
+// The direction is E = H G with H the L-BFGS inverse-Hessian estimate from the
+// last m pairs (s, y), s = R_new - R = -t E_old, y = G_new - G_old, and the
+// step R <- R - t E takes the exact minimiser t of the quartic along -E.  The
+// two-loop recursion runs on the coefficients of E in the basis {G, E_a, y_a}
+// from inner products kept on the device (s_a^T y_b, y_a^T y_b, and the new
+// gradient's products with every stored vector), so a step streams each
+// stored vector twice (once for the inner products, once to form E) instead
+// of 4m times.
+constexpr int kMaxLbfgs = 8;
+constexpr int kLbfgsSlots = kMaxLbfgs + 1;   // ring slots of E and of y
+constexpr int kLbfgsDots = 5 * kLbfgsSlots;  // inner-product partial slots per block
+
+struct LbfgsState {
+  int32_t m;                       // pairs kept (1..kMaxLbfgs)
+  int32_t cnt;                     // pairs held
+  int32_t cur;                     // slot of the direction E_k (and of y_k)
+  int32_t have;                    // a direction was taken (a pair candidate exists)
+  int32_t ord[kMaxLbfgs];          // slots of the held pairs, oldest first
+  int32_t resets;                  // memory clears (non-descent direction or zero step)
+  int32_t accepted;                // pairs taken
+  double tp[kLbfgsSlots];          // step taken along the direction in each slot (s = -t E)
+  double ee;                       // ||E_k||^2
+  double SY[kMaxLbfgs][kMaxLbfgs]; // s_a^T y_b (pairs in set order)
+  double YY[kMaxLbfgs][kMaxLbfgs]; // y_a^T y_b
+  double cg;                       // E_{k+1} = cg G + sum_a (ce[a] E_ord[a] + cy[a] y_ord[a])
+  double ce[kMaxLbfgs], cy[kMaxLbfgs];
+};
+
+// Device rings of one handle: slot s of E at e + s * stride, of y at y + s * stride.
+template <typename T> struct LbfgsRing {
+  LbfgsState* s = nullptr;
+  T* e = nullptr;
+  T* y = nullptr;
+  long stride = 0;
+};
+
 // Sparse symmetric cost S (off-diagonal) + diagonal, in arithmetic type V.
 template <typename V> struct Cost {
   long n;

@@ -108,4 +108,41 @@ struct SplitAcc {
   }
 };
 
+// Tile (lanes per row, columns per lane) for a rank r.  `variant` selects an
+// alternative tile for the same r (autotuner); 0 is the default.
+#define ALMBM_DISPATCH_DIAG(T, FN, ...)                                                   \
+  do {                                                                                    \
+    if constexpr (sizeof(T) == 8) {                                                       \
+      if (r <= 4) FN<T, 4, 1>(__VA_ARGS__);                                               \
+      else if (r <= 8) { if (variant == 1) FN<T, 4, 2>(__VA_ARGS__); else FN<T, 8, 1>(__VA_ARGS__); } \
+      else if (r <= 16) {                                                                 \
+        if (variant == 1) FN<T, 16, 1>(__VA_ARGS__);                                      \
+        else if (variant == 2) FN<T, 4, 4>(__VA_ARGS__);                                  \
+        else FN<T, 8, 2>(__VA_ARGS__);                                                    \
+      } else if (r <= 32) { if (variant == 1) FN<T, 16, 2>(__VA_ARGS__); else FN<T, 8, 4>(__VA_ARGS__); } \
+      else if (r <= 64) FN<T, 16, 4>(__VA_ARGS__);                                        \
+      else FN<T, 32, 4>(__VA_ARGS__);                                                     \
+    } else if constexpr (sizeof(T) == 4) {                                                \
+      if (r <= 4) FN<T, 4, 1>(__VA_ARGS__);                                               \
+      else if (r <= 8) { if (variant == 1) FN<T, 8, 1>(__VA_ARGS__); else FN<T, 4, 2>(__VA_ARGS__); } \
+      else if (r <= 16) {                                                                 \
+        if (variant == 1) FN<T, 8, 2>(__VA_ARGS__);                                       \
+        else if (variant == 2) FN<T, 2, 8>(__VA_ARGS__);                                  \
+        else FN<T, 4, 4>(__VA_ARGS__);                                                    \
+      } else if (r <= 32) { if (variant == 1) FN<T, 4, 8>(__VA_ARGS__); else FN<T, 8, 4>(__VA_ARGS__); } \
+      else if (r <= 64) FN<T, 16, 4>(__VA_ARGS__);                                        \
+      else FN<T, 32, 4>(__VA_ARGS__);                                                     \
+    } else {                                                                              \
+      if (r <= 4) FN<T, 2, 2>(__VA_ARGS__);                                               \
+      else if (r <= 8) { if (variant == 1) FN<T, 1, 8>(__VA_ARGS__); else FN<T, 2, 4>(__VA_ARGS__); } \
+      else if (r <= 16) {                                                                 \
+        if (variant == 1) FN<T, 4, 4>(__VA_ARGS__);                                       \
+        else if (variant == 2) FN<T, 1, 16>(__VA_ARGS__);                                 \
+        else FN<T, 2, 8>(__VA_ARGS__);                                                    \
+      } else if (r <= 32) { if (variant == 1) FN<T, 8, 4>(__VA_ARGS__); else FN<T, 4, 8>(__VA_ARGS__); } \
+      else if (r <= 64) FN<T, 8, 8>(__VA_ARGS__);                                         \
+      else FN<T, 16, 8>(__VA_ARGS__);                                                     \
+    }                                                                                     \
+  } while (0)
+
 }  // namespace almbm

@@ -26,9 +26,9 @@ def rel(a, b):
     return float(np.linalg.norm(np.asarray(a, np.float64) - b) / max(np.linalg.norm(b), 1e-300))
 
 
-def _problem(inst, prec="f64", r_max=16, kmax=60):
+def _problem(inst, prec="f64", r_max=16, kmax=60, **ws):
     return _almbm().Problem.matrix_completion(inst.n1, inst.n2, inst.rows, inst.cols, inst.vals, precision=prec,
-                                              r_max=r_max, lanczos_kmax=kmax, device=DEV)
+                                              r_max=r_max, lanczos_kmax=kmax, device=DEV, **ws)
 
 
 @pytest.mark.parametrize("r", [3, 5])
@@ -93,7 +93,7 @@ def test_completion_block_rank_step_from_rank_one():
     eps = 1e-5
     inst = gen.completion_instance(1000, 1000, 3, 13)
     nuc = float(np.sum(np.linalg.svd(inst.U @ inst.V.T, compute_uv=False)))
-    p = _problem(inst, r_max=32)
+    p = _problem(inst, r_max=32, rank_block_max=3)
     st, res, R, y = p.solve(gen.init_factor(inst.n, 1, 1), eps_kkt=eps, sigma=0.03, rank_block=3, max_outer=500,
                             time_limit_s=60)
     print(f"completion 1000x1000 r=3 from rank 1, rank_block 3: status {st} outer {res['outer']} "

@@ -53,9 +53,9 @@ def expected_hubs(g):
     return int(np.sum(deg > max(32, 2 * avg))), int(deg.max())
 
 
-def problem(g, prec="f64", r_max=16, kmax=0):
+def problem(g, prec="f64", r_max=16, kmax=0, hub_min_degree=0):
     return almbm().Problem.maxcut(g.n, g.ei, g.ej, g.w, precision=prec, r_max=r_max, lanczos_kmax=kmax, device=DEV,
-                                  validate=False)
+                                  validate=False, hub_min_degree=hub_min_degree)
 
 
 @pytest.mark.parametrize("scale", [12, 14])
@@ -95,7 +95,7 @@ def test_cost_apply_hub_settings_agree(r):
     g = rmat(14)
     X = np.random.default_rng(r).standard_normal((g.n, r))
     P_o = oracle.cost_apply(oracle.maxcut_sdp(g), X)
-    p = problem(g, r_max=64)
+    p = problem(g, r_max=64, hub_min_degree=8)  # reserves the hubs of the lowest threshold used below
     Xt = p.factor(X)
     for thr in (0, -1, 8):
         nh = p.set_hub_threshold(thr)

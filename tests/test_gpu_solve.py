@@ -26,8 +26,9 @@ def almbm():
     return m
 
 
-def _maxcut(g, prec="f64", r_max=32, kmax=100):
-    return almbm().Problem.maxcut(g.n, g.ei, g.ej, g.w, precision=prec, r_max=r_max, lanczos_kmax=kmax, device=DEV)
+def _maxcut(g, prec="f64", r_max=32, kmax=100, **ws):
+    return almbm().Problem.maxcut(g.n, g.ei, g.ej, g.w, precision=prec, r_max=r_max, lanczos_kmax=kmax, device=DEV,
+                                  **ws)
 
 
 def _oracle_kkt(po, R, y):
@@ -224,7 +225,7 @@ def test_block_rank_step_cycles_closed_form(n, q):
     """Rank steps with q directions (Ritz vectors of a full Lanczos pass and the
     small PSD subproblem) from rank 1: the closed forms are reached."""
     g = gen.cycle_graph(n)
-    prob = _maxcut(g, r_max=16, kmax=min(n, 60))
+    prob = _maxcut(g, r_max=16, kmax=min(n, 60), rank_block_max=q)
     st, res, R, y = prob.solve(gen.init_factor(n, 1, 1), eps_kkt=1e-8, rank_block=q, max_outer=400, max_inner=2000)
     val = -res["pobj"]
     expect = n if n % 2 == 0 else n * (1 + math.cos(math.pi / n)) / 2
@@ -242,7 +243,7 @@ def test_block_rank_step_er_workload():
     eps = 1e-6
     out = {}
     for q in (1, 4):
-        prob = _maxcut(g, r_max=48, kmax=100)
+        prob = _maxcut(g, r_max=48, kmax=100, rank_block_max=q)
         st, res, R, y = prob.solve(gen.init_factor(g.n, 1, 1), eps_kkt=eps, rank_block=q, max_outer=500)
         print(f"ER 2000 from rank 1, rank_block {q}: status {st} outer {res['outer']} inner {res['inner_total']} "
               f"rank {res['rank']} pobj {res['pobj']:.12e} time {res['time_s']:.2f}s", flush=True)
@@ -260,7 +261,7 @@ def test_block_rank_step_lovasz_c5():
     """Lovasz theta of C5 (trace row + edge rows, C = -J) from rank 1 with 2
     directions per rank step and the edge penalty: sqrt(5)."""
     g = gen.cycle_graph(5)
-    prob = almbm().Problem.lovasz(5, g.ei, g.ej, precision="f64", r_max=8, lanczos_kmax=5, device=DEV)
+    prob = almbm().Problem.lovasz(5, g.ei, g.ej, precision="f64", r_max=8, lanczos_kmax=5, device=DEV, rank_block_max=2)
     st, res, R, y = prob.solve(gen.init_factor(5, 1, 1), eps_kkt=1e-6, sigma_edges=5.0, rank_block=2,
                                max_outer=400, max_inner=2000)
     print(f"lovasz C5 rank_block 2: status {st} value {-res['pobj']:.10f} outer {res['outer']} rank {res['rank']}",
