@@ -12,8 +12,8 @@ Each step is one gradient evaluation, so steps/s = gradient evaluations/s.
 The rows evaluated once per outer iteration (dual update, Lanczos matvec and
 reorthogonalisation) are timed separately and reported under "per_outer".
 
-Usage: python bench.py [--steps K] [--warmup W] [--precision bf16|f32|f64]
-                       [--n N] [--deg D] [--rank R] [--modes] [--solve]
+Usage: python bench.py [--steps K] [--warmup W] [--precision bf16|f32|f64] [--no-solve]
+                       [--n N] [--deg D] [--rank R] [--modes] [--inner lbfgs|gd]
                        [--no-cpu-baseline]
 """
 
@@ -77,7 +77,7 @@ def time_events(fn, iters):
     return s.elapsed_time(e) / 1000.0
 
 
-def bench_mode(g, prec, r, steps, warmup, seed, refresh_every=0):
+def bench_mode(g, prec, r, steps, warmup, seed, refresh_every=0, lbfgs_memory=0):
     import torch
 
     import gen
@@ -86,7 +86,7 @@ def bench_mode(g, prec, r, steps, warmup, seed, refresh_every=0):
     dev = torch.device("cuda:0")
     t0 = time.time()
     prob = almbm.Problem.maxcut(g.n, g.ei, g.ej, g.w, precision=prec, r_max=r, lanczos_kmax=LANCZOS_STEPS,
-                                device=dev, validate=False)
+                                device=dev, validate=False, lbfgs_memory_max=lbfgs_memory)
     log(f"[bench] {prec}: problem resident in {time.time() - t0:.1f}s (nnz {prob.desc.nnz})")
     R = prob.factor(torch.from_numpy(gen.init_factor(g.n, r, seed)))
     y = torch.zeros(g.n, dtype=torch.float64, device=dev)
@@ -105,6 +105,20 @@ def bench_mode(g, prec, r, steps, warmup, seed, refresh_every=0):
     el = time.perf_counter() - t1
     assert done == steps and flag == 2, (done, flag)
     log(f"[bench] {prec}: {steps} inner steps in {el:.3f}s, f={f_last:.6e}")
+    lb_el = None
+    if lbfgs_memory > 0:
+        # the same loop with the L-BFGS direction (one gradient evaluation per
+        # step plus the streaming of the stored vectors)
+        R2 = R.clone()
+        lopts = dict(sigma=sigma, refresh_every=refresh_every, inner_solver=1, lbfgs_memory=lbfgs_memory)
+        prob.inner_solve(R2, y, 0.0, warmup, **lopts)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        done, flag, _ = prob.inner_solve(R2, y, 0.0, steps, **lopts)
+        lb_el = time.perf_counter() - t1
+        assert done == steps and flag == 2, (done, flag)
+        log(f"[bench] {prec}: {steps} L-BFGS steps (memory {lbfgs_memory}) in {lb_el:.3f}s")
+        del R2
 
     # the dominant kernel alone (objective/gradient pass + its one-block finalize)
     from paper_2505_15775_amd import _lib, _ptr, _stream  # noqa: F401
@@ -132,6 +146,7 @@ def bench_mode(g, prec, r, steps, warmup, seed, refresh_every=0):
     per_cp = el_cp / n_og
     nnz = int(prob.desc.nnz)
     out = {"steps_per_s": steps / el, "ms_per_step": 1000.0 * el / steps,
+           "lbfgs_steps_per_s": (steps / lb_el) if lb_el else None,
            "objgrad_ms": 1000.0 * per_og, "objgrad_evals_per_s": 1.0 / per_og,
            "objgrad_bytes": objgrad_bytes(g.n, nnz, r, prec),
            "spmm_ms": 1000.0 * per_cp, "spmm_bytes": spmm_bytes(g.n, nnz, r, prec)}
@@ -403,6 +418,91 @@ def cpu_baseline(n_full, deg, r, seed, evals=2):
                       f"N(0,1) weights r={r}, {evals} timed evals of {dt:.2f}s each, scaled by n ratio {scale:.1f}"}
 
 
+def certified_bracket(pb, Rf, yf, lanczos_steps=200):
+    """Bracket on the MaxCut SDP optimum (minimisation form) at a returned
+    point, on an FP64 handle pb of the same cost.  Upper end: <C, X^> for X^
+    with the rows of R scaled to unit length, a feasible point.  Lower end:
+    sum(y) + n * theta, the dual objective of y + theta 1, which is dual
+    feasible when theta <= lambda_min(C - Diag(y)); theta is the smallest Ritz
+    value of a long Lanczos run, itself an upper bound on lambda_min, so the
+    lower end holds as far as theta has converged (its residual is given)."""
+    import torch
+
+    Rn = Rf.to(dtype=torch.float64)
+    Rn = (Rn / Rn.norm(dim=1, keepdim=True).clamp_min(1e-300)).contiguous()
+    zero = torch.zeros(pb.n, dtype=torch.float64, device=Rn.device)
+    f, _, _ = pb.objective_grad(Rn, zero, 0.0, want_G=False, want_Av=False)
+    yd = yf.to(dtype=torch.float64).contiguous()
+    theta, _, resid, iters = pb.lanczos_min_eig(yd, max_iter=lanczos_steps, tol=1e-9, want_vector=False)
+    upper = f.item()
+    lower = float(yd.sum().item()) + pb.n * theta
+    return {"upper": upper, "lower": lower, "rel_width": (upper - lower) / abs(upper), "theta": theta,
+            "theta_resid": resid, "lanczos_steps": iters}
+
+
+def solve_legs(g, args):
+    """Solves to 1e-4 relative KKT on the benchmark graph (the metric's third
+    part): FP64 from the default start (R0 of rank r with unit rows, y = 0),
+    the bench precision (BF16 storage, with the ladder to float) from the same
+    start, and from the learned warm start.  Each reports wall time, outer and
+    inner iterations, rank, the KKT terms, and the objective bracket."""
+    import torch
+
+    import gen
+    import paper_2505_15775_amd as almbm
+    from paper_2505_15775_amd import warmstart
+
+    lbfgs = args.inner == "lbfgs"
+    max_inner = args.max_inner or (100 if lbfgs else 500)
+    keys = ("outer", "inner_total", "rank", "kkt", "pinf", "dinf", "gap", "pobj", "time_s", "time_lanczos_s",
+            "promoted_at_outer", "sigma_final", "sigma_increases", "lam_min", "lanczos_resid")
+    legs = {"f64": ("f64_default_start", "f64", False),
+            "default": (f"{args.precision}_default_start", args.precision, False),
+            "learned": (f"{args.precision}_learned_start", args.precision, True)}
+    out, finals = {}, {}
+    for leg in [x for x in args.solve_legs.split(",") if x]:
+        name, pm, warm = legs[leg]
+        log(f"[bench] solve leg {name}")
+        ps = almbm.Problem.maxcut(g.n, g.ei, g.ej, g.w, precision=pm, r_max=64, lanczos_kmax=60, device="cuda:0",
+                                  validate=False, lbfgs_memory_max=args.lbfgs_memory if lbfgs else 0)
+        opts = dict(eps_kkt=1e-4, sigma=args.sigma, max_inner=max_inner, time_limit_s=args.solve_time_limit,
+                    verbose=1, inner_solver=1 if lbfgs else 0, lbfgs_memory=args.lbfgs_memory)
+        if args.sigma_growth != 1.0:
+            opts["sigma_growth"] = args.sigma_growth
+        if args.refresh_every:
+            opts["refresh_every"] = args.refresh_every
+        torch.cuda.synchronize()
+        if warm:
+            model = warmstart.WarmStartModel.load(device="cuda:0")
+            st, res, Rf, yf, info = warmstart.solve_warm(ps, model, **opts)
+            extra = {"r0": info["r0"], "fallback": info["fallback"], "predict_s": round(info["predict_s"], 3),
+                     "total_s": round(info["total_s"], 3)}
+        else:
+            st, res, Rf, yf = ps.solve(gen.init_factor(g.n, args.rank, args.seed), **opts)
+            extra = {}
+        out[name] = {"status": int(st), "sigma": args.sigma, "sigma_growth": args.sigma_growth, "max_inner": max_inner,
+                     "inner_solver": args.inner, "lbfgs_memory": args.lbfgs_memory if lbfgs else None,
+                     **{k: res[k] for k in keys}, **extra}
+        log(f"[bench] {name}: {out[name]}")
+        finals[name] = (Rf.clone(), yf.clone())
+        ps.close()
+        del ps, Rf, yf
+        torch.cuda.empty_cache()
+    if finals:
+        pb = almbm.Problem.maxcut(g.n, g.ei, g.ej, g.w, precision="f64", r_max=64, lanczos_kmax=200,
+                                  device="cuda:0", validate=False)
+        for name, (Rf, yf) in finals.items():
+            out[name]["bracket"] = certified_bracket(pb, Rf, yf)
+            log(f"[bench] {name} bracket: {out[name]['bracket']}")
+        pb.close()
+        ref = out.get("f64_default_start")
+        if ref:
+            for name in out:
+                if name != "f64_default_start":
+                    out[name]["rel_objective_diff_vs_f64"] = abs(out[name]["pobj"] - ref["pobj"]) / abs(ref["pobj"])
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -414,16 +514,21 @@ def main():
     ap.add_argument("--rank", type=int, default=16)
     ap.add_argument("--seed", type=int, default=5)
     ap.add_argument("--modes", action="store_true", help="also time the other two precisions")
-    ap.add_argument("--solve", action="store_true", help="also run the full solve to 1e-4 relative KKT")
-    ap.add_argument("--solve-f64", action="store_true", help="also the FP64 solve from the default start")
-    ap.add_argument("--warm", action="store_true", help="also the solve from the learned warm start")
-    ap.add_argument("--solve-time-limit", type=float, default=600.0)
+    ap.add_argument("--no-solve", action="store_true",
+                    help="skip the solves to 1e-4 relative KKT (FP64 and BF16-ladder default starts, learned start)")
+    ap.add_argument("--solve-legs", default="f64,default,learned",
+                    help="comma list of solve legs: f64 (FP64 default start), default (bench precision, default "
+                         "start), learned (bench precision, learned warm start)")
+    ap.add_argument("--solve-time-limit", type=float, default=120.0)
     ap.add_argument("--sigma", type=float, default=16.0, help="penalty of the --solve leg")
     ap.add_argument("--refresh-every", type=int, default=0,
                     help="inner steps between full sparse evaluations (0: the library default for the precision)")
     ap.add_argument("--sigma-growth", type=float, default=1.0,
                     help="penalty schedule of the --solve legs: sigma x this factor whenever pinf falls by less than 4x")
-    ap.add_argument("--max-inner", type=int, default=500, help="gradient steps per subproblem in the solve legs")
+    ap.add_argument("--max-inner", type=int, default=0,
+                    help="gradient steps per subproblem in the solve legs (0: 100 for L-BFGS, 500 for GD)")
+    ap.add_argument("--inner", default="lbfgs", choices=["lbfgs", "gd"], help="subproblem solver of the solve legs")
+    ap.add_argument("--lbfgs-memory", type=int, default=3, help="L-BFGS pairs kept")
     ap.add_argument("--batch", type=int, default=0, help="also the batched solve of this many instances vs a loop")
     ap.add_argument("--batch-eps", type=float, default=1e-4)
     ap.add_argument("--kernels", action="store_true", help="also time the edge-family and warm-start kernels")
@@ -453,7 +558,7 @@ def main():
     log(f"[bench] graph n={g.n} M={g.m_edges} generated in {time.time() - t0:.1f}s")
 
     prob, R, y, main_out = bench_mode(g, args.precision, args.rank, args.steps, args.warmup, args.seed,
-                                      args.refresh_every)
+                                      args.refresh_every, args.lbfgs_memory)
     per_outer = per_outer_rows(prob, y, 20)
     modes = {}
     if args.modes:
@@ -490,48 +595,12 @@ def main():
                             "algorithmic_bytes_per_launch": main_out["objgrad_bytes"],
                             "launch_ms": round(main_out["objgrad_ms"], 4), "traffic": traffic_og}}
 
-    solves = {}
-    if args.solve or args.solve_f64 or args.warm:
+    solves = None
+    if not args.no_solve:
         prob.close()
-        del prob
+        del prob, R, y
         torch.cuda.empty_cache()
-        import paper_2505_15775_amd as almbm
-        from paper_2505_15775_amd import warmstart
-
-        keys = ("outer", "inner_total", "rank", "kkt", "pinf", "dinf", "gap", "pobj", "time_s", "time_lanczos_s",
-                "promoted_at_outer", "sigma_final", "sigma_increases")
-        legs = []
-        if args.solve_f64:
-            legs.append(("f64_default_start", "f64", False))
-        if args.solve:
-            legs.append((f"{args.precision}_default_start", args.precision, False))
-        if args.warm:
-            legs.append((f"{args.precision}_learned_start", args.precision, True))
-        for name, pm, warm in legs:
-            log(f"[bench] solve leg {name}")
-            ps = almbm.Problem.maxcut(g.n, g.ei, g.ej, g.w, precision=pm, r_max=64, lanczos_kmax=60,
-                                      device="cuda:0", validate=False)
-            opts = dict(eps_kkt=1e-4, sigma=args.sigma, max_inner=args.max_inner, time_limit_s=args.solve_time_limit,
-                        verbose=1)
-            if args.sigma_growth != 1.0:
-                opts["sigma_growth"] = args.sigma_growth
-            if args.refresh_every:
-                opts["refresh_every"] = args.refresh_every
-            if warm:
-                model = warmstart.WarmStartModel.load(device="cuda:0")
-                st, res, Rf, yf, info = warmstart.solve_warm(ps, model, **opts)
-                extra = {"r0": info["r0"], "fallback": info["fallback"], "predict_s": round(info["predict_s"], 3),
-                         "total_s": round(info["total_s"], 3)}
-            else:
-                st, res, Rf, yf = ps.solve(gen.init_factor(g.n, args.rank, args.seed), **opts)
-                extra = {}
-            solves[name] = {"status": int(st), "sigma": args.sigma, "sigma_growth": args.sigma_growth,
-                            "max_inner": args.max_inner,
-                            **{k: res[k] for k in keys}, **extra}
-            log(f"[bench] {name}: {solves[name]}")
-            ps.close()
-            del ps
-            torch.cuda.empty_cache()
+        solves = solve_legs(g, args)
 
     batch = batch_leg(args.batch, args.batch_eps, args.sigma, "f64") if args.batch > 0 else None
     other = kernels_leg(g) if args.kernels else None
@@ -558,6 +627,7 @@ def main():
                                f"{'BF16 R storage, FP32 arithmetic' if args.precision == 'bf16' else args.precision}",
                    "n": args.n, "nnz": int(2 * M), "r": args.rank, "precision": args.precision},
         "objgrad_evals_per_s": round(main_out["objgrad_evals_per_s"], 3),
+        "lbfgs_steps_per_s": (round(main_out["lbfgs_steps_per_s"], 3) if main_out["lbfgs_steps_per_s"] else None),
         "per_outer": per_outer,
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -102,9 +102,11 @@ struct alm_bm_problem {
   int lb_m = 0;                   // memory of the running solve (0: gradient descent)
 };
 
-template <typename T> static LbfgsRing<T> lbfgs_ring(const alm_bm_problem* p) {
-  if (p->lb_m <= 0) return LbfgsRing<T>{};
-  return LbfgsRing<T>{p->lbs, static_cast<T*>(p->lb_e), static_cast<T*>(p->lb_y), p->lb_stride};
+// Rings of storage type S (RingT of the factor's type) while an L-BFGS solve
+// runs; empty otherwise.
+template <typename S> static LbfgsRing<S> lbfgs_ring(const alm_bm_problem* p) {
+  if (p->lb_m <= 0) return LbfgsRing<S>{};
+  return LbfgsRing<S>{p->lbs, static_cast<S*>(p->lb_e), static_cast<S*>(p->lb_y), p->lb_stride};
 }
 
 static size_t esize(alm_bm_precision p) { return p == ALM_BM_F64 ? 8 : (p == ALM_BM_F32 ? 4 : 2); }
@@ -569,8 +571,8 @@ extern "C" alm_bm_status alm_bm_create(const alm_bm_problem_desc* desc, hipStrea
     CK(dalloc_t(p, &p->gpart, (size_t)p->lnb * ne));
   }
   if (d.lbfgs_memory_max > 0) {
-    // float-sized elements for BF16 handles: the ladder's float phase uses the same rings
-    const size_t lbe = d.precision == ALM_BM_BF16 ? sizeof(float) : es;
+    // ring elements: double for FP64 handles, bfloat16 otherwise (RingT)
+    const size_t lbe = d.precision == ALM_BM_F64 ? sizeof(double) : sizeof(bf16);
     p->lb_stride = ((long)n * d.r_max + 63) / 64 * 64;
     const size_t bytes = (size_t)(d.lbfgs_memory_max + 1) * (size_t)p->lb_stride * lbe;
     CK(dalloc(p, &p->lb_e, bytes));
@@ -636,20 +638,24 @@ static void enqueue_inner_step(alm_bm_problem* p, int r, T* R, const double* y, 
   DevScalars* sc = p->sc_solve;
   if (d.cons_kind == ALM_BM_CONS_DIAG) {
     V* Q = static_cast<V*>(p->Qbuf);
-    const LbfgsRing<T> lb = lbfgs_ring<T>(p);  // empty: gradient descent
+    using S = RingT<T>;
+    const LbfgsRing<S> lb = lbfgs_ring<S>(p);  // empty: gradient descent
     launch_upd_eval_diag<T>(d.n, r, p->variant, R, G, Q, y, d.b, sigma, p->Av, p->part, sc, refresh, p->tab, p->nblk,
                             st, lb);
     launch_objgrad_diag<T>(cost_of<T>(p), r, p->variant, R, y, d.b, sigma, G, p->Av, p->part, sc, refresh, p->tab,
                            p->nblk, st, lb);
     launch_fin_objgrad(p->part, p->nblk, sc, sigma, 1, nullptr, st, p->tab, p->count);
     if (lb.s) {
-      // L-BFGS: the direction E = H G and its line-search totals replace G's
+      // L-BFGS: the direction E = H G and its line-search totals replace G's;
+      // the line-search product gathers E in the ring type
       launch_lbfgs_dots<T>((long)d.n * r, G, lb, p->part, p->nblk, sc, st);
       launch_fin_lbfgs(p->part, p->nblk, sc, lb.s, st);
       launch_lbfgs_combine<T>(d.n, r, p->variant, R, G, y, d.b, sigma, p->Av, lb, p->part, sc, p->nblk, st);
       launch_fin_lsdir(p->part, p->nblk, sc, lb.s, st);
+      launch_quadq_diag<S>(cost_of<S>(p), r, p->variant, lb.e, Q, p->part_c2, sc, p->tab, p->nblk, st, lb);
+    } else {
+      launch_quadq_diag<T>(cost_of<T>(p), r, p->variant, G, Q, p->part_c2, sc, p->tab, p->nblk, st);
     }
-    launch_quadq_diag<T>(cost_of<T>(p), r, p->variant, G, Q, p->part_c2, sc, p->tab, p->nblk, st, lb);
     launch_fin_step(p->part_c2, p->nblk, 1, sc, sigma, 0.0, 1, nullptr, nullptr, st, p->tab, p->count);
   } else {
     enqueue_objgrad<T>(p, r, R, y, sigma, G, p->Av, sc, 1, nullptr, st);

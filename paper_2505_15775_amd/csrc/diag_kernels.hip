@@ -20,7 +20,7 @@ __global__ void __launch_bounds__(kBlock)
 k_objgrad_diag(Cost<typename Acc<T>::type> C, int r, const T* __restrict__ R,
                const double* __restrict__ y, const double* __restrict__ b, double sigma,
                T* __restrict__ G, double* __restrict__ Av, double* __restrict__ part,
-               const DevScalars* __restrict__ sc_base, int refresh_every, BlockTab tab, LbfgsRing<T> lb) {
+               const DevScalars* __restrict__ sc_base, int refresh_every, BlockTab tab, LbfgsRing<RingT<T>> lb) {
   using V = typename Acc<T>::type;
   const Rows ch = rows_of(C.n, tab);
   const DevScalars* sc = sc_base ? sc_base + ch.inst : nullptr;
@@ -28,7 +28,7 @@ k_objgrad_diag(Cost<typename Acc<T>::type> C, int r, const T* __restrict__ R,
   // inside the inner loop this full pass runs only on refresh iterations
   if (sc && refresh_every > 1 && (sc->iter % refresh_every) != 0) return;
   // L-BFGS: y_k = G_new - G_old into the current y slot (not on the first step)
-  T* __restrict__ yk = (lb.s && sc && sc->iter > 0) ? lb.y + (long)lb.s->cur * lb.stride : nullptr;
+  RingT<T>* __restrict__ yk = (lb.s && sc && sc->iter > 0) ? lb.y + (long)lb.s->cur * lb.stride : nullptr;
   constexpr int RPB = kBlock / LPR;
   const int lane = threadIdx.x % LPR;
   const int slot = threadIdx.x / LPR;
@@ -64,7 +64,7 @@ k_objgrad_diag(Cost<typename Acc<T>::type> C, int r, const T* __restrict__ R,
       load_frag<T, VEC, FULL>(G + i * r, lane, r, go);
 #pragma unroll
       for (int v = 0; v < VEC; ++v) dy[v] = g[v] - go[v];
-      store_frag<T, VEC, FULL>(yk + i * r, lane, r, dy);
+      store_frag<RingT<T>, VEC, FULL>(yk + i * r, lane, r, dy);
     }
     if (G) store_frag<T, VEC, FULL>(G + i * r, lane, r, g);
     V gg = 0, gp = 0, rg = 0;
@@ -172,7 +172,7 @@ __global__ void __launch_bounds__(kBlock)
 k_upd_eval_diag(long n, int r, T* __restrict__ R, T* __restrict__ G, const typename Acc<T>::type* __restrict__ Q,
                 const double* __restrict__ y, const double* __restrict__ b, double sigma, double* __restrict__ Av,
                 double* __restrict__ part, const DevScalars* __restrict__ sc_base, int refresh_every, BlockTab tab,
-                LbfgsRing<T> lb) {
+                LbfgsRing<RingT<T>> lb) {
   using V = typename Acc<T>::type;
   const Rows ch = rows_of(n, tab);
   const DevScalars* sc = sc_base + ch.inst;
@@ -181,8 +181,9 @@ k_upd_eval_diag(long n, int r, T* __restrict__ R, T* __restrict__ G, const typen
   if (e == 0) return;
   // the step is R <- R - t D with D = G (gradient descent) or D = E (L-BFGS,
   // which also writes y_k = G_new - G_old into the current y slot)
-  const T* __restrict__ D = lb.s ? lb.e + (long)lb.s->cur * lb.stride : G;
-  T* __restrict__ yk = lb.s ? lb.y + (long)lb.s->cur * lb.stride : nullptr;
+  using S = RingT<T>;
+  const S* __restrict__ D = lb.s ? lb.e + (long)lb.s->cur * lb.stride : nullptr;
+  S* __restrict__ yk = lb.s ? lb.y + (long)lb.s->cur * lb.stride : nullptr;
   const bool update_only = refresh_every <= 1 || (e % refresh_every) == 0;
   const V t = static_cast<V>(sc->t);
   constexpr int RPB = kBlock / LPR;
@@ -200,7 +201,7 @@ k_upd_eval_diag(long n, int r, T* __restrict__ R, T* __restrict__ G, const typen
     V ri[VEC], gi[VEC], di[VEC];
     load_frag<T, VEC, FULL>(R + i * r, lane, r, ri);
     load_frag<T, VEC, FULL>(G + i * r, lane, r, gi);
-    if (yk) load_frag<T, VEC, FULL>(D + i * r, lane, r, di);
+    if (D) load_frag<S, VEC, FULL>(D + i * r, lane, r, di);
     else {
 #pragma unroll
       for (int v = 0; v < VEC; ++v) di[v] = gi[v];
@@ -235,7 +236,7 @@ k_upd_eval_diag(long n, int r, T* __restrict__ R, T* __restrict__ G, const typen
       V dy[VEC];
 #pragma unroll
       for (int v = 0; v < VEC; ++v) dy[v] = g[v] - gi[v];
-      store_frag<T, VEC, FULL>(yk + i * r, lane, r, dy);
+      store_frag<S, VEC, FULL>(yk + i * r, lane, r, dy);
     }
     store_frag<T, VEC, FULL>(G + i * r, lane, r, g);
     V gg = 0, gp = 0, rg = 0;
@@ -403,7 +404,7 @@ template <typename T, int LPR, int VEC>
 static void launch_objgrad_cfg(const Cost<typename Acc<T>::type>& C, int r, const T* R, const double* y,
                                const double* b, double sigma, T* G, double* Av, double* part,
                                const DevScalars* sc, int refresh_every, const BlockTab& tab, int nblk,
-                               hipStream_t st, const LbfgsRing<T>& lb) {
+                               hipStream_t st, const LbfgsRing<RingT<T>>& lb) {
   if (r == LPR * VEC)
     hipLaunchKernelGGL((k_objgrad_diag<T, LPR, VEC, true>), dim3(nblk), dim3(kBlock), 0, st, C, r, R, y, b,
                        sigma, G, Av, part, sc, refresh_every, tab, lb);
@@ -428,7 +429,7 @@ template <typename T, int LPR, int VEC>
 static void launch_upd_eval_cfg(long n, int r, T* R, T* G, const typename Acc<T>::type* Q, const double* y,
                                 const double* b, double sigma, double* Av, double* part, const DevScalars* sc,
                                 int refresh_every, const BlockTab& tab, int nblk, hipStream_t st,
-                                const LbfgsRing<T>& lb) {
+                                const LbfgsRing<RingT<T>>& lb) {
   if (r == LPR * VEC)
     hipLaunchKernelGGL((k_upd_eval_diag<T, LPR, VEC, true>), dim3(nblk), dim3(kBlock), 0, st, n, r, R, G, Q, y, b,
                        sigma, Av, part, sc, refresh_every, tab, lb);
@@ -467,7 +468,8 @@ void launch_hub_rows(const Cost<typename Acc<T>::type>& C, int r, int variant, c
 template <typename T>
 void launch_objgrad_diag(const Cost<typename Acc<T>::type>& C, int r, int variant, const T* R, const double* y,
                          const double* b, double sigma, T* G, double* Av, double* part, const DevScalars* sc,
-                         int refresh_every, const BlockTab& tab, int nblk, hipStream_t st, const LbfgsRing<T>& lb) {
+                         int refresh_every, const BlockTab& tab, int nblk, hipStream_t st,
+                         const LbfgsRing<RingT<T>>& lb) {
   launch_hub_rows<T>(C, r, variant, R, C.hsum, sc, refresh_every, st, LbfgsRing<T>{});
   ALMBM_DISPATCH_DIAG(T, launch_objgrad_cfg, C, r, R, y, b, sigma, G, Av, part, sc, refresh_every, tab, nblk, st,
                       lb);
@@ -484,7 +486,8 @@ void launch_quadq_diag(const Cost<typename Acc<T>::type>& C, int r, int variant,
 template <typename T>
 void launch_upd_eval_diag(long n, int r, int variant, T* R, T* G, const typename Acc<T>::type* Q, const double* y,
                           const double* b, double sigma, double* Av, double* part, const DevScalars* sc,
-                          int refresh_every, const BlockTab& tab, int nblk, hipStream_t st, const LbfgsRing<T>& lb) {
+                          int refresh_every, const BlockTab& tab, int nblk, hipStream_t st,
+                          const LbfgsRing<RingT<T>>& lb) {
   ALMBM_DISPATCH_DIAG(T, launch_upd_eval_cfg, n, r, R, G, Q, y, b, sigma, Av, part, sc, refresh_every, tab, nblk, st,
                       lb);
 }
@@ -507,13 +510,13 @@ void launch_ls_diag(const Cost<typename Acc<T>::type>& C, int r, int variant, co
 #define ALMBM_INST(T)                                                                                     \
   template void launch_objgrad_diag<T>(const Cost<Acc<T>::type>&, int, int, const T*, const double*,      \
                                        const double*, double, T*, double*, double*, const DevScalars*, int, \
-                                       const BlockTab&, int, hipStream_t, const LbfgsRing<T>&);           \
+                                       const BlockTab&, int, hipStream_t, const LbfgsRing<RingT<T>>&);    \
   template void launch_quadq_diag<T>(const Cost<Acc<T>::type>&, int, int, const T*, Acc<T>::type*, double*, \
                                      const DevScalars*, const BlockTab&, int, hipStream_t,                 \
                                      const LbfgsRing<T>&);                                                 \
   template void launch_upd_eval_diag<T>(long, int, int, T*, T*, const Acc<T>::type*, const double*,          \
                                         const double*, double, double*, double*, const DevScalars*, int,     \
-                                        const BlockTab&, int, hipStream_t, const LbfgsRing<T>&);            \
+                                        const BlockTab&, int, hipStream_t, const LbfgsRing<RingT<T>>&);     \
   template void launch_quad_diag<T>(const Cost<Acc<T>::type>&, int, int, const T*, double*,               \
                                     const DevScalars*, int, hipStream_t);                                 \
   template void launch_ls_diag<T>(const Cost<Acc<T>::type>&, int, int, const T*, const T*, const double*,  \

@@ -82,6 +82,14 @@ struct LbfgsState {
   double ce[kMaxLbfgs], cy[kMaxLbfgs];
 };
 
+// Storage type of the rings: double for FP64 handles, bfloat16 otherwise.  The
+// rings only shape the direction; the exact line search then runs along the
+// direction as stored, so reduced ring precision never breaks descent (a
+// direction that fails the descent test clears the memory).
+template <typename T> struct RingOf { using type = bf16; };
+template <> struct RingOf<double> { using type = double; };
+template <typename T> using RingT = typename RingOf<T>::type;
+
 // Device rings of one handle: slot s of E at e + s * stride, of y at y + s * stride.
 template <typename T> struct LbfgsRing {
   LbfgsState* s = nullptr;

@@ -7,8 +7,9 @@ namespace almbm {
 
 // Hub-row neighbour sums of C X into out (no-op when C has no hubs).
 // lb: the L-BFGS rings (empty: gradient descent).  With rings, the row kernels
-// step along the ring's current direction E instead of G, the product of the
-// line search multiplies E, and the gradient passes write y_k = G_new - G_old.
+// step along the ring's current direction E instead of G and the gradient
+// passes write y_k = G_new - G_old (ring type RingT<T>); the line-search
+// product (instantiated for the ring type) multiplies E.
 template <typename T>
 void launch_hub_rows(const Cost<typename Acc<T>::type>& C, int r, int variant, const T* X,
                      typename Acc<T>::type* out, const DevScalars* sc, int refresh_every, hipStream_t st,
@@ -17,7 +18,7 @@ template <typename T>
 void launch_objgrad_diag(const Cost<typename Acc<T>::type>& C, int r, int variant, const T* R, const double* y,
                          const double* b, double sigma, T* G, double* Av, double* part, const DevScalars* sc,
                          int refresh_every, const BlockTab& tab, int nblk, hipStream_t st,
-                         const LbfgsRing<T>& lb = LbfgsRing<T>{});
+                         const LbfgsRing<RingT<T>>& lb = LbfgsRing<RingT<T>>{});
 template <typename T>
 void launch_quadq_diag(const Cost<typename Acc<T>::type>& C, int r, int variant, const T* G,
                        typename Acc<T>::type* Q, double* part, const DevScalars* sc, const BlockTab& tab, int nblk,
@@ -26,21 +27,21 @@ template <typename T>
 void launch_upd_eval_diag(long n, int r, int variant, T* R, T* G, const typename Acc<T>::type* Q, const double* y,
                           const double* b, double sigma, double* Av, double* part, const DevScalars* sc,
                           int refresh_every, const BlockTab& tab, int nblk, hipStream_t st,
-                          const LbfgsRing<T>& lb = LbfgsRing<T>{});
+                          const LbfgsRing<RingT<T>>& lb = LbfgsRing<RingT<T>>{});
 // L-BFGS steps (lbfgs_kernels.hip).  Reset at the start of a subproblem.
 void launch_lbfgs_reset(LbfgsState* s, int m, hipStream_t st);
 // Inner products of the new gradient G and of y_k with the stored vectors
 // (n*r elements each), per block of nb blocks into part[nb][kLbfgsDots].
 template <typename T>
-void launch_lbfgs_dots(long len, const T* G, const LbfgsRing<T>& lb, double* part, int nb, const DevScalars* sc,
-                       hipStream_t st);
+void launch_lbfgs_dots(long len, const T* G, const LbfgsRing<RingT<T>>& lb, double* part, int nb,
+                       const DevScalars* sc, hipStream_t st);
 // Pair update and the coefficients of the next direction (one block).
 void launch_fin_lbfgs(const double* part, int nb, const DevScalars* sc, LbfgsState* s, hipStream_t st);
 // E = cg G + sum (ce E_a + cy y_a) into the current slot, and the quartic's
 // direction-dependent partial sums along -E (NUM_P per block).
 template <typename T>
 void launch_lbfgs_combine(long n, int r, int variant, const T* R, const T* G, const double* y, const double* b,
-                          double sigma, const double* Av, const LbfgsRing<T>& lb, double* part,
+                          double sigma, const double* Av, const LbfgsRing<RingT<T>>& lb, double* part,
                           const DevScalars* sc, int nblk, hipStream_t st);
 // Direction-dependent totals of the quartic from the combine partials.
 void launch_fin_lsdir(const double* part, int nb, DevScalars* sc, LbfgsState* s, hipStream_t st);

@@ -65,24 +65,24 @@ template <typename V> struct DotAcc {
 };
 
 // NV consecutive elements at idx of every vector.
-template <typename T, int NV>
+template <typename T, int NV, typename S = RingT<T>>
 __device__ __forceinline__ void dots_chunk(DotAcc<typename Acc<T>::type>& A, long idx, const T* __restrict__ G,
-                                           const T* __restrict__ yk, const T* __restrict__ ek,
-                                           const T* const (&ea)[kMaxLbfgs], const T* const (&ya)[kMaxLbfgs],
+                                           const S* __restrict__ yk, const S* __restrict__ ek,
+                                           const S* const (&ea)[kMaxLbfgs], const S* const (&ya)[kMaxLbfgs],
                                            int cnt, bool have) {
   using V = typename Acc<T>::type;
   V g[NV], y_k[NV], e_k[NV];
   load_flat<T, NV>(G + idx, g);
   if (have) {
-    load_flat<T, NV>(yk + idx, y_k);
-    load_flat<T, NV>(ek + idx, e_k);
+    load_flat<S, NV>(yk + idx, y_k);
+    load_flat<S, NV>(ek + idx, e_k);
   }
 #pragma unroll
   for (int a = 0; a < kMaxLbfgs; ++a) {
     if (a < cnt) {
       V ev[NV], yv[NV];
-      load_flat<T, NV>(ea[a] + idx, ev);
-      load_flat<T, NV>(ya[a] + idx, yv);
+      load_flat<S, NV>(ea[a] + idx, ev);
+      load_flat<S, NV>(ya[a] + idx, yv);
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
         A.gE[a] += g[v] * ev[v];
@@ -111,18 +111,19 @@ __device__ __forceinline__ void dots_chunk(DotAcc<typename Acc<T>::type>& A, lon
 
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
-k_lbfgs_dots(long len, const T* __restrict__ G, LbfgsRing<T> lb, double* __restrict__ part,
+k_lbfgs_dots(long len, const T* __restrict__ G, LbfgsRing<RingT<T>> lb, double* __restrict__ part,
              const DevScalars* __restrict__ sc) {
   using V = typename Acc<T>::type;
+  using R = RingT<T>;
   constexpr int N = FlatVec<T>::N;
   if (sc->flag) return;
   const LbfgsState* S = lb.s;
   const int cnt = S->cnt;
   const bool have = S->have != 0;
-  const T* yk = lb.y + (long)S->cur * lb.stride;
-  const T* ek = lb.e + (long)S->cur * lb.stride;
-  const T* ea[kMaxLbfgs];
-  const T* ya[kMaxLbfgs];
+  const R* yk = lb.y + (long)S->cur * lb.stride;
+  const R* ek = lb.e + (long)S->cur * lb.stride;
+  const R* ea[kMaxLbfgs];
+  const R* ya[kMaxLbfgs];
 #pragma unroll
   for (int a = 0; a < kMaxLbfgs; ++a) {
     const int sl = a < cnt ? S->ord[a] : 0;
@@ -292,14 +293,15 @@ k_fin_lbfgs(const double* __restrict__ part, int nb, const DevScalars* __restric
 template <typename T, int LPR, int VEC, bool FULL>
 __global__ void __launch_bounds__(kBlock)
 k_lbfgs_combine(long n, int r, const T* __restrict__ R, const T* __restrict__ G, const double* __restrict__ y,
-                const double* __restrict__ b, double sigma, const double* __restrict__ Av, LbfgsRing<T> lb,
+                const double* __restrict__ b, double sigma, const double* __restrict__ Av, LbfgsRing<RingT<T>> lb,
                 double* __restrict__ part, const DevScalars* __restrict__ sc) {
   using V = typename Acc<T>::type;
+  using RS = RingT<T>;
   if (sc->flag) return;
   const LbfgsState* S = lb.s;
   const int c = S->cnt;
   const V cg = static_cast<V>(S->cg);
-  T* __restrict__ E = lb.e + (long)S->cur * lb.stride;
+  RS* __restrict__ E = lb.e + (long)S->cur * lb.stride;
   constexpr int RPB = kBlock / LPR;
   const int lane = threadIdx.x % LPR;
   const int slot = threadIdx.x / LPR;
@@ -318,14 +320,14 @@ k_lbfgs_combine(long n, int r, const T* __restrict__ R, const T* __restrict__ G,
       const long off = (long)S->ord[a] * lb.stride + i * r;
       const V ca = static_cast<V>(S->ce[a]), cb = static_cast<V>(S->cy[a]);
       V ev[VEC], yv[VEC];
-      load_frag<T, VEC, FULL>(lb.e + off, lane, r, ev);
-      load_frag<T, VEC, FULL>(lb.y + off, lane, r, yv);
+      load_frag<RS, VEC, FULL>(lb.e + off, lane, r, ev);
+      load_frag<RS, VEC, FULL>(lb.y + off, lane, r, yv);
 #pragma unroll
       for (int v = 0; v < VEC; ++v) e[v] += ca * ev[v] + cb * yv[v];
     }
 #pragma unroll
-    for (int v = 0; v < VEC; ++v) e[v] = round_st<T>(e[v]);
-    store_frag<T, VEC, FULL>(E + i * r, lane, r, e);
+    for (int v = 0; v < VEC; ++v) e[v] = round_st<RS>(e[v]);  // the direction as stored
+    store_frag<RS, VEC, FULL>(E + i * r, lane, r, e);
     // C R = G/2 + w R at the current point
     const double yi = y[i], ai = Av[i], ei = ai - b[i];
     const V wv = static_cast<V>(yi - sigma * ei);
@@ -381,8 +383,8 @@ void launch_lbfgs_reset(LbfgsState* s, int m, hipStream_t st) {
 }
 
 template <typename T>
-void launch_lbfgs_dots(long len, const T* G, const LbfgsRing<T>& lb, double* part, int nb, const DevScalars* sc,
-                       hipStream_t st) {
+void launch_lbfgs_dots(long len, const T* G, const LbfgsRing<RingT<T>>& lb, double* part, int nb,
+                       const DevScalars* sc, hipStream_t st) {
   hipLaunchKernelGGL((k_lbfgs_dots<T>), dim3(nb), dim3(kBlock), 0, st, len, G, lb, part, sc);
 }
 
@@ -392,8 +394,8 @@ void launch_fin_lbfgs(const double* part, int nb, const DevScalars* sc, LbfgsSta
 
 template <typename T, int LPR, int VEC>
 static void launch_combine_cfg(long n, int r, const T* R, const T* G, const double* y, const double* b, double sigma,
-                               const double* Av, const LbfgsRing<T>& lb, double* part, const DevScalars* sc,
-                               int nblk, hipStream_t st) {
+                               const double* Av, const LbfgsRing<RingT<T>>& lb, double* part,
+                               const DevScalars* sc, int nblk, hipStream_t st) {
   if (r == LPR * VEC)
     hipLaunchKernelGGL((k_lbfgs_combine<T, LPR, VEC, true>), dim3(nblk), dim3(kBlock), 0, st, n, r, R, G, y, b,
                        sigma, Av, lb, part, sc);
@@ -404,7 +406,7 @@ static void launch_combine_cfg(long n, int r, const T* R, const T* G, const doub
 
 template <typename T>
 void launch_lbfgs_combine(long n, int r, int variant, const T* R, const T* G, const double* y, const double* b,
-                          double sigma, const double* Av, const LbfgsRing<T>& lb, double* part,
+                          double sigma, const double* Av, const LbfgsRing<RingT<T>>& lb, double* part,
                           const DevScalars* sc, int nblk, hipStream_t st) {
   ALMBM_DISPATCH_DIAG(T, launch_combine_cfg, n, r, R, G, y, b, sigma, Av, lb, part, sc, nblk, st);
 }
@@ -414,10 +416,10 @@ void launch_fin_lsdir(const double* part, int nb, DevScalars* sc, LbfgsState* s,
 }
 
 #define ALMBM_LBFGS_INST(T)                                                                               \
-  template void launch_lbfgs_dots<T>(long, const T*, const LbfgsRing<T>&, double*, int, const DevScalars*, \
-                                     hipStream_t);                                                        \
+  template void launch_lbfgs_dots<T>(long, const T*, const LbfgsRing<RingT<T>>&, double*, int,            \
+                                     const DevScalars*, hipStream_t);                                      \
   template void launch_lbfgs_combine<T>(long, int, int, const T*, const T*, const double*, const double*,   \
-                                        double, const double*, const LbfgsRing<T>&, double*,                 \
+                                        double, const double*, const LbfgsRing<RingT<T>>&, double*,          \
                                         const DevScalars*, int, hipStream_t);
 
 ALMBM_LBFGS_INST(double)
