@@ -377,6 +377,45 @@ def rmat_leg(scale=22, edge_factor=8, r=16, precs=("bf16", "f64"), reps=20):
     return out
 
 
+def gather_probe_leg(rows_list=(500_000, 2_000_000, 10_000_000, 40_000_000), widths=(8, 32, 128), count=80_000_000,
+                     reps=5, seed=11):
+    """Gathered rows per second of the library's random-row gather probe for
+    tables of rows x width bytes (int32 indices uniform over the rows, count
+    gathers per launch): the ceiling the sparse cost product runs against.
+    Tables above 2.56 GB are skipped."""
+    import torch
+
+    from paper_2505_15775_amd import _lib, _ptr, _stream
+
+    dev = torch.device("cuda:0")
+    gen_ = torch.Generator(device=dev)
+    gen_.manual_seed(seed)
+    out = torch.empty(_lib.lib.alm_bm_gather_probe_out_size(), dtype=torch.float32, device=dev)
+    res = []
+    for rows in rows_list:
+        idx = torch.randint(0, rows, (count,), dtype=torch.int32, device=dev, generator=gen_)
+        for wb in widths:
+            if rows * wb > 2_560_000_000:
+                continue
+            table = torch.rand(rows * wb // 4, dtype=torch.float32, device=dev, generator=gen_)
+
+            def run():
+                _lib.check(_lib.lib.alm_bm_gather_probe(_ptr(table), rows, wb, _ptr(idx), count, _ptr(out),
+                                                        _stream()), "gather_probe")
+
+            run()
+            t = time_events(run, reps) / reps
+            res.append({"table_rows": rows, "row_bytes": wb, "table_mb": round(rows * wb / 1e6, 1),
+                        "gathers": count, "ms": round(1000 * t, 4), "rows_per_s": round(count / t, 0),
+                        "line_requests_per_s": round(count * -(-wb // 128) / t, 0)})
+            log(f"[bench] gather probe: {res[-1]}")
+            del table
+        del idx
+    del out
+    torch.cuda.empty_cache()
+    return res
+
+
 def calibrate_copy(nbytes=1 << 30):
     """A plain elementwise copy of known size (read nbytes, write nbytes), for
     scaling the HBM byte counters of a profiled run."""
@@ -537,6 +576,7 @@ def main():
     ap.add_argument("--rmat", type=int, default=0, metavar="SCALE",
                     help="also the skewed-degree leg on an R-MAT graph with 2^SCALE vertices (e.g. 22)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-gather-probe", action="store_true", help="skip the random-row gather ceiling sweep")
     ap.add_argument("--calibrate-copy", action="store_true", help="run a 1 GiB copy kernel first (profiling)")
     args = ap.parse_args()
 
@@ -580,6 +620,7 @@ def main():
             traffic = run.get("k_quadq_diag", {}).get("hbm_bytes_per_launch")
             traffic_og = run.get("k_objgrad_diag", {}).get("hbm_bytes_per_launch")
 
+    probe = None if args.no_gather_probe else gather_probe_leg()
     ach = main_out["spmm_gbs"]
     roofline = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
@@ -594,6 +635,14 @@ def main():
                             "frac": round(main_out["objgrad_gbs"] / HBM_PEAK_GBS, 4),
                             "algorithmic_bytes_per_launch": main_out["objgrad_bytes"],
                             "launch_ms": round(main_out["objgrad_ms"], 4), "traffic": traffic_og}}
+    if probe:
+        # the product's own shape: n rows of r * storage bytes, nnz gathers per launch
+        rb = {"f64": 8, "f32": 4, "bf16": 2}[args.precision] * args.rank
+        same = [x for x in probe if x["table_rows"] == args.n and x["row_bytes"] == rb]
+        if same:
+            roofline["gather_ceiling"] = {"probe_rows_per_s": same[0]["rows_per_s"],
+                                          "product_rows_per_s": round(main_out["spmm_gathers_per_s"], 0),
+                                          "frac": round(main_out["spmm_gathers_per_s"] / same[0]["rows_per_s"], 4)}
 
     solves = None
     if not args.no_solve:
@@ -637,6 +686,8 @@ def main():
                          for k, v in modes.items()}
     if solves:
         line["solve_to_1e-4_kkt"] = solves
+    if probe:
+        line["gather_probe"] = probe
     if batch is not None:
         line["batched_solve"] = batch
     if other is not None:

@@ -349,6 +349,18 @@ alm_bm_status alm_bm_set_hub_threshold(alm_bm_problem* prob, int32_t min_degree,
  * solver alm_bm_solve uses with rank_block > 1; it needs no device.         */
 alm_bm_status alm_bm_psd_step(int32_t q, const double* theta, const double* M4, double sigma, double* S);
 
+/* The penalty's quadratic form of the block rank step (Alg. 1, Sec. 5): for q
+ * orthonormal directions V (device, n x q column-major doubles, 1 <= q <=
+ * the handle's rank_block_max), M4 (host out, np x np row-major, np =
+ * q(q+1)/2, pairs a <= b numbered row-major) with
+ *   M4[pair(a,b), pair(c,d)] = sum_i w_i A_i(v_a v_b^T) A_i(v_c v_d^T),
+ * w_i = edge_weight on the edge rows of the TRACE_EDGES family (the ratio
+ * sigma_edges / sigma inside a solve) and 1 on every other row; the trace row
+ * contributes trace_coef^2 [a = b][c = d] (exact for orthonormal V).  This is
+ * the M4 that alm_bm_psd_step takes.  Synchronises stream.                  */
+alm_bm_status alm_bm_block_moments(alm_bm_problem* prob, int32_t q, const double* V, double edge_weight, double* M4,
+                                   hipStream_t stream);
+
 /* Autotuner: times reps objective/gradient passes at rank r for every
  * (variant, row_blocks) candidate with HIP events on `stream`, keeps the
  * fastest in the handle and returns it (host int32 each, nullable).  Uses the
@@ -434,6 +446,18 @@ alm_bm_status alm_bm_ws_adam(float* params, const float* grad, float* m, float* 
  * rows x_k of X (host k x p, row-major), by the normal equations.              */
 alm_bm_status alm_bm_ws_ridge_fit(const double* X, const double* t, int32_t k, int32_t p, double lambda,
                                   double* coef);
+
+/* ---- measurement ------------------------------------------------------------
+ * Random-row gather probe, the access pattern that bounds the sparse cost
+ * product (each stored entry of C gathers one row of the factor): reads rows
+ * idx[0..count) (each row_bytes = 8, 16, 32, 64, 128 or 256 bytes) of table
+ * (device, rows x row_bytes bytes, 8-byte aligned) and writes per-thread sums
+ * to out (device, alm_bm_gather_probe_out_size() floats) so no load is dead.
+ * idx: device int32, each in [0, rows) (not checked).  Enqueued on stream;
+ * time it with events to get the chip's gathered rows per second.           */
+int64_t alm_bm_gather_probe_out_size(void);
+alm_bm_status alm_bm_gather_probe(const void* table, int64_t rows, int32_t row_bytes, const int32_t* idx,
+                                  int64_t count, float* out, hipStream_t stream);
 
 void alm_bm_default_options(alm_bm_options* opts);
 const char* alm_bm_last_error(void);

@@ -46,6 +46,7 @@ from .alm import (  # noqa: F401
     inner_lbfgs,
     solve,
     curvature_step,
+    penalty_moments,
 )
 from .dense_alm import dense_alm  # noqa: F401
 from . import warmstart  # noqa: F401

@@ -172,6 +172,20 @@ def _psd_part(M):
     return (U * np.maximum(lam, 0.0)) @ U.T
 
 
+def penalty_moments(p, V, weights=None):
+    """The penalty's quadratic form of the negative-curvature subproblem of
+    Alg. 1 over the pairs a <= b (row-major) of the columns of V:
+        M[pair(a,b), pair(c,d)] = sum_i weights_i A_i(v_a v_b^T) A_i(v_c v_d^T)
+    (weights: one per constraint row, default 1), so that for symmetric S
+    sum_{a,b,c,d} S_ab S_cd M[pair(a,b), pair(c,d)] = sum_i weights_i A_i(V S V^T)^2."""
+    V = np.asarray(V, dtype=np.float64)
+    q = V.shape[1]
+    wts = np.ones(p.m) if weights is None else np.asarray(weights, dtype=np.float64)
+    pairs = [(a, b) for a in range(q) for b in range(a, q)]
+    img = [amap_uv(p, V[:, a], V[:, b]) for a, b in pairs]
+    return np.array([[float(np.dot(wts * x, z)) for z in img] for x in img])
+
+
 def curvature_step(p, w, sigma, V, max_iter=200000, tol=1e-12):
     """The negative-curvature subproblem of Alg. 1 (Sec. 5).
 

@@ -296,6 +296,18 @@ class Problem:
         check(lib.alm_bm_autotune(self._h, int(r), int(reps), C.byref(v), C.byref(nb), _stream(stream)), "autotune")
         return v.value, nb.value
 
+    def block_moments(self, V, edge_weight=1.0, stream=None):
+        """M4 of the block rank step for orthonormal directions V (n x q,
+        float64, on the device): host numpy np x np, np = q(q+1)/2."""
+        V = torch.as_tensor(V).to(device=self.device, dtype=torch.float64)
+        q = int(V.shape[1])
+        Vc = V.t().contiguous()  # column-major n x q
+        npair = q * (q + 1) // 2
+        M4 = np.empty((npair, npair), dtype=np.float64)
+        check(lib.alm_bm_block_moments(self._h, q, _ptr(Vc), float(edge_weight), M4.ctypes.data, _stream(stream)),
+              "block_moments")
+        return M4
+
     def kkt(self, R, y, lam_min, stream=None):
         self._check_R(R)
         self._check_y(y)

@@ -125,7 +125,7 @@ EXPORTS = [
     "alm_bm_inner_solve", "alm_bm_ws_features", "alm_bm_ws_pool", "alm_bm_ws_param_count", "alm_bm_ws_work_size",
     "alm_bm_ws_forward", "alm_bm_ws_loss_grad", "alm_bm_ws_adam", "alm_bm_ws_ridge_fit",
     "alm_bm_batch_create", "alm_bm_batch_destroy", "alm_bm_batch_offsets", "alm_bm_batch_solve",
-    "alm_bm_objective_grad_noalloc",
+    "alm_bm_objective_grad_noalloc", "alm_bm_block_moments", "alm_bm_gather_probe", "alm_bm_gather_probe_out_size",
 ]
 
 vp = C.c_void_p
@@ -158,6 +158,9 @@ def _load():
         "alm_bm_set_tiles": (i32, [vp, i32, i32]),
         "alm_bm_set_hub_threshold": (i32, [vp, i32, vp]),
         "alm_bm_psd_step": (i32, [i32, vp, vp, C.c_double, vp]),
+        "alm_bm_block_moments": (i32, [vp, i32, vp, f64, vp, vp]),
+        "alm_bm_gather_probe": (i32, [vp, i64, i32, vp, i64, vp, vp]),
+        "alm_bm_gather_probe_out_size": (i64, []),
         "alm_bm_ws_features": (i32, [vp, vp, vp, vp]),
         "alm_bm_ws_pool": (i32, [vp, i64, vp, vp, vp]),
         "alm_bm_ws_param_count": (i64, [i32, i32]),

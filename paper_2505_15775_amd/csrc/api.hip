@@ -1521,6 +1521,52 @@ static alm_bm_status restride(alm_bm_problem* p, T* R, int ss, int nc, int rd, h
   return ALM_BM_OK;
 }
 
+// Penalty quadratic form of A(V S V^T) over the pairs a <= b of q orthonormal
+// directions V (device n x q, column-major): M4[pair(a,b), pair(c,d)] = sum over
+// constraint rows of A_i(v_a v_b^T) A_i(v_c v_d^T), edge rows weighted by
+// edge_w.  Fourth moments per block from k_gram4 / k_gram4_edges, summed on the
+// host in block order; the trace row adds c_tr^2 [a = b][c = d].
+static alm_bm_status block_moments(alm_bm_problem* p, int q, const double* V, double edge_w, std::vector<double>& M4,
+                                   hipStream_t st) {
+  const auto& d = p->d;
+  const int np = q * (q + 1) / 2, ne = np * (np + 1) / 2;
+  const bool edges = d.cons_kind != ALM_BM_CONS_DIAG;
+  if (edges) launch_gram4_edges(d.n_edges, d.n, q, d.edge_i, d.edge_j, V, p->gpart, p->lnb, st);
+  else launch_gram4(d.n, q, V, p->gpart, p->lnb, st);
+  std::vector<double> gp((size_t)p->lnb * ne);
+  HIPCHK(hipMemcpyAsync(gp.data(), p->gpart, gp.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  HIPCHK(hipGetLastError());
+  M4.assign((size_t)np * np, 0.0);
+  for (int e = 0, p1 = 0, p2 = 0; e < ne; ++e) {
+    double s = 0.0;
+    for (int b = 0; b < p->lnb; ++b) s += gp[(size_t)b * ne + e];
+    M4[(size_t)p1 * np + p2] = M4[(size_t)p2 * np + p1] = (edges ? edge_w : 1.0) * s;
+    if (++p2 == np) p2 = ++p1;
+  }
+  if (edges && d.trace_coef != 0.0) {
+    // trace row: c_tr tr(V S V^T) = c_tr tr(S) for orthonormal V
+    for (int a0 = 0; a0 < q; ++a0)
+      for (int c0 = 0; c0 < q; ++c0) {
+        const int pa = a0 * q - a0 * (a0 - 1) / 2, pc = c0 * q - c0 * (c0 - 1) / 2;  // index of (a, a), (c, c)
+        M4[(size_t)pa * np + pc] += d.trace_coef * d.trace_coef;
+      }
+  }
+  return ALM_BM_OK;
+}
+
+extern "C" alm_bm_status alm_bm_block_moments(alm_bm_problem* p, int32_t q, const double* V, double edge_weight,
+                                              double* M4, hipStream_t st) {
+  if (!p || !V || !M4) return fail(ALM_BM_ERR_INVALID_ARG, "block_moments: null argument");
+  if (q < 1 || q > p->d.rank_block_max || !p->gpart)
+    return fail(ALM_BM_ERR_INVALID_ARG, "block_moments: q must be in 1..rank_block_max of the handle");
+  if (!(edge_weight >= 0.0)) return fail(ALM_BM_ERR_INVALID_ARG, "block_moments: edge_weight must be >= 0");
+  std::vector<double> out;
+  STCHK(block_moments(p, q, V, edge_weight, out, st));
+  std::copy(out.begin(), out.end(), M4);
+  return ALM_BM_OK;
+}
+
 // Block rank step (Alg. 1 with several directions): the
 // smallest Ritz pairs below -tau_rank of a full Lanczos pass on Z(w) from a
 // random start give V (n x qv, orthonormal, V^T Z V = diag(theta)); k_gram4
@@ -1570,28 +1616,9 @@ static alm_bm_status block_rank_step(alm_bm_problem* p, T* R, int& r, int& w, in
   HIPCHK(hipMemcpyAsync(p->ycoef, Y.data(), Y.size() * sizeof(double), hipMemcpyHostToDevice, st));
   for (int j = 0; j < qv; ++j)
     launch_combine(n, m, p->Q, n, p->ycoef + (long)j * m, p->vblk + (long)j * n, p->lpart2, p->lnb, st);
-  const int np = qv * (qv + 1) / 2, ne = np * (np + 1) / 2;
-  const bool edges = d.cons_kind != ALM_BM_CONS_DIAG;
-  if (edges) launch_gram4_edges(d.n_edges, n, qv, d.edge_i, d.edge_j, p->vblk, p->gpart, p->lnb, st);
-  else launch_gram4(n, qv, p->vblk, p->gpart, p->lnb, st);
-  std::vector<double> gp((size_t)p->lnb * ne);
-  HIPCHK(hipMemcpyAsync(gp.data(), p->gpart, gp.size() * sizeof(double), hipMemcpyDeviceToHost, st));
-  HIPCHK(hipStreamSynchronize(st));
-  std::vector<double> M4((size_t)np * np, 0.0);
-  for (int e = 0, p1 = 0, p2 = 0; e < ne; ++e) {
-    double s = 0.0;
-    for (int b = 0; b < p->lnb; ++b) s += gp[(size_t)b * ne + e];
-    M4[(size_t)p1 * np + p2] = M4[(size_t)p2 * np + p1] = (edges ? p->rho : 1.0) * s;
-    if (++p2 == np) p2 = ++p1;
-  }
-  if (edges && d.trace_coef != 0.0) {
-    // trace row: c_tr tr(V S V^T) = c_tr tr(S) for orthonormal V
-    for (int a0 = 0; a0 < qv; ++a0)
-      for (int c0 = 0; c0 < qv; ++c0) {
-        const int pa = a0 * qv - a0 * (a0 - 1) / 2, pc = c0 * qv - c0 * (c0 - 1) / 2;  // index of (a, a), (c, c)
-        M4[(size_t)pa * np + pc] += d.trace_coef * d.trace_coef;
-      }
-  }
+  const int np = qv * (qv + 1) / 2;
+  std::vector<double> M4;
+  STCHK(block_moments(p, qv, p->vblk, p->rho, M4, st));
   const std::vector<double> S = block_subproblem(qv, th, M4, np, sigma);
   std::vector<double> lam, U;
   small_sym_eig(qv, S, lam, U);

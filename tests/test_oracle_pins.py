@@ -170,3 +170,47 @@ def test_min_eigs_arpack_branch_cycle_spectrum(n):
     if n % 2:
         assert abs(vals[0] - vals[1]) <= 1e-10
     assert abs(oracle.min_eig(p, y, dense_limit=10) - spec[0]) <= 1e-10
+
+
+# ---------------------------------------------------------------- penalty moments
+
+
+@pytest.mark.parametrize("kind", ["maxcut", "lovasz"])
+def test_penalty_moments_quadratic_form_equals_penalty_of_the_step(kind):
+    """For symmetric S, sum_{abcd} S_ab S_cd M[pair(a,b), pair(c,d)] must equal
+    sum_i w_i A_i(V S V^T)^2 with A applied to the dense matrix V S V^T through
+    the explicit constraint matrices (another route than the pair images)."""
+    rng = np.random.default_rng(11)
+    if kind == "maxcut":
+        p = oracle.maxcut_sdp(gen.er_graph(30, 80, 2, "gauss"))
+        mats = []
+        for i in range(p.n):
+            E = np.zeros((p.n, p.n))
+            E[i, i] = 1.0
+            mats.append(E)
+    else:
+        g = gen.er_graph(25, 60, 3, "unit")
+        p = oracle.lovasz_sdp(g)
+        mats = [np.eye(p.n)]
+        for i, j in zip(g.ei, g.ej):
+            E = np.zeros((p.n, p.n))
+            E[i, j] = E[j, i] = 0.5
+            mats.append(E)
+    q = 3
+    V = np.linalg.qr(rng.standard_normal((p.n, q)))[0]
+    wts = rng.uniform(0.5, 2.0, p.m)
+    M = oracle.penalty_moments(p, V, wts)
+    pairs = [(a, b) for a in range(q) for b in range(a, q)]
+    for _ in range(3):
+        S = rng.standard_normal((q, q))
+        S = S + S.T
+        X = V @ S @ V.T
+        direct = sum(wi * np.sum(A * X) ** 2 for wi, A in zip(wts, mats))
+        # expand the sum over all (a, b, c, d) through the pair numbering
+        full = 0.0
+        for i1, (a, b) in enumerate(pairs):
+            for i2, (c, d) in enumerate(pairs):
+                m1 = 1.0 if a == b else 2.0
+                m2 = 1.0 if c == d else 2.0
+                full += m1 * m2 * S[a, b] * S[c, d] * M[i1, i2]
+        assert math.isclose(full, direct, rel_tol=1e-12)
