@@ -174,6 +174,14 @@ typedef struct {
                                 -tau_rank of a full Lanczos pass, S of the small PSD
                                 subproblem, and the columns of V S^(1/2); at most the
                                 handle's rank_block_max                            */
+  int32_t resume_outer;      /* 0      resume a stopped solve: the outer iteration to
+                                continue from (the stopped solve's result.outer),
+                                with R, r and y as it returned them                */
+  double resume_inner_tol;   /* 0      with resume_outer: the stopped solve's
+                                result.inner_tol (<= 0: none)                      */
+  double resume_pinf;        /* 0      with resume_outer: its result.pinf (<= 0: none);
+                                with the three, an FP64 solve stopped by max_outer
+                                and resumed repeats the uninterrupted one bitwise   */
   alm_bm_inner_solver inner_solver; /* GD  subproblem solver: gradient descent (eq. GD)
                                 or L-BFGS (the solver of the SDPLR code Sec. 2 names;
                                 DIAG family, needs lbfgs_memory_max >= lbfgs_memory),
@@ -199,6 +207,7 @@ typedef struct {
   double sigma_final;        /* penalty at the end (differs from sigma only with the
                                 schedule)                                              */
   int32_t sigma_increases;   /* schedule steps taken                                   */
+  double inner_tol;          /* tolerance of the last subproblem (for resume_inner_tol) */
   double lanczos_resid;      /* Ritz residual ||Z v - theta v|| of the Lanczos run
                                 behind lam_min.  A solve returns ALM_BM_OK only when
                                 this met the Lanczos tolerance and theta did not

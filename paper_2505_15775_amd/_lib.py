@@ -86,6 +86,9 @@ class Options(C.Structure):
         ("sigma_max", C.c_double),
         ("pinf_reduction", C.c_double),
         ("rank_block", C.c_int32),
+        ("resume_outer", C.c_int32),
+        ("resume_inner_tol", C.c_double),
+        ("resume_pinf", C.c_double),
         ("inner_solver", C.c_int32),
         ("lbfgs_memory", C.c_int32),
     ]
@@ -110,6 +113,7 @@ class Result(C.Structure):
         ("time_promoted_s", C.c_double),
         ("sigma_final", C.c_double),
         ("sigma_increases", C.c_int32),
+        ("inner_tol", C.c_double),
         ("lanczos_resid", C.c_double),
     ]
 

@@ -1669,6 +1669,7 @@ static alm_bm_status solve_impl(alm_bm_problem* p, const alm_bm_options& o, T* R
     const double pinf_last = pinf_prev;  // of the previous outer iteration (inf at the start)
     const double tol = std::max(o.eps_kkt / 10.0, std::min(o.inner_tol_scale, std::min(pinf_prev, o.inner_tol_decay * tol_prev)));
     tol_prev = tol;
+    acc.inner_tol = tol;
     int iters = 0, flag = 0;
     STCHK(inner_solve<T>(p, w, R, y, sigma, tol, o, gc, st, iters, flag));
     acc.inner_total += iters;
@@ -1831,6 +1832,8 @@ extern "C" alm_bm_status alm_bm_solve(alm_bm_problem* p, const alm_bm_options* o
   if (o.sigma_edges < 0.0) return fail(ALM_BM_ERR_INVALID_ARG, "solve: sigma_edges must be >= 0");
   if (!(o.sigma_growth >= 1.0) || !(o.sigma_max >= o.sigma) || !(o.pinf_reduction > 0.0 && o.pinf_reduction <= 1.0))
     return fail(ALM_BM_ERR_INVALID_ARG, "solve: need sigma_growth >= 1, sigma_max >= sigma, 0 < pinf_reduction <= 1");
+  if (o.resume_outer < 0 || o.resume_outer >= o.max_outer)
+    return fail(ALM_BM_ERR_INVALID_ARG, "solve: resume_outer must be in 0..max_outer-1");
   if (o.rank_block < 1 || o.rank_block > std::max(1, p->d.rank_block_max))
     return fail(ALM_BM_ERR_INVALID_ARG, "solve: rank_block must be in 1..rank_block_max of the handle (" +
                                             std::to_string(std::max(1, p->d.rank_block_max)) + ")");
@@ -1839,6 +1842,8 @@ extern "C" alm_bm_status alm_bm_solve(alm_bm_problem* p, const alm_bm_options* o
   HIPCHK(hipStreamSynchronize(st_user));
   hipStream_t st = p->ss;
   InnerScope inner_scope(p, lb_m);
+  // a NaN seen by an earlier call must not fail this one
+  HIPCHK(hipMemsetAsync(&p->sc_api->numeric_error, 0, sizeof(int32_t), st));
   // penalty of the edge rows relative to sigma, for the length of this solve
   struct RhoScope {
     alm_bm_problem* p;
@@ -1850,8 +1855,12 @@ extern "C" alm_bm_status alm_bm_solve(alm_bm_problem* p, const alm_bm_options* o
   acc.promoted_at_outer = -1;
   int r = *r_io;
   int w = pad_width(r, p->d.r_max);
-  int k_done = 0;
-  double pinf_prev = INFINITY, tol_prev = INFINITY;
+  // resume: the outer index (Lanczos seeds) and the tolerance recurrence of a
+  // stopped solve, so that stopping and resuming repeats the uninterrupted solve
+  const int k0 = o.resume_outer;
+  int k_done = k0;
+  double pinf_prev = o.resume_pinf > 0.0 ? o.resume_pinf : INFINITY;
+  double tol_prev = o.resume_inner_tol > 0.0 ? o.resume_inner_tol : INFINITY;
   double sigma = o.sigma;
   acc.sigma_final = sigma;
   bool stalled = false;
@@ -1859,7 +1868,7 @@ extern "C" alm_bm_status alm_bm_solve(alm_bm_problem* p, const alm_bm_options* o
   if (p->d.precision == ALM_BM_BF16 && o.bf16_promote) {
     bf16* Rb = static_cast<bf16*>(R);
     STCHK(restride<bf16>(p, Rb, r, r, w, st));
-    s = solve_impl<bf16>(p, o, Rb, y, st, r, w, 0, k_done, true, stalled, t0, pinf_prev, tol_prev, sigma, acc);
+    s = solve_impl<bf16>(p, o, Rb, y, st, r, w, k0, k_done, true, stalled, t0, pinf_prev, tol_prev, sigma, acc);
     if (s >= 0 && stalled) {
       // precision ladder: continue with float storage (the float cost copy is resident)
       const long n = p->d.n;
@@ -1889,7 +1898,7 @@ extern "C" alm_bm_status alm_bm_solve(alm_bm_problem* p, const alm_bm_options* o
       T* Rt = static_cast<T*>(R);
       alm_bm_status s1 = restride<T>(p, Rt, r, r, w, st);
       if (s1 < 0) return s1;
-      s1 = solve_impl<T>(p, o, Rt, y, st, r, w, 0, k_done, false, stalled, t0, pinf_prev, tol_prev, sigma, acc);
+      s1 = solve_impl<T>(p, o, Rt, y, st, r, w, k0, k_done, false, stalled, t0, pinf_prev, tol_prev, sigma, acc);
       const alm_bm_status s2 = restride<T>(p, Rt, w, r, r, st);
       return s1 < 0 ? s1 : (s2 < 0 ? s2 : s1);
     });
@@ -2638,6 +2647,7 @@ extern "C" alm_bm_status alm_bm_batch_solve(alm_bm_batch* b, const alm_bm_option
   if (o.rank_block != 1) return fail(ALM_BM_ERR_UNSUPPORTED, "batch_solve: rank_block > 1 is for single solves");
   if (o.inner_solver != ALM_BM_INNER_GD)
     return fail(ALM_BM_ERR_UNSUPPORTED, "batch_solve: the L-BFGS inner solver is for single solves");
+  if (o.resume_outer != 0) return fail(ALM_BM_ERR_UNSUPPORTED, "batch_solve: resume is for single solves");
   HIPCHK(hipStreamSynchronize(st_user));
   hipStream_t st = b->p->ss;
   alm_bm_status s = with_storage(b->p->d.precision, [&]<typename T>() {

@@ -173,6 +173,7 @@ __global__ void k_inner_reset(DevScalars* sc, double tol, int max_inner, int ste
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     sc->flag = 0;
     sc->iter = 0;
+    sc->numeric_error = 0;
     sc->tol = tol;
     sc->max_inner = max_inner;
     sc->step_rule = step_rule;
@@ -187,6 +188,7 @@ __global__ void k_inner_reset_batch(DevScalars* sc, int count, const double* __r
   if (q >= count) return;
   sc[q].flag = active[q] ? 0 : 3;
   sc[q].iter = 0;
+  sc[q].numeric_error = 0;
   sc[q].tol = tols[q];
   sc[q].max_inner = max_inner;
   sc[q].step_rule = step_rule;
