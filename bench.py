@@ -254,6 +254,11 @@ def kernels_leg(g, reps=20):
     out["lovasz_objective_grad"] = {"n": n, "edges": E, "r": r, "precision": "f32", "ms": round(1000 * t, 4),
                                     "evals_per_s": round(1.0 / t, 2), "algorithmic_bytes": byts,
                                     "gbs": round(byts / t / 1e9, 1)}
+    # the exact line search along a direction (passes 1-3 and their finalizers)
+    _, Gd, _ = pl.objective_grad(R, y, 1.0)
+    pl.line_search(R, Gd, y, 1.0)
+    t = time_events(lambda: pl.line_search(R, Gd, y, 1.0), reps) / reps
+    out["lovasz_line_search"] = {"ms": round(1000 * t, 4)}
     pl.close()
 
     pm = almbm.Problem.maxcut(g.n, g.ei, g.ej, g.w, precision="f32", r_max=16, lanczos_kmax=0, device="cuda:0",

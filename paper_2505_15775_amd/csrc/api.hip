@@ -59,6 +59,7 @@ struct alm_bm_problem {
   int count = 1;                  // instances (DevScalars in sc_solve)
   double rho = 1.0;               // edge rows' penalty / sigma (set for the length of a solve)
   double* part = nullptr;     // nblk * (NUM_P + kMaxR)
+  double* part2 = nullptr;    // edge family: 64 * (NUM_P + kMaxR), first stage of the finalizers
   double* part_c2 = nullptr;  // nblk
   double* part_vec = nullptr; // vec kernels
   DevScalars* sc_api = nullptr;
@@ -521,6 +522,7 @@ extern "C" alm_bm_status alm_bm_create(const alm_bm_problem_desc* desc, hipStrea
     }
     p->adj = EdgeAdj{drp, dci, deid, durp, d.edge_j, (float)(2.0 * (double)d.n_edges / (double)std::max<long>(1, d.n))};
     CK(dalloc_t(p, &p->wE, std::max<long>(1, E)));
+    CK(dalloc_t(p, &p->part2, (size_t)64 * (NUM_P + kMaxR)));
   }
 
   // ---- workspace
@@ -617,10 +619,10 @@ static void enqueue_objgrad(alm_bm_problem* p, int r, const T* R, const double* 
     launch_fin_objgrad(p->part, p->nblk, sc, sigma, mode, f_out, st, p->tab, p->count);
   } else {
     launch_edges_p1<T>(p->adj, d.n, r, p->variant, R, y, d.b, sigma, Av, p->wE, p->part, sc, p->nblk, st, p->rho);
-    launch_fin_edges1(p->part, p->nblk, r, sc, y, d.b, sigma, d.trace_coef, Av, st);
+    launch_fin_edges1(p->part, p->nblk, r, sc, y, d.b, sigma, d.trace_coef, Av, st, p->part2);
     launch_edges_p2<T>(cost_of<T>(p), p->adj, r, p->variant, R, p->wE, d.trace_coef, d.j_coef, nullptr, G, p->part,
                        sc, p->nblk, st);
-    launch_fin_edges2(p->part, p->nblk, r, sc, sigma, mode, f_out, st);
+    launch_fin_edges2(p->part, p->nblk, r, sc, sigma, mode, f_out, st, p->part2);
   }
 }
 
@@ -661,7 +663,8 @@ static void enqueue_inner_step(alm_bm_problem* p, int r, T* R, const double* y, 
     enqueue_objgrad<T>(p, r, R, y, sigma, G, p->Av, sc, 1, nullptr, st);
     launch_edges_p3<T>(cost_of<T>(p), p->adj, r, p->variant, R, G, y, d.b, p->Av, p->part, sc, p->nblk, st,
                        p->rho);
-    launch_fin_edges3(p->part, p->nblk, r, sc, y, d.b, sigma, d.trace_coef, d.j_coef, 1, nullptr, nullptr, st);
+    launch_fin_edges3(p->part, p->nblk, r, sc, y, d.b, sigma, d.trace_coef, d.j_coef, 1, nullptr, nullptr, st,
+                      p->part2);
     launch_update<T>((long)d.n * r, R, G, sc, 1, st);
   }
 }
@@ -742,12 +745,13 @@ extern "C" alm_bm_status alm_bm_line_search(alm_bm_problem* p, int32_t r, const 
     } else {
       DevScalars* sc = p->sc_api;
       launch_edges_p1<T>(p->adj, d.n, r, p->variant, Rt, y, d.b, sigma, p->Av, p->wE, p->part, sc, p->nblk, st);
-      launch_fin_edges1(p->part, p->nblk, r, sc, y, d.b, sigma, d.trace_coef, p->Av, st);
+      launch_fin_edges1(p->part, p->nblk, r, sc, y, d.b, sigma, d.trace_coef, p->Av, st, p->part2);
       launch_edges_p2<T>(cost_of<T>(p), p->adj, r, p->variant, Rt, p->wE, d.trace_coef, d.j_coef, Gt, nullptr,
                          p->part, sc, p->nblk, st);
-      launch_fin_edges2(p->part, p->nblk, r, sc, sigma, 0, nullptr, st);
+      launch_fin_edges2(p->part, p->nblk, r, sc, sigma, 0, nullptr, st, p->part2);
       launch_edges_p3<T>(cost_of<T>(p), p->adj, r, p->variant, Rt, Gt, y, d.b, p->Av, p->part, sc, p->nblk, st);
-      launch_fin_edges3(p->part, p->nblk, r, sc, y, d.b, sigma, d.trace_coef, d.j_coef, 0, coeffs, t_star, st);
+      launch_fin_edges3(p->part, p->nblk, r, sc, y, d.b, sigma, d.trace_coef, d.j_coef, 0, coeffs, t_star, st,
+                        p->part2);
     }
     return 0;
   });
@@ -770,7 +774,7 @@ extern "C" alm_bm_status alm_bm_gd_step(alm_bm_problem* p, int32_t r, void* R, c
       launch_fin_step(p->part_c2, p->nblk, 1, sc, sigma, 0.0, 0, nullptr, t, st);
     } else {
       launch_edges_p3<T>(cost_of<T>(p), p->adj, r, p->variant, Rt, Gt, y, d.b, p->Av, p->part, sc, p->nblk, st);
-      launch_fin_edges3(p->part, p->nblk, r, sc, y, d.b, sigma, d.trace_coef, d.j_coef, 0, nullptr, t, st);
+      launch_fin_edges3(p->part, p->nblk, r, sc, y, d.b, sigma, d.trace_coef, d.j_coef, 0, nullptr, t, st, p->part2);
     }
     launch_update<T>((long)d.n * r, Rt, Gt, sc, 0, st);
     return 0;

@@ -20,6 +20,7 @@
 namespace almbm {
 
 constexpr int kEdgePS = NUM_P + kMaxR;  // partial stride: scalars, then r column sums
+constexpr int kEdgePre = 64;            // rows after the finalizers' first reduction stage
 
 // out[c] = sum over blocks of the column-sum partials (c < r <= kMaxR), by the
 // whole (single) block: P = kBlock / r threads per column take the blocks
@@ -117,22 +118,35 @@ k_edges_p1(EdgeAdj A, long n, int r, const T* __restrict__ R, const double* __re
     }
     rr = group_sum<LPR>(rr);
     const int k0 = A.urp[i], k1 = A.urp[i + 1];
-    for (int k = k0 + grp; k < k1; k += S) {
-      const int j = A.uci[k];
-      V rj[VEC];
-      load_frag<T, VEC, FULL>(R + (long)j * r, lane, r, rj);
-      V s = 0;
+    // kUnroll neighbour rows in flight per group (entries past the row end
+    // gather row i itself and are skipped), edges taken in order
+    for (int k = k0 + grp; k < k1; k += S * kUnroll) {
+      int jj[kUnroll];
 #pragma unroll
-      for (int v = 0; v < VEC; ++v) s += ri[v] * rj[v];
-      s = group_sum<LPR>(s);
-      const double a = s, be = b[1 + k], ye = y[1 + k];
-      const double e = a - be;
-      if (lane == 0) {
-        if (Av) Av[1 + k] = a;
-        wE[k] = ye - rho * sigma * e;
+      for (int u = 0; u < kUnroll; ++u) {
+        const int kk = k + u * S;
+        jj[u] = kk < k1 ? A.uci[kk] : (int)i;
       }
-      acc.add(lane, P_YBMA, ye * (be - a));
-      acc.add(lane, P_EE, rho * e * e);
+      V rj[kUnroll][VEC];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) load_frag<T, VEC, FULL>(R + (long)jj[u] * r, lane, r, rj[u]);
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const int kk = k + u * S;
+        if (kk >= k1) break;
+        V s = 0;
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) s += ri[v] * rj[u][v];
+        s = group_sum<LPR>(s);
+        const double a = s, be = b[1 + kk], ye = y[1 + kk];
+        const double e = a - be;
+        if (lane == 0) {
+          if (Av) Av[1 + kk] = a;
+          wE[kk] = ye - rho * sigma * e;
+        }
+        acc.add(lane, P_YBMA, ye * (be - a));
+        acc.add(lane, P_EE, rho * e * e);
+      }
     }
     if (grp == 0) acc.add(lane, P_RR, (double)rr);
   }
@@ -306,20 +320,33 @@ k_edges_p3(Cost<typename Acc<T>::type> C, EdgeAdj A, int r, const T* __restrict_
       acc.add(lane, P_C2, (double)gq);
     }
     const int k0 = A.urp[i], k1 = A.urp[i + 1];
-    for (int k = k0 + grp; k < k1; k += S) {
-      const int j = A.uci[k];
-      V rj[VEC], gj[VEC];
-      load_frag<T, VEC, FULL>(R + (long)j * r, lane, r, rj);
-      load_frag<T, VEC, FULL>(G + (long)j * r, lane, r, gj);
+    constexpr int U3 = kUnroll / 2;  // two rows (R_j, G_j) per edge
+    for (int k = k0 + grp; k < k1; k += S * U3) {
+      int jj[U3];
+#pragma unroll
+      for (int u = 0; u < U3; ++u) {
+        const int kk = k + u * S;
+        jj[u] = kk < k1 ? A.uci[kk] : (int)i;
+      }
+      V rj[U3][VEC], gj[U3][VEC];
+#pragma unroll
+      for (int u = 0; u < U3; ++u) {
+        load_frag<T, VEC, FULL>(R + (long)jj[u] * r, lane, r, rj[u]);
+        load_frag<T, VEC, FULL>(G + (long)jj[u] * r, lane, r, gj[u]);
+      }
+#pragma unroll
+      for (int u = 0; u < U3; ++u) {
+      const int kk = k + u * S;
+      if (kk >= k1) break;
       V a1 = 0, a2 = 0;
 #pragma unroll
       for (int v = 0; v < VEC; ++v) {
-        a1 += ri[v] * gj[v] + gi[v] * rj[v];
-        a2 += gi[v] * gj[v];
+        a1 += ri[v] * gj[u][v] + gi[v] * rj[u][v];
+        a2 += gi[v] * gj[u][v];
       }
       a1 = group_sum<LPR>(a1);
       a2 = group_sum<LPR>(a2);
-      const double ye = y[1 + k], e = Av[1 + k] - b[1 + k];
+      const double ye = y[1 + kk], e = Av[1 + kk] - b[1 + kk];
       const double d1 = a1, d2 = a2;
       acc.add(lane, P_YA1, ye * d1);
       acc.add(lane, P_YA2, ye * d2);
@@ -328,6 +355,7 @@ k_edges_p3(Cost<typename Acc<T>::type> C, EdgeAdj A, int r, const T* __restrict_
       acc.add(lane, P_A1A1, rho * d1 * d1);
       acc.add(lane, P_A1A2, rho * d1 * d2);
       acc.add(lane, P_A2A2, rho * d2 * d2);
+      }
     }
   }
   acc.block_store(lane, part + (long)blockIdx.x * kEdgePS);
@@ -479,17 +507,48 @@ void launch_edges_p3(const Cost<typename Acc<T>::type>& C, const EdgeAdj& A, int
   ALMBM_DISPATCH_EDGES(T, p3_cfg, C, A, r, R, G, y, b, Av, part, sc, nblk, st, rho);
 }
 
+// First stage of the finalizers' reductions: block k of kEdgePre sums the
+// partial rows [k nb / kEdgePre, (k+1) nb / kEdgePre) of the first ncols
+// columns in order into row k of out, so the one-block finalizer then reduces
+// kEdgePre rows instead of nb (thousands at the Lovasz and completion shapes).
+__global__ void __launch_bounds__(kBlock)
+k_edges_prereduce(const double* __restrict__ part, int nb, int ncols, double* __restrict__ out) {
+  const int c = threadIdx.x;
+  if (c >= ncols) return;
+  const long lo = (long)blockIdx.x * nb / gridDim.x, hi = (long)(blockIdx.x + 1) * nb / gridDim.x;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  long bi = lo;
+  for (; bi + 4 <= hi; bi += 4) {
+    a0 += part[bi * kEdgePS + c];
+    a1 += part[(bi + 1) * kEdgePS + c];
+    a2 += part[(bi + 2) * kEdgePS + c];
+    a3 += part[(bi + 3) * kEdgePS + c];
+  }
+  for (; bi < hi; ++bi) a0 += part[bi * kEdgePS + c];
+  out[(long)blockIdx.x * kEdgePS + c] = (a0 + a1) + (a2 + a3);
+}
+
+static const double* prereduce(const double* part, int& nb, int r, double* part2, hipStream_t st) {
+  if (!part2 || nb <= kEdgePre) return part;
+  hipLaunchKernelGGL(k_edges_prereduce, dim3(kEdgePre), dim3(kBlock), 0, st, part, nb, NUM_P + r, part2);
+  nb = kEdgePre;
+  return part2;
+}
+
 void launch_fin_edges1(const double* part, int nb, int r, DevScalars* sc, const double* y, const double* b,
-                       double sigma, double c_tr, double* Av, hipStream_t st) {
+                       double sigma, double c_tr, double* Av, hipStream_t st, double* part2) {
+  part = prereduce(part, nb, r, part2, st);
   hipLaunchKernelGGL(k_fin_edges1, dim3(1), dim3(kBlock), 0, st, part, nb, r, sc, y, b, sigma, c_tr, Av);
 }
 void launch_fin_edges2(const double* part, int nb, int r, DevScalars* sc, double sigma, int mode, double* f_out,
-                       hipStream_t st) {
+                       hipStream_t st, double* part2) {
+  part = prereduce(part, nb, r, part2, st);
   hipLaunchKernelGGL(k_fin_edges2, dim3(1), dim3(kBlock), 0, st, part, nb, r, sc, sigma, mode, f_out);
 }
 void launch_fin_edges3(const double* part, int nb, int r, DevScalars* sc, const double* y, const double* b,
                        double sigma, double c_tr, double j_coef, int mode, double* coeffs_out, double* t_out,
-                       hipStream_t st) {
+                       hipStream_t st, double* part2) {
+  part = prereduce(part, nb, r, part2, st);
   hipLaunchKernelGGL(k_fin_edges3, dim3(1), dim3(kBlock), 0, st, part, nb, r, sc, y, b, sigma, c_tr, j_coef, mode,
                      coeffs_out, t_out);
 }

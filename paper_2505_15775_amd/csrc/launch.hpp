@@ -64,13 +64,15 @@ template <typename T>
 void launch_edges_p3(const Cost<typename Acc<T>::type>& C, const EdgeAdj& A, int r, int variant, const T* R,
                      const T* G, const double* y, const double* b, const double* Av, double* part,
                      const DevScalars* sc, int nblk, hipStream_t st, double rho = 1.0);
+// part2 (64 x (NUM_P + kMaxR) doubles, nullable): the finalizers first reduce
+// the nb partial rows to 64 with 64 blocks, then finish with one block.
 void launch_fin_edges1(const double* part, int nb, int r, DevScalars* sc, const double* y, const double* b,
-                       double sigma, double c_tr, double* Av, hipStream_t st);
+                       double sigma, double c_tr, double* Av, hipStream_t st, double* part2 = nullptr);
 void launch_fin_edges2(const double* part, int nb, int r, DevScalars* sc, double sigma, int mode, double* f_out,
-                       hipStream_t st);
+                       hipStream_t st, double* part2 = nullptr);
 void launch_fin_edges3(const double* part, int nb, int r, DevScalars* sc, const double* y, const double* b,
                        double sigma, double c_tr, double j_coef, int mode, double* coeffs_out, double* t_out,
-                       hipStream_t st);
+                       hipStream_t st, double* part2 = nullptr);
 
 void launch_fin_objgrad(const double* part, int nb, DevScalars* sc, double sigma, int mode, double* f_out,
                         hipStream_t st, const BlockTab& tab = BlockTab{}, int count = 1);
