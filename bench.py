@@ -180,7 +180,7 @@ def per_outer_rows(prob, y, steps):
             "lanczos_ms_total": 1000.0 * tl, "lanczos_ms_per_step": 1000.0 * tl / max(1, iters)}
 
 
-def batch_leg(count, eps, sigma, prec, seed=3):
+def batch_leg(count, eps, sigma, prec, seed=3, loop=True, tune=True):
     """Uneven MaxCut instances (n log-uniform in [1e3, 2e5], average degree
     uniform in [4, 32], +-1 weights, r in {8, 16}) solved together by one
     batched solve, then one by one with the same options."""
@@ -196,6 +196,12 @@ def batch_leg(count, eps, sigma, prec, seed=3):
     probs = [almbm.Problem.maxcut(g.n, g.ei, g.ej, g.w, precision=prec, r_max=64, lanczos_kmax=40, device="cuda:0",
                                   validate=False) for g, _ in insts]
     batch = almbm.Batch(probs, rank_stride=64)
+    table, t_tune = None, 0.0
+    if tune:
+        t0 = time.perf_counter()
+        table = batch.autotune(reps=3)
+        t_tune = time.perf_counter() - t0
+        log(f"[bench] batch: tile variants per width {table} (tuned in {t_tune:.2f}s)")
     factors = [gen.init_factor(g.n, r, 1) for g, r in insts]
     opts = dict(eps_kkt=eps, sigma=sigma, max_outer=300)
     torch.cuda.synchronize()
@@ -207,7 +213,7 @@ def batch_leg(count, eps, sigma, prec, seed=3):
     t0 = time.perf_counter()
     nconv = 0
     worst = 0.0
-    for q, p in enumerate(probs):
+    for q, p in enumerate(probs if loop else []):
         s1, r1, _, _ = p.solve(factors[q], **opts)
         nconv += int(s1 == 0)
         worst = max(worst, abs(r1["pobj"] - res[q]["pobj"]) / abs(r1["pobj"]))
@@ -215,15 +221,19 @@ def batch_leg(count, eps, sigma, prec, seed=3):
             log(f"[bench] batch loop: instance {q} n={p.n} outer {r1['outer']} {time.perf_counter() - t0:.1f}s")
     torch.cuda.synchronize()
     tl = time.perf_counter() - t0
-    log(f"[bench] batch: per-instance loop {tl:.1f}s, {nconv}/{count} converged")
+    if loop:
+        log(f"[bench] batch: per-instance loop {tl:.1f}s, {nconv}/{count} converged")
     batch.close()
     for p in probs:
         p.close()
     return {"instances": count, "sum_n": sum_n, "sum_nnz": sum_nnz, "precision": prec, "eps_kkt": eps,
             "sigma": sigma, "batched_s": round(tb, 2), "batched_converged": int(sum(s == 0 for s in sts)),
-            "loop_s": round(tl, 2), "loop_converged": nconv, "speedup": round(tl / tb, 3),
+            "loop_s": round(tl, 2) if loop else None, "loop_converged": nconv if loop else None,
+            "speedup": round(tl / tb, 3) if loop else None,
             "max_outer_batched": int(max(x["outer"] for x in res)),
-            "max_rel_objective_diff": worst}
+            "max_rel_objective_diff": worst if loop else None,
+            "tile_variants": {str(k): v for k, v in table.items()} if table else None,
+            "tune_s": round(t_tune, 3)}
 
 
 def kernels_leg(g, reps=20):
@@ -575,6 +585,8 @@ def main():
     ap.add_argument("--lbfgs-memory", type=int, default=3, help="L-BFGS pairs kept")
     ap.add_argument("--batch", type=int, default=0, help="also the batched solve of this many instances vs a loop")
     ap.add_argument("--batch-eps", type=float, default=1e-4)
+    ap.add_argument("--batch-no-loop", action="store_true", help="skip the per-instance loop of the batch leg")
+    ap.add_argument("--batch-no-tune", action="store_true", help="batch leg with the default tiles")
     ap.add_argument("--kernels", action="store_true", help="also time the edge-family and warm-start kernels")
     ap.add_argument("--completion", action="store_true", help="also the matrix completion instances of Table 2")
     ap.add_argument("--completion-sigma", type=float, default=0.03, help="penalty for the matrix completion solves")
@@ -656,7 +668,8 @@ def main():
         torch.cuda.empty_cache()
         solves = solve_legs(g, args)
 
-    batch = batch_leg(args.batch, args.batch_eps, args.sigma, "f64") if args.batch > 0 else None
+    batch = batch_leg(args.batch, args.batch_eps, args.sigma, "f64", loop=not args.batch_no_loop,
+                      tune=not args.batch_no_tune) if args.batch > 0 else None
     other = kernels_leg(g) if args.kernels else None
     completion = completion_leg(sigma=args.completion_sigma) if args.completion else None
     skewed = rmat_leg(args.rmat) if args.rmat else None

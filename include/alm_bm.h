@@ -42,7 +42,8 @@
  *   - All work is enqueued on the given stream.  Calls that return host
  *     results synchronise it: alm_bm_solve, alm_bm_inner_solve,
  *     alm_bm_lanczos_min_eig (its small tridiagonal eigensolve runs on the
- *     host), alm_bm_kkt, alm_bm_autotune and alm_bm_batch_solve;
+ *     host), alm_bm_kkt, alm_bm_autotune, alm_bm_batch_autotune and
+ *     alm_bm_batch_solve;
  *     alm_bm_set_hub_threshold synchronises the device.
  *   - A handle is not thread-safe.  Calls that overlap on one handle race.
  *   - The handle owns its workspace, allocated in alm_bm_create and sized by the
@@ -405,6 +406,19 @@ alm_bm_status alm_bm_batch_offsets(const alm_bm_batch* batch, int64_t* offsets);
  * Returns ALM_BM_OK when every instance met eps_kkt, else NOT_CONVERGED.        */
 alm_bm_status alm_bm_batch_solve(alm_bm_batch* batch, const alm_bm_options* opts, void* R, int32_t* r,
                                  double* y, alm_bm_result* results, int32_t* status, hipStream_t stream);
+/* Tile choice of a batch, the batched counterpart of alm_bm_autotune: for every
+ * width a batched solve can give an instance (4, 8, 16, ... up to rank_stride),
+ * times reps objective/gradient passes over all instances at that width with
+ * each tile variant and keeps the fastest; later alm_bm_batch_solve calls
+ * launch that variant for that width (untuned widths use variant 0).  The
+ * variants sum each row in a different order, so two handles tuned apart may
+ * round differently; solves on one handle stay deterministic.  widths, variants:
+ * host arrays of ALM_BM_BATCH_TUNE_MAX (nullable), receiving the table in
+ * increasing width; n_out: its length (nullable).  reps >= 1.  Overwrites the
+ * handle's scratch and its last objective pass; synchronises stream.          */
+#define ALM_BM_BATCH_TUNE_MAX 16
+alm_bm_status alm_bm_batch_autotune(alm_bm_batch* batch, int32_t reps, int32_t* widths, int32_t* variants,
+                                    int32_t* n_out, hipStream_t stream);
 
 /* Relative KKT measure of Sec. 6 at (RR^T, y) with lambda_min supplied by the
  * caller (host double); kkt_out: host array of 6 doubles

@@ -415,6 +415,17 @@ class Batch:
                                           sts.ctypes.data, _stream(stream)), "batch_solve")
         return st, sts.tolist(), [x.as_dict() for x in res], R, r.tolist(), y
 
+    def autotune(self, reps=3, stream=None):
+        """Time the tile variants for every width a solve can use
+        (alm_bm_batch_autotune); returns {width: variant}."""
+        cap = 16  # ALM_BM_BATCH_TUNE_MAX
+        ws = np.zeros(cap, dtype=np.int32)
+        vs = np.zeros(cap, dtype=np.int32)
+        n = C.c_int32(0)
+        check(lib.alm_bm_batch_autotune(self._h, int(reps), ws.ctypes.data, vs.ctypes.data, C.byref(n),
+                                        _stream(stream)), "batch_autotune")
+        return {int(ws[i]): int(vs[i]) for i in range(n.value)}
+
     def instance(self, q, R, y, r):
         """Instance q's factor (n_q x r_q view) and dual."""
         a, b = self.offsets[q], self.offsets[q + 1]

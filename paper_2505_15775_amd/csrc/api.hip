@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -1944,7 +1945,9 @@ struct alm_bm_batch {
   int32_t* c_gid[kNC] = {};
   int c_nb[kNC] = {};
   int c_w[kNC] = {};
+  int c_var[kNC] = {};              // tile variant of each class (from wvar)
   int nclass = 0;
+  std::map<int, int> wvar;          // width -> tile variant chosen by alm_bm_batch_autotune
   int32_t* a_inst = nullptr;        // blocks of every running instance (Lanczos)
   int64_t* a_lo = nullptr;
   int64_t* a_hi = nullptr;
@@ -2364,6 +2367,8 @@ static alm_bm_status batch_classes(alm_bm_batch* b, const std::vector<int>& w, c
     const size_t k = ci[c].size();
     b->c_nb[c] = (int)k;
     b->c_w[c] = widths[c];
+    const auto it = b->wvar.find(widths[c]);
+    b->c_var[c] = it == b->wvar.end() ? 0 : it->second;
     HIPCHK(hipMemcpyAsync(b->c_inst[c], ci[c].data(), k * sizeof(int32_t), hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(b->c_lo[c], cl[c].data(), k * sizeof(int64_t), hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(b->c_hi[c], ch[c].data(), k * sizeof(int64_t), hipMemcpyHostToDevice, st));
@@ -2407,14 +2412,15 @@ static void batch_enqueue_step(alm_bm_batch* b, T* R, const double* y, double si
   DevScalars* sc = p->sc_solve;
   V* Q = static_cast<V*>(p->Qbuf);
   for (int c = 0; c < b->nclass; ++c)
-    launch_upd_eval_diag<T>(d.n, b->c_w[c], 0, R, G, Q, y, d.b, sigma, p->Av, p->part, sc, refresh,
+    launch_upd_eval_diag<T>(d.n, b->c_w[c], b->c_var[c], R, G, Q, y, d.b, sigma, p->Av, p->part, sc, refresh,
                             batch_class_tab(b, c), b->c_nb[c], st);
   for (int c = 0; c < b->nclass; ++c)
-    launch_objgrad_diag<T>(cost_of<T>(p), b->c_w[c], 0, R, y, d.b, sigma, G, p->Av, p->part, sc, refresh,
+    launch_objgrad_diag<T>(cost_of<T>(p), b->c_w[c], b->c_var[c], R, y, d.b, sigma, G, p->Av, p->part, sc, refresh,
                            batch_class_tab(b, c), b->c_nb[c], st);
   launch_fin_objgrad(p->part, p->nblk, sc, sigma, 1, nullptr, st, p->tab, p->count);
   for (int c = 0; c < b->nclass; ++c)
-    launch_quadq_diag<T>(cost_of<T>(p), b->c_w[c], 0, G, Q, p->part_c2, sc, batch_class_tab(b, c), b->c_nb[c], st);
+    launch_quadq_diag<T>(cost_of<T>(p), b->c_w[c], b->c_var[c], G, Q, p->part_c2, sc, batch_class_tab(b, c),
+                         b->c_nb[c], st);
   launch_fin_step(p->part_c2, p->nblk, 1, sc, sigma, 0.0, 1, nullptr, nullptr, st, p->tab, p->count);
 }
 
@@ -2423,8 +2429,8 @@ template <typename T>
 static void batch_enqueue_objgrad(alm_bm_batch* b, const T* R, const double* y, double sigma, hipStream_t st) {
   alm_bm_problem* p = b->p;
   for (int c = 0; c < b->nclass; ++c)
-    launch_objgrad_diag<T>(cost_of<T>(p), b->c_w[c], 0, R, y, p->d.b, sigma, nullptr, p->Av, p->part, p->sc_api, 0,
-                           batch_class_tab(b, c), b->c_nb[c], st);
+    launch_objgrad_diag<T>(cost_of<T>(p), b->c_w[c], b->c_var[c], R, y, p->d.b, sigma, nullptr, p->Av, p->part,
+                           p->sc_api, 0, batch_class_tab(b, c), b->c_nb[c], st);
   launch_fin_objgrad(p->part, p->nblk, p->sc_api, sigma, 0, nullptr, st, p->tab, p->count);
 }
 
@@ -2467,6 +2473,11 @@ static alm_bm_status batch_solve_impl(alm_bm_batch* b, const alm_bm_options& o, 
   }
   STCHK(batch_restride<T>(b, R, zero64, rsv, xb, wv, r, st));
   GraphCache gc;
+  // The launch tables and the captured step depend only on the widths and the
+  // running set: both are rebuilt when either changed since they were made.
+  std::vector<int> tab_w, gr_w;
+  std::vector<int32_t> tab_active, gr_active;
+  int captures = 0;
   std::vector<int32_t> fl(2 * count);
   int nactive = count;
   for (int k = 0; k < o.max_outer && nactive > 0; ++k) {
@@ -2476,12 +2487,22 @@ static alm_bm_status batch_solve_impl(alm_bm_batch* b, const alm_bm_options& o, 
       tol_prev[q] = tolv[q];
     }
     // launch tables of this outer iteration's running instances, and the graph
-    STCHK(batch_classes(b, w, active, st));
-    gc.reset();
-    HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-    for (int u = 0; u < U; ++u) batch_enqueue_step<T>(b, R, y, sigma, G, refresh, st);
-    HIPCHK(hipStreamEndCapture(st, &gc.graph));
-    HIPCHK(hipGraphInstantiate(&gc.exec, gc.graph, nullptr, nullptr, 0));
+    const double ti = now_s();
+    if (w != tab_w || active != tab_active) {
+      STCHK(batch_classes(b, w, active, st));
+      tab_w = w;
+      tab_active = active;
+    }
+    if (!gc.exec || w != gr_w || active != gr_active) {
+      gc.reset();
+      HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+      for (int u = 0; u < U; ++u) batch_enqueue_step<T>(b, R, y, sigma, G, refresh, st);
+      HIPCHK(hipStreamEndCapture(st, &gc.graph));
+      HIPCHK(hipGraphInstantiate(&gc.exec, gc.graph, nullptr, nullptr, 0));
+      gr_w = w;
+      gr_active = active;
+      ++captures;
+    }
     HIPCHK(hipMemcpyAsync(b->tols_dev, tolv.data(), count * sizeof(double), hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(b->active_dev, active.data(), count * sizeof(int32_t), hipMemcpyHostToDevice, st));
     launch_inner_reset_batch(p->sc_solve, count, b->tols_dev, b->active_dev, o.max_inner, (int)o.step_rule,
@@ -2501,6 +2522,7 @@ static alm_bm_status batch_solve_impl(alm_bm_batch* b, const alm_bm_options& o, 
     }
     for (int q = 0; q < count; ++q)
       if (active[q]) res[q].inner_total += fl[2 * q + 1];
+    const double tinner = now_s() - ti;
     // w = y - sigma (A(RR^T) - b) for every instance
     launch_dual_batch(N, p->Av, p->d.b, y, p->ybuf, sigma, p->part_vec, p->sc_solve, b->bnorm_dev, p->tab, p->nblk,
                       count, st);
@@ -2554,6 +2576,8 @@ static alm_bm_status batch_solve_impl(alm_bm_batch* b, const alm_bm_options& o, 
           STCHK(batch_restride<T>(b, R, ob, os, nbv, ns, r, st));
           w = w2;
           STCHK(batch_classes(b, w, active, st));
+          tab_w = w;
+          tab_active = active;
         }
         for (int q = 0; q < count; ++q)
           if (expanded[q]) r[q] += 1;
@@ -2617,7 +2641,10 @@ static alm_bm_status batch_solve_impl(alm_bm_batch* b, const alm_bm_options& o, 
       }
     }
     if (o.verbose)
-      std::fprintf(stderr, "[almbm batch] k=%d active=%d t=%.2fs\n", k, nactive, now_s() - t0);
+      std::fprintf(stderr,
+                   "[almbm batch] k=%d active=%d t=%.2fs (inner %.3fs, %d graph launches, %d captures; "
+                   "lanczos %.3fs)\n",
+                   k, nactive, now_s() - t0, tinner, launched / U, captures, tlan + tlan2);
     if (o.time_limit_s > 0.0 && now_s() - t0 > o.time_limit_s) break;
   }
   // back to the caller's layout
@@ -2636,6 +2663,85 @@ static alm_bm_status batch_solve_impl(alm_bm_batch* b, const alm_bm_options& o, 
     if (status) status[q] = st_q[q];
   }
   return nactive == 0 ? ALM_BM_OK : ALM_BM_NOT_CONVERGED;
+}
+
+// Tile choice per width: every width a batched solve can give an instance
+// (pad_width of 1..rank_stride) is timed with all instances at that width,
+// one objective/gradient pass over the whole block table per repetition and
+// variant, on a zero factor in the handle's scratch (the gathers do not
+// depend on the values).
+template <typename T>
+static alm_bm_status batch_autotune_impl(alm_bm_batch* b, int reps, hipStream_t st) {
+  alm_bm_problem* p = b->p;
+  const int count = b->count;
+  const auto& d = p->d;
+  std::vector<int> widths;
+  for (int r = 1; r <= b->rs; ++r) {
+    const int w = pad_width(r, b->rs);
+    if (std::find(widths.begin(), widths.end(), w) == widths.end()) widths.push_back(w);
+  }
+  HIPCHK(hipMemsetAsync(p->Rtmp, 0, (size_t)d.n * b->rs * sizeof(T), st));
+  HIPCHK(hipMemsetAsync(p->ybuf, 0, (size_t)d.m * sizeof(double), st));
+  const T* R = static_cast<const T*>(p->Rtmp);
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  std::vector<int32_t> all(count, 1);
+  alm_bm_status s = ALM_BM_OK;
+  for (int w : widths) {
+    std::vector<int> wq(count, w);
+    b->wvar.erase(w);
+    s = batch_classes(b, wq, all, st);
+    if (s != ALM_BM_OK) break;
+    float best = INFINITY;
+    int bv = 0;
+    for (int v = 0; v <= 2; ++v) {
+      auto run = [&]() {
+        launch_objgrad_diag<T>(cost_of<T>(p), w, v, R, p->ybuf, d.b, 1.0, nullptr, p->Av, p->part, p->sc_api, 0,
+                               batch_class_tab(b, 0), b->c_nb[0], st);
+      };
+      run();  // warm
+      if (hipEventRecord(e0, st) != hipSuccess) s = fail(ALM_BM_ERR_HIP, "batch_autotune: event record");
+      for (int k = 0; k < reps && s == ALM_BM_OK; ++k) run();
+      if (s == ALM_BM_OK && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess))
+        s = fail(ALM_BM_ERR_HIP, "batch_autotune: event wait");
+      float ms = 0.f;
+      if (s == ALM_BM_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+        s = fail(ALM_BM_ERR_HIP, "batch_autotune: elapsed time");
+      if (s != ALM_BM_OK) break;
+      if (ms < best) {
+        best = ms;
+        bv = v;
+      }
+    }
+    if (s != ALM_BM_OK) break;
+    b->wvar[w] = bv;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  STCHK(s);
+  HIPCHK(hipGetLastError());
+  return ALM_BM_OK;
+}
+
+extern "C" alm_bm_status alm_bm_batch_autotune(alm_bm_batch* b, int32_t reps, int32_t* widths_out,
+                                               int32_t* variants_out, int32_t* n_out, hipStream_t st_user) {
+  if (!b) return fail(ALM_BM_ERR_INVALID_ARG, "batch_autotune: null handle");
+  if (reps < 1) return fail(ALM_BM_ERR_INVALID_ARG, "batch_autotune: reps < 1");
+  HIPCHK(hipStreamSynchronize(st_user));
+  hipStream_t st = b->p->ss;
+  STCHK(with_storage(b->p->d.precision, [&]<typename T>() { return batch_autotune_impl<T>(b, reps, st); }));
+  HIPCHK(hipStreamSynchronize(st));
+  int k = 0;
+  for (const auto& [w, v] : b->wvar) {
+    if (k < ALM_BM_BATCH_TUNE_MAX) {
+      if (widths_out) widths_out[k] = w;
+      if (variants_out) variants_out[k] = v;
+    }
+    ++k;
+  }
+  if (n_out) *n_out = std::min(k, ALM_BM_BATCH_TUNE_MAX);
+  return ALM_BM_OK;
 }
 
 extern "C" alm_bm_status alm_bm_batch_solve(alm_bm_batch* b, const alm_bm_options* opts, void* R, int32_t* r,

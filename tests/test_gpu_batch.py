@@ -120,3 +120,32 @@ def test_batch_uneven_recipe_32_instances():
     batch.close()
     for p in probs:
         p.close()
+
+
+def test_batch_graph_reuse_and_tuned_tiles():
+    """A batch with tuned tiles (alm_bm_batch_autotune): the table covers every
+    width the stride allows, two solves on the tuned handle agree bitwise, and
+    the tuned solve converges to the untuned one's objectives (the variants only
+    reorder row sums).  The captured step is reused while the running set and
+    widths are unchanged, which the same-handle repeat also exercises."""
+    insts = _instances()[2:8]
+    m = _almbm()
+    factors = [gen.init_factor(g.n, r, 2) for g, r in insts]
+    opts = dict(eps_kkt=1e-6, max_outer=300)
+    plain = m.Batch(_problems(insts, prec="f64"), rank_stride=48)
+    st0, sts0, res0, _, _, _ = plain.solve(factors, **opts)
+    plain.close()
+    assert st0 == 0
+    tuned = m.Batch(_problems(insts, prec="f64"), rank_stride=48)
+    table = tuned.autotune(reps=2)
+    print(f"tuned variants per width: {table}")
+    assert sorted(table) == [4, 8, 16, 32, 48] and all(v in (0, 1, 2) for v in table.values())
+    outs = []
+    for _ in range(2):
+        st, sts, res, R, ranks, y = tuned.solve(factors, **opts)
+        assert st == 0 and all(s == 0 for s in sts)
+        outs.append((R.cpu().numpy().copy(), y.cpu().numpy().copy(), ranks, [x["pobj"] for x in res]))
+    tuned.close()
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+    for q in range(len(insts)):
+        assert abs(outs[0][3][q] - res0[q]["pobj"]) <= 2e-6 * abs(res0[q]["pobj"])

@@ -138,6 +138,7 @@ def test_set_tiles_rejects_bad_values_without_device():
     from paper_2505_15775_amd import _lib
 
     assert _lib.lib.alm_bm_set_tiles(None, 0, 0) == -1
+    assert _lib.lib.alm_bm_batch_autotune(None, 3, None, None, None, None) == -1
 
 
 def _pairs(q):
