@@ -180,7 +180,7 @@ def per_outer_rows(prob, y, steps):
             "lanczos_ms_total": 1000.0 * tl, "lanczos_ms_per_step": 1000.0 * tl / max(1, iters)}
 
 
-def batch_leg(count, eps, sigma, prec, seed=3, loop=True, tune=True):
+def batch_leg(count, eps, sigma, prec, seed=3, loop=True, tune=True, inner="lbfgs"):
     """Uneven MaxCut instances (n log-uniform in [1e3, 2e5], average degree
     uniform in [4, 32], +-1 weights, r in {8, 16}) solved together by one
     batched solve, then one by one with the same options."""
@@ -193,8 +193,9 @@ def batch_leg(count, eps, sigma, prec, seed=3, loop=True, tune=True):
     sum_n = sum(g.n for g, _ in insts)
     sum_nnz = sum(2 * g.m_edges for g, _ in insts)
     log(f"[bench] batch: {count} instances, sum n {sum_n}, sum nnz {sum_nnz}")
+    lbm = 3 if inner == "lbfgs" else 0
     probs = [almbm.Problem.maxcut(g.n, g.ei, g.ej, g.w, precision=prec, r_max=64, lanczos_kmax=40, device="cuda:0",
-                                  validate=False) for g, _ in insts]
+                                  validate=False, lbfgs_memory_max=lbm) for g, _ in insts]
     batch = almbm.Batch(probs, rank_stride=64)
     table, t_tune = None, 0.0
     if tune:
@@ -204,6 +205,8 @@ def batch_leg(count, eps, sigma, prec, seed=3, loop=True, tune=True):
         log(f"[bench] batch: tile variants per width {table} (tuned in {t_tune:.2f}s)")
     factors = [gen.init_factor(g.n, r, 1) for g, r in insts]
     opts = dict(eps_kkt=eps, sigma=sigma, max_outer=300)
+    if inner == "lbfgs":
+        opts.update(inner_solver=1, lbfgs_memory=3, max_inner=100)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     st, sts, res, _, ranks, _ = batch.solve(factors, verbose=1, **opts)
@@ -227,7 +230,7 @@ def batch_leg(count, eps, sigma, prec, seed=3, loop=True, tune=True):
     for p in probs:
         p.close()
     return {"instances": count, "sum_n": sum_n, "sum_nnz": sum_nnz, "precision": prec, "eps_kkt": eps,
-            "sigma": sigma, "batched_s": round(tb, 2), "batched_converged": int(sum(s == 0 for s in sts)),
+            "sigma": sigma, "inner_solver": inner, "max_inner": opts.get("max_inner", 500), "batched_s": round(tb, 2), "batched_converged": int(sum(s == 0 for s in sts)),
             "loop_s": round(tl, 2) if loop else None, "loop_converged": nconv if loop else None,
             "speedup": round(tl / tb, 3) if loop else None,
             "max_outer_batched": int(max(x["outer"] for x in res)),
@@ -587,6 +590,8 @@ def main():
     ap.add_argument("--batch-eps", type=float, default=1e-4)
     ap.add_argument("--batch-no-loop", action="store_true", help="skip the per-instance loop of the batch leg")
     ap.add_argument("--batch-no-tune", action="store_true", help="batch leg with the default tiles")
+    ap.add_argument("--batch-inner", choices=["lbfgs", "gd"], default="lbfgs",
+                    help="subproblem solver of the batch leg (both the batch and the loop)")
     ap.add_argument("--kernels", action="store_true", help="also time the edge-family and warm-start kernels")
     ap.add_argument("--completion", action="store_true", help="also the matrix completion instances of Table 2")
     ap.add_argument("--completion-sigma", type=float, default=0.03, help="penalty for the matrix completion solves")
@@ -669,7 +674,7 @@ def main():
         solves = solve_legs(g, args)
 
     batch = batch_leg(args.batch, args.batch_eps, args.sigma, "f64", loop=not args.batch_no_loop,
-                      tune=not args.batch_no_tune) if args.batch > 0 else None
+                      tune=not args.batch_no_tune, inner=args.batch_inner) if args.batch > 0 else None
     other = kernels_leg(g) if args.kernels else None
     completion = completion_leg(sigma=args.completion_sigma) if args.completion else None
     skewed = rmat_leg(args.rmat) if args.rmat else None

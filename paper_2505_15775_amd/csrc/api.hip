@@ -574,7 +574,8 @@ extern "C" alm_bm_status alm_bm_create(const alm_bm_problem_desc* desc, hipStrea
     CK(dalloc_t(p, &p->gpart, (size_t)p->lnb * ne));
   }
   if (d.lbfgs_memory_max > 0) {
-    // ring elements: double for FP64 handles, bfloat16 otherwise (RingT)
+    // ring elements: double for FP64 handles, bfloat16 otherwise (RingT); a
+    // batch replaces the single state by one per instance
     const size_t lbe = d.precision == ALM_BM_F64 ? sizeof(double) : sizeof(bf16);
     p->lb_stride = ((long)n * d.r_max + 63) / 64 * 64;
     const size_t bytes = (size_t)(d.lbfgs_memory_max + 1) * (size_t)p->lb_stride * lbe;
@@ -651,7 +652,7 @@ static void enqueue_inner_step(alm_bm_problem* p, int r, T* R, const double* y, 
     if (lb.s) {
       // L-BFGS: the direction E = H G and its line-search totals replace G's;
       // the line-search product gathers E in the ring type
-      launch_lbfgs_dots<T>((long)d.n * r, G, lb, p->part, p->nblk, sc, st);
+      launch_lbfgs_dots<T>((long)d.n * r, r, G, lb, p->part, p->nblk, sc, st);
       launch_fin_lbfgs(p->part, p->nblk, sc, lb.s, st);
       launch_lbfgs_combine<T>(d.n, r, p->variant, R, G, y, d.b, sigma, p->Av, lb, p->part, sc, p->nblk, st);
       launch_fin_lsdir(p->part, p->nblk, sc, lb.s, st);
@@ -1993,7 +1994,7 @@ extern "C" alm_bm_status alm_bm_batch_create(int32_t count, const alm_bm_problem
   *out = nullptr;
   const alm_bm_precision prec = descs[0].precision;
   long N = 0, NNZ = 0;
-  int kmax_all = 0;
+  int kmax_all = 0, lbm_all = 0;
   for (int q = 0; q < count; ++q) {
     const auto& d = descs[q];
     if (d.cons_kind != ALM_BM_CONS_DIAG || d.m != d.n || d.j_coef != 0.0)
@@ -2004,6 +2005,9 @@ extern "C" alm_bm_status alm_bm_batch_create(int32_t count, const alm_bm_problem
     N += d.n;
     NNZ += d.nnz;
     kmax_all = std::max(kmax_all, d.lanczos_kmax);
+    if (d.lbfgs_memory_max < 0 || d.lbfgs_memory_max > kMaxLbfgs)
+      return fail(ALM_BM_ERR_INVALID_ARG, "batch_create: lbfgs_memory_max must be in 0..8");
+    lbm_all = std::max(lbm_all, d.lbfgs_memory_max);
   }
   if (N > INT32_MAX || NNZ > INT32_MAX) return fail(ALM_BM_ERR_UNSUPPORTED, "batch_create: totals exceed int32");
   if (kmax_all < 1) return fail(ALM_BM_ERR_INVALID_ARG, "batch_create: lanczos_kmax must be >= 1");
@@ -2106,10 +2110,11 @@ extern "C" alm_bm_status alm_bm_batch_create(int32_t count, const alm_bm_problem
   sd.lanczos_kmax = kmax_all;
   sd.validate = 0;
   sd.rank_block_max = 0;
-  sd.lbfgs_memory_max = 0;
+  sd.lbfgs_memory_max = lbm_all;  // rings of (sum n) x rank_stride elements per slot
   sd.hub_min_degree = -1;  // per-instance row widths: the hub sums (one stride r) do not apply
   BK(alm_bm_create(&sd, st, &b->p));
   alm_bm_problem* p = b->p;
+  if (lbm_all > 0) BK(balloc(b, (void**)&p->lbs, (size_t)count * sizeof(LbfgsState)));
   // ---- block table: instance q gets ceil(n_q / rows_per_block) blocks
   const long rpb = std::max<long>(256, (N + 8191) / 8192);
   std::vector<int32_t> binst, iblo(count), ibhi(count);
@@ -2411,16 +2416,33 @@ static void batch_enqueue_step(alm_bm_batch* b, T* R, const double* y, double si
   const auto& d = p->d;
   DevScalars* sc = p->sc_solve;
   V* Q = static_cast<V*>(p->Qbuf);
+  using S = RingT<T>;
+  const LbfgsRing<S> lb = lbfgs_ring<S>(p);  // empty: gradient descent
   for (int c = 0; c < b->nclass; ++c)
     launch_upd_eval_diag<T>(d.n, b->c_w[c], b->c_var[c], R, G, Q, y, d.b, sigma, p->Av, p->part, sc, refresh,
-                            batch_class_tab(b, c), b->c_nb[c], st);
+                            batch_class_tab(b, c), b->c_nb[c], st, lb);
   for (int c = 0; c < b->nclass; ++c)
     launch_objgrad_diag<T>(cost_of<T>(p), b->c_w[c], b->c_var[c], R, y, d.b, sigma, G, p->Av, p->part, sc, refresh,
-                           batch_class_tab(b, c), b->c_nb[c], st);
+                           batch_class_tab(b, c), b->c_nb[c], st, lb);
   launch_fin_objgrad(p->part, p->nblk, sc, sigma, 1, nullptr, st, p->tab, p->count);
-  for (int c = 0; c < b->nclass; ++c)
-    launch_quadq_diag<T>(cost_of<T>(p), b->c_w[c], b->c_var[c], G, Q, p->part_c2, sc, batch_class_tab(b, c),
-                         b->c_nb[c], st);
+  if (lb.s) {
+    // L-BFGS per instance: states, ring regions and partial slots follow the
+    // block table, so one launch per width class covers every instance
+    for (int c = 0; c < b->nclass; ++c)
+      launch_lbfgs_dots<T>(d.n, b->c_w[c], G, lb, p->part, b->c_nb[c], sc, st, batch_class_tab(b, c));
+    launch_fin_lbfgs(p->part, p->nblk, sc, lb.s, st, p->tab, p->count);
+    for (int c = 0; c < b->nclass; ++c)
+      launch_lbfgs_combine<T>(d.n, b->c_w[c], b->c_var[c], R, G, y, d.b, sigma, p->Av, lb, p->part, sc,
+                              b->c_nb[c], st, batch_class_tab(b, c));
+    launch_fin_lsdir(p->part, p->nblk, sc, lb.s, st, p->tab, p->count);
+    for (int c = 0; c < b->nclass; ++c)
+      launch_quadq_diag<S>(cost_of<S>(p), b->c_w[c], b->c_var[c], lb.e, Q, p->part_c2, sc, batch_class_tab(b, c),
+                           b->c_nb[c], st, lb);
+  } else {
+    for (int c = 0; c < b->nclass; ++c)
+      launch_quadq_diag<T>(cost_of<T>(p), b->c_w[c], b->c_var[c], G, Q, p->part_c2, sc, batch_class_tab(b, c),
+                           b->c_nb[c], st);
+  }
   launch_fin_step(p->part_c2, p->nblk, 1, sc, sigma, 0.0, 1, nullptr, nullptr, st, p->tab, p->count);
 }
 
@@ -2507,6 +2529,7 @@ static alm_bm_status batch_solve_impl(alm_bm_batch* b, const alm_bm_options& o, 
     HIPCHK(hipMemcpyAsync(b->active_dev, active.data(), count * sizeof(int32_t), hipMemcpyHostToDevice, st));
     launch_inner_reset_batch(p->sc_solve, count, b->tols_dev, b->active_dev, o.max_inner, (int)o.step_rule,
                              o.eta_fixed, st);
+    if (p->lb_m > 0) launch_lbfgs_reset(p->lbs, p->lb_m, st, count);  // empty memories
     int launched = 0;
     while (true) {
       HIPCHK(hipGraphLaunch(gc.exec, st));
@@ -2755,11 +2778,19 @@ extern "C" alm_bm_status alm_bm_batch_solve(alm_bm_batch* b, const alm_bm_option
   if (o.sigma_growth != 1.0)
     return fail(ALM_BM_ERR_UNSUPPORTED, "batch_solve: the penalty schedule (sigma_growth) is for single solves");
   if (o.rank_block != 1) return fail(ALM_BM_ERR_UNSUPPORTED, "batch_solve: rank_block > 1 is for single solves");
-  if (o.inner_solver != ALM_BM_INNER_GD)
-    return fail(ALM_BM_ERR_UNSUPPORTED, "batch_solve: the L-BFGS inner solver is for single solves");
+  int lb_m = 0;
+  if (o.inner_solver == ALM_BM_INNER_LBFGS) {
+    if (o.lbfgs_memory < 1 || o.lbfgs_memory > b->p->d.lbfgs_memory_max)
+      return fail(ALM_BM_ERR_INVALID_ARG, "batch_solve: lbfgs_memory must be in 1..the largest lbfgs_memory_max of "
+                                          "the instances (" + std::to_string(b->p->d.lbfgs_memory_max) + ")");
+    lb_m = o.lbfgs_memory;
+  } else if (o.inner_solver != ALM_BM_INNER_GD) {
+    return fail(ALM_BM_ERR_INVALID_ARG, "batch_solve: unknown inner_solver");
+  }
   if (o.resume_outer != 0) return fail(ALM_BM_ERR_UNSUPPORTED, "batch_solve: resume is for single solves");
   HIPCHK(hipStreamSynchronize(st_user));
   hipStream_t st = b->p->ss;
+  InnerScope inner_scope(b->p, lb_m);
   alm_bm_status s = with_storage(b->p->d.precision, [&]<typename T>() {
     return batch_solve_impl<T>(b, o, static_cast<T*>(R), r, y, results, status, st);
   });

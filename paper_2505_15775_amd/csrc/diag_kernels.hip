@@ -28,11 +28,12 @@ k_objgrad_diag(Cost<typename Acc<T>::type> C, int r, const T* __restrict__ R,
   // inside the inner loop this full pass runs only on refresh iterations
   if (sc && refresh_every > 1 && (sc->iter % refresh_every) != 0) return;
   // L-BFGS: y_k = G_new - G_old into the current y slot (not on the first step)
-  RingT<T>* __restrict__ yk = (lb.s && sc && sc->iter > 0) ? lb.y + (long)lb.s->cur * lb.stride : nullptr;
+  const long xb = row_base(tab, ch.inst);
+  RingT<T>* __restrict__ yk =
+      (lb.s && sc && sc->iter > 0) ? lb.y + (long)lb.s[ch.inst].cur * lb.stride + xb : nullptr;
   constexpr int RPB = kBlock / LPR;
   const int lane = threadIdx.x % LPR;
   const int slot = threadIdx.x / LPR;
-  const long xb = row_base(tab, ch.inst);
   R += xb;
   if (G) G += xb;
   SplitAcc<NUM_P, LPR> acc;
@@ -136,7 +137,7 @@ k_quadq_diag(Cost<typename Acc<T>::type> C, int r, const T* __restrict__ G, type
   using V = typename Acc<T>::type;
   const Rows ch = rows_of(C.n, tab);
   if (sc_base && sc_base[ch.inst].flag) return;
-  if (lb.s) G = lb.e + (long)lb.s->cur * lb.stride;  // L-BFGS: the product of the direction E
+  if (lb.s) G = lb.e + (long)lb.s[ch.inst].cur * lb.stride;  // L-BFGS: the product of the direction E
   constexpr int RPB = kBlock / LPR;
   const int lane = threadIdx.x % LPR;
   const int slot = threadIdx.x / LPR;
@@ -182,14 +183,14 @@ k_upd_eval_diag(long n, int r, T* __restrict__ R, T* __restrict__ G, const typen
   // the step is R <- R - t D with D = G (gradient descent) or D = E (L-BFGS,
   // which also writes y_k = G_new - G_old into the current y slot)
   using S = RingT<T>;
-  const S* __restrict__ D = lb.s ? lb.e + (long)lb.s->cur * lb.stride : nullptr;
-  S* __restrict__ yk = lb.s ? lb.y + (long)lb.s->cur * lb.stride : nullptr;
+  const long xb = row_base(tab, ch.inst);
+  const S* __restrict__ D = lb.s ? lb.e + (long)lb.s[ch.inst].cur * lb.stride + xb : nullptr;
+  S* __restrict__ yk = lb.s ? lb.y + (long)lb.s[ch.inst].cur * lb.stride + xb : nullptr;
   const bool update_only = refresh_every <= 1 || (e % refresh_every) == 0;
   const V t = static_cast<V>(sc->t);
   constexpr int RPB = kBlock / LPR;
   const int lane = threadIdx.x % LPR;
   const int slot = threadIdx.x / LPR;
-  const long xb = row_base(tab, ch.inst);
   R += xb;
   G += xb;
   Q += xb;

@@ -29,22 +29,26 @@ void launch_upd_eval_diag(long n, int r, int variant, T* R, T* G, const typename
                           int refresh_every, const BlockTab& tab, int nblk, hipStream_t st,
                           const LbfgsRing<RingT<T>>& lb = LbfgsRing<RingT<T>>{});
 // L-BFGS steps (lbfgs_kernels.hip).  Reset at the start of a subproblem.
-void launch_lbfgs_reset(LbfgsState* s, int m, hipStream_t st);
+// Empty memories of m pairs for `count` instances (states s[0..count)).
+void launch_lbfgs_reset(LbfgsState* s, int m, hipStream_t st, int count = 1);
 // Inner products of the new gradient G and of y_k with the stored vectors
-// (n*r elements each), per block of nb blocks into part[nb][kLbfgsDots].
+// (len = n*r elements each without a table; with one, the rows of each block
+// at width r), per block of nb blocks into part[slot][kLbfgsDots].
 template <typename T>
-void launch_lbfgs_dots(long len, const T* G, const LbfgsRing<RingT<T>>& lb, double* part, int nb,
-                       const DevScalars* sc, hipStream_t st);
-// Pair update and the coefficients of the next direction (one block).
-void launch_fin_lbfgs(const double* part, int nb, const DevScalars* sc, LbfgsState* s, hipStream_t st);
+void launch_lbfgs_dots(long len, int r, const T* G, const LbfgsRing<RingT<T>>& lb, double* part, int nb,
+                       const DevScalars* sc, hipStream_t st, const BlockTab& tab = BlockTab{});
+// Pair update and the coefficients of the next direction (one block per instance).
+void launch_fin_lbfgs(const double* part, int nb, const DevScalars* sc, LbfgsState* s, hipStream_t st,
+                      const BlockTab& tab = BlockTab{}, int count = 1);
 // E = cg G + sum (ce E_a + cy y_a) into the current slot, and the quartic's
 // direction-dependent partial sums along -E (NUM_P per block).
 template <typename T>
 void launch_lbfgs_combine(long n, int r, int variant, const T* R, const T* G, const double* y, const double* b,
                           double sigma, const double* Av, const LbfgsRing<RingT<T>>& lb, double* part,
-                          const DevScalars* sc, int nblk, hipStream_t st);
-// Direction-dependent totals of the quartic from the combine partials.
-void launch_fin_lsdir(const double* part, int nb, DevScalars* sc, LbfgsState* s, hipStream_t st);
+                          const DevScalars* sc, int nblk, hipStream_t st, const BlockTab& tab = BlockTab{});
+// Direction-dependent totals of the quartic from the combine partials (one block per instance).
+void launch_fin_lsdir(const double* part, int nb, DevScalars* sc, LbfgsState* s, hipStream_t st,
+                      const BlockTab& tab = BlockTab{}, int count = 1);
 template <typename T>
 void launch_quad_diag(const Cost<typename Acc<T>::type>& C, int r, int variant, const T* G, double* part,
                       const DevScalars* sc, int nblk, hipStream_t st);

@@ -20,8 +20,10 @@ namespace almbm {
 
 // ---- reset -----------------------------------------------------------------------
 
+// One block per instance (state s + blockIdx.x).
 __global__ void k_lbfgs_reset(LbfgsState* s, int m) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  if (threadIdx.x != 0) return;
+  s += blockIdx.x;
   s->m = m;
   s->cnt = 0;
   s->cur = 0;
@@ -109,15 +111,28 @@ __device__ __forceinline__ void dots_chunk(DotAcc<typename Acc<T>::type>& A, lon
   }
 }
 
+// Without a table the grid strides over all len elements.  With a table each
+// block takes the elements of its rows, [xbase + lo r, xbase + hi r) of its
+// instance (stored at width r), with the instance's own state and stop flag.
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
-k_lbfgs_dots(long len, const T* __restrict__ G, LbfgsRing<RingT<T>> lb, double* __restrict__ part,
-             const DevScalars* __restrict__ sc) {
+k_lbfgs_dots(long len, int r, const T* __restrict__ G, LbfgsRing<RingT<T>> lb, double* __restrict__ part,
+             const DevScalars* __restrict__ sc_base, BlockTab tab) {
   using V = typename Acc<T>::type;
   using R = RingT<T>;
   constexpr int N = FlatVec<T>::N;
-  if (sc->flag) return;
-  const LbfgsState* S = lb.s;
+  long a = 0, e = len, t0 = (long)blockIdx.x * kBlock + threadIdx.x, tstride = (long)gridDim.x * kBlock;
+  int inst = 0;
+  if (tab.inst) {
+    inst = tab.inst[blockIdx.x];
+    const long xb = row_base(tab, inst);
+    a = xb + (long)tab.lo[blockIdx.x] * r;
+    e = xb + (long)tab.hi[blockIdx.x] * r;
+    t0 = threadIdx.x;
+    tstride = kBlock;
+  }
+  if (sc_base[inst].flag) return;
+  const LbfgsState* S = lb.s + inst;
   const int cnt = S->cnt;
   const bool have = S->have != 0;
   const R* yk = lb.y + (long)S->cur * lb.stride;
@@ -135,12 +150,14 @@ k_lbfgs_dots(long len, const T* __restrict__ G, LbfgsRing<RingT<T>> lb, double* 
   for (int a = 0; a < kLbfgsSlots; ++a) A.gE[a] = A.gY[a] = A.kE[a] = A.kY[a] = V(0);
 #pragma unroll
   for (int a = 0; a < kMaxLbfgs; ++a) A.eY[a] = V(0);
-  const long nvec = len / N;
-  const long stride = (long)gridDim.x * kBlock;
-  for (long q = (long)blockIdx.x * kBlock + threadIdx.x; q < nvec; q += stride)
-    dots_chunk<T, N>(A, q * N, G, yk, ek, ea, ya, cnt, have);
-  if (blockIdx.x == 0 && threadIdx.x == 0)  // tail of len % N elements
-    for (long idx = nvec * N; idx < len; ++idx) dots_chunk<T, 1>(A, idx, G, yk, ek, ea, ya, cnt, have);
+  // element-wise head up to N-element alignment, N-element chunks, element-wise tail
+  const long pad = (N - a % N) % N;
+  const long a_al = a + pad < e ? a + pad : e;
+  for (long idx = a + t0; idx < a_al; idx += tstride) dots_chunk<T, 1>(A, idx, G, yk, ek, ea, ya, cnt, have);
+  const long nvec = (e - a_al) / N;
+  for (long q = t0; q < nvec; q += tstride) dots_chunk<T, N>(A, a_al + q * N, G, yk, ek, ea, ya, cnt, have);
+  for (long idx = a_al + nvec * N + t0; idx < e; idx += tstride)
+    dots_chunk<T, 1>(A, idx, G, yk, ek, ea, ya, cnt, have);
   double acc[kLbfgsDots];
 #pragma unroll
   for (int a = 0; a < kLbfgsSlots; ++a) {
@@ -150,19 +167,25 @@ k_lbfgs_dots(long len, const T* __restrict__ G, LbfgsRing<RingT<T>> lb, double* 
     acc[3 * kLbfgsSlots + a] = (double)A.kY[a];
     acc[4 * kLbfgsSlots + a] = a < kMaxLbfgs ? (double)A.eY[a] : 0.0;
   }
-  block_sum_store<kLbfgsDots>(acc, part + (long)blockIdx.x * kLbfgsDots);
+  block_sum_store<kLbfgsDots>(acc, part + part_slot(tab) * kLbfgsDots);
 }
 
 // ---- pair update and the two-loop recursion on coefficients ----------------------
 
+// One block per instance (blockIdx.x; a single instance without a table).
 __global__ void __launch_bounds__(kBlock)
-k_fin_lbfgs(const double* __restrict__ part, int nb, const DevScalars* __restrict__ sc, LbfgsState* __restrict__ S) {
+k_fin_lbfgs(const double* __restrict__ part, int nb, const DevScalars* __restrict__ sc_base,
+            LbfgsState* __restrict__ S_base, BlockTab tab) {
+  const DevScalars* sc = sc_base + blockIdx.x;
+  LbfgsState* S = S_base + blockIdx.x;
   if (sc->flag) return;
-  // fixed-order totals: thread t sums blocks t, t + kBlock, ..., then the block tree
+  int b0, b1;
+  inst_blocks(tab, blockIdx.x, nb, b0, b1);
+  // fixed-order totals: thread t sums blocks b0 + t, b0 + t + kBlock, ..., then the block tree
   double acc[kLbfgsDots];
 #pragma unroll
   for (int k = 0; k < kLbfgsDots; ++k) acc[k] = 0.0;
-  for (int bi = threadIdx.x; bi < nb; bi += kBlock)
+  for (int bi = b0 + threadIdx.x; bi < b1; bi += kBlock)
 #pragma unroll
     for (int k = 0; k < kLbfgsDots; ++k) acc[k] += part[(long)bi * kLbfgsDots + k];
   __shared__ double tot[kLbfgsDots];
@@ -294,20 +317,23 @@ template <typename T, int LPR, int VEC, bool FULL>
 __global__ void __launch_bounds__(kBlock)
 k_lbfgs_combine(long n, int r, const T* __restrict__ R, const T* __restrict__ G, const double* __restrict__ y,
                 const double* __restrict__ b, double sigma, const double* __restrict__ Av, LbfgsRing<RingT<T>> lb,
-                double* __restrict__ part, const DevScalars* __restrict__ sc) {
+                double* __restrict__ part, const DevScalars* __restrict__ sc_base, BlockTab tab) {
   using V = typename Acc<T>::type;
   using RS = RingT<T>;
-  if (sc->flag) return;
-  const LbfgsState* S = lb.s;
+  const Rows ch = rows_of(n, tab);
+  if (sc_base[ch.inst].flag) return;
+  const LbfgsState* S = lb.s + ch.inst;
   const int c = S->cnt;
   const V cg = static_cast<V>(S->cg);
-  RS* __restrict__ E = lb.e + (long)S->cur * lb.stride;
+  const long xb = row_base(tab, ch.inst);
+  R += xb;
+  G += xb;
+  RS* __restrict__ E = lb.e + (long)S->cur * lb.stride + xb;
   constexpr int RPB = kBlock / LPR;
   const int lane = threadIdx.x % LPR;
   const int slot = threadIdx.x / LPR;
   SplitAcc<NUM_P, LPR> acc;
   acc.zero();
-  const RowChunk ch = row_chunk(n);
   for (long base = ch.lo; base < ch.hi; base += RPB) {
     const long i = base + slot;
     if (i >= ch.hi) break;
@@ -317,7 +343,7 @@ k_lbfgs_combine(long n, int r, const T* __restrict__ R, const T* __restrict__ G,
 #pragma unroll
     for (int v = 0; v < VEC; ++v) e[v] = cg * gi[v];
     for (int a = 0; a < c; ++a) {
-      const long off = (long)S->ord[a] * lb.stride + i * r;
+      const long off = (long)S->ord[a] * lb.stride + xb + i * r;
       const V ca = static_cast<V>(S->ce[a]), cb = static_cast<V>(S->cy[a]);
       V ev[VEC], yv[VEC];
       load_frag<RS, VEC, FULL>(lb.e + off, lane, r, ev);
@@ -354,18 +380,23 @@ k_lbfgs_combine(long n, int r, const T* __restrict__ R, const T* __restrict__ G,
     acc.add(lane, P_A2A2, a2 * a2);
     acc.add(lane, P_RG, (double)re);
   }
-  acc.block_store(lane, part + (long)blockIdx.x * NUM_P);
+  acc.block_store(lane, part + part_slot(tab) * NUM_P);
 }
 
 __global__ void __launch_bounds__(kBlock)
-k_fin_lsdir(const double* __restrict__ part, int nb, DevScalars* __restrict__ sc, LbfgsState* __restrict__ S) {
+k_fin_lsdir(const double* __restrict__ part, int nb, DevScalars* __restrict__ sc_base, LbfgsState* __restrict__ S_base,
+            BlockTab tab) {
+  DevScalars* sc = sc_base + blockIdx.x;
+  LbfgsState* S = S_base + blockIdx.x;
   if (sc->flag) return;
+  int b0, b1;
+  inst_blocks(tab, blockIdx.x, nb, b0, b1);
   constexpr int K = 10;
   const int sl[K] = {P_GG, P_GP, P_YA1, P_YA2, P_EA1, P_EA2, P_A1A1, P_A1A2, P_A2A2, P_RG};
   double acc[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) acc[k] = 0.0;
-  for (int bi = threadIdx.x; bi < nb; bi += kBlock)
+  for (int bi = b0 + threadIdx.x; bi < b1; bi += kBlock)
 #pragma unroll
     for (int k = 0; k < K; ++k) acc[k] += part[(long)bi * NUM_P + sl[k]];
   __shared__ double tot[K];
@@ -378,49 +409,51 @@ k_fin_lsdir(const double* __restrict__ part, int nb, DevScalars* __restrict__ sc
 
 // ---- launchers ---------------------------------------------------------------------
 
-void launch_lbfgs_reset(LbfgsState* s, int m, hipStream_t st) {
-  hipLaunchKernelGGL(k_lbfgs_reset, dim3(1), dim3(64), 0, st, s, m);
+void launch_lbfgs_reset(LbfgsState* s, int m, hipStream_t st, int count) {
+  hipLaunchKernelGGL(k_lbfgs_reset, dim3(count), dim3(64), 0, st, s, m);
 }
 
 template <typename T>
-void launch_lbfgs_dots(long len, const T* G, const LbfgsRing<RingT<T>>& lb, double* part, int nb,
-                       const DevScalars* sc, hipStream_t st) {
-  hipLaunchKernelGGL((k_lbfgs_dots<T>), dim3(nb), dim3(kBlock), 0, st, len, G, lb, part, sc);
+void launch_lbfgs_dots(long len, int r, const T* G, const LbfgsRing<RingT<T>>& lb, double* part, int nb,
+                       const DevScalars* sc, hipStream_t st, const BlockTab& tab) {
+  hipLaunchKernelGGL((k_lbfgs_dots<T>), dim3(nb), dim3(kBlock), 0, st, len, r, G, lb, part, sc, tab);
 }
 
-void launch_fin_lbfgs(const double* part, int nb, const DevScalars* sc, LbfgsState* s, hipStream_t st) {
-  hipLaunchKernelGGL(k_fin_lbfgs, dim3(1), dim3(kBlock), 0, st, part, nb, sc, s);
+void launch_fin_lbfgs(const double* part, int nb, const DevScalars* sc, LbfgsState* s, hipStream_t st,
+                      const BlockTab& tab, int count) {
+  hipLaunchKernelGGL(k_fin_lbfgs, dim3(count), dim3(kBlock), 0, st, part, nb, sc, s, tab);
 }
 
 template <typename T, int LPR, int VEC>
 static void launch_combine_cfg(long n, int r, const T* R, const T* G, const double* y, const double* b, double sigma,
                                const double* Av, const LbfgsRing<RingT<T>>& lb, double* part,
-                               const DevScalars* sc, int nblk, hipStream_t st) {
+                               const DevScalars* sc, int nblk, hipStream_t st, const BlockTab& tab) {
   if (r == LPR * VEC)
     hipLaunchKernelGGL((k_lbfgs_combine<T, LPR, VEC, true>), dim3(nblk), dim3(kBlock), 0, st, n, r, R, G, y, b,
-                       sigma, Av, lb, part, sc);
+                       sigma, Av, lb, part, sc, tab);
   else
     hipLaunchKernelGGL((k_lbfgs_combine<T, LPR, VEC, false>), dim3(nblk), dim3(kBlock), 0, st, n, r, R, G, y, b,
-                       sigma, Av, lb, part, sc);
+                       sigma, Av, lb, part, sc, tab);
 }
 
 template <typename T>
 void launch_lbfgs_combine(long n, int r, int variant, const T* R, const T* G, const double* y, const double* b,
                           double sigma, const double* Av, const LbfgsRing<RingT<T>>& lb, double* part,
-                          const DevScalars* sc, int nblk, hipStream_t st) {
-  ALMBM_DISPATCH_DIAG(T, launch_combine_cfg, n, r, R, G, y, b, sigma, Av, lb, part, sc, nblk, st);
+                          const DevScalars* sc, int nblk, hipStream_t st, const BlockTab& tab) {
+  ALMBM_DISPATCH_DIAG(T, launch_combine_cfg, n, r, R, G, y, b, sigma, Av, lb, part, sc, nblk, st, tab);
 }
 
-void launch_fin_lsdir(const double* part, int nb, DevScalars* sc, LbfgsState* s, hipStream_t st) {
-  hipLaunchKernelGGL(k_fin_lsdir, dim3(1), dim3(kBlock), 0, st, part, nb, sc, s);
+void launch_fin_lsdir(const double* part, int nb, DevScalars* sc, LbfgsState* s, hipStream_t st,
+                      const BlockTab& tab, int count) {
+  hipLaunchKernelGGL(k_fin_lsdir, dim3(count), dim3(kBlock), 0, st, part, nb, sc, s, tab);
 }
 
 #define ALMBM_LBFGS_INST(T)                                                                               \
-  template void launch_lbfgs_dots<T>(long, const T*, const LbfgsRing<RingT<T>>&, double*, int,            \
-                                     const DevScalars*, hipStream_t);                                      \
+  template void launch_lbfgs_dots<T>(long, int, const T*, const LbfgsRing<RingT<T>>&, double*, int,       \
+                                     const DevScalars*, hipStream_t, const BlockTab&);                     \
   template void launch_lbfgs_combine<T>(long, int, int, const T*, const T*, const double*, const double*,   \
                                         double, const double*, const LbfgsRing<RingT<T>>&, double*,          \
-                                        const DevScalars*, int, hipStream_t);
+                                        const DevScalars*, int, hipStream_t, const BlockTab&);
 
 ALMBM_LBFGS_INST(double)
 ALMBM_LBFGS_INST(float)

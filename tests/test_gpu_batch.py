@@ -149,3 +149,53 @@ def test_batch_graph_reuse_and_tuned_tiles():
     assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
     for q in range(len(insts)):
         assert abs(outs[0][3][q] - res0[q]["pobj"]) <= 2e-6 * abs(res0[q]["pobj"])
+
+
+def test_batch_lbfgs_matches_single_lbfgs_solves_and_oracle_kkt():
+    """L-BFGS subproblems inside a batch (per-instance memories, ring regions
+    and partial slots from the block table): every instance converges, agrees
+    with its own single L-BFGS solve to what 1e-6 KKT fixes, meets the oracle's
+    KKT measure, and two batched solves agree bitwise."""
+    insts = _instances()
+    m = _almbm()
+
+    def probs():
+        return [m.Problem.maxcut(g.n, g.ei, g.ej, g.w, precision="f64", r_max=48, lanczos_kmax=60, device=DEV,
+                                 lbfgs_memory_max=4) for g, _ in insts]
+
+    factors = [gen.init_factor(g.n, r, 1) for g, r in insts]
+    opts = dict(eps_kkt=1e-6, max_outer=400, inner_solver=1, lbfgs_memory=3, max_inner=100)
+    outs = []
+    for rep in range(2):
+        ps = probs()
+        batch = m.Batch(ps, rank_stride=48)
+        st, sts, res, R, ranks, y = batch.solve(factors, **opts)
+        print(f"batched L-BFGS: status {st} {sts} outer {[x['outer'] for x in res]} "
+              f"inner {[x['inner_total'] for x in res]} ranks {ranks}", flush=True)
+        assert st == 0 and all(s == 0 for s in sts)
+        outs.append((R.cpu().numpy().copy(), y.cpu().numpy().copy()))
+        if rep == 0:
+            for q, ((g, r), p) in enumerate(zip(insts, ps)):
+                s1, r1, _, _ = p.solve(factors[q], **opts)
+                assert s1 == 0
+                Rq, yq = batch.instance(q, R, y, ranks[q])
+                po = oracle.maxcut_sdp(g)
+                yh = yq.cpu().numpy()
+                k = oracle.kkt(po, Rq.cpu().numpy(), yh, lam_min=oracle.min_eig(po, yh))
+                print(f"instance {q} n={g.n}: batch pobj {res[q]['pobj']:.10f} single {r1['pobj']:.10f} "
+                      f"inner {res[q]['inner_total']} vs {r1['inner_total']}; oracle kkt {k['kkt']:.2e}", flush=True)
+                assert abs(res[q]["pobj"] - r1["pobj"]) <= 2e-6 * abs(r1["pobj"])
+                assert k["pinf"] <= 1e-6 and k["gap"] <= 1e-6 and k["dinf"] <= 2e-6
+        batch.close()
+        for p in ps:
+            p.close()
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+
+
+def test_batch_lbfgs_rejects_memory_beyond_reservation():
+    insts = _instances()[:2]
+    m = _almbm()
+    batch = m.Batch(_problems(insts), rank_stride=16)  # instances reserve no L-BFGS rings
+    with pytest.raises(m.AlmBmError):
+        batch.solve([gen.init_factor(g.n, r, 1) for g, r in insts], inner_solver=1, lbfgs_memory=3)
+    batch.close()
