@@ -1949,11 +1949,13 @@ struct alm_bm_batch {
   int c_var[kNC] = {};              // tile variant of each class (from wvar)
   int nclass = 0;
   std::map<int, int> wvar;          // width -> tile variant chosen by alm_bm_batch_autotune
-  int32_t* a_inst = nullptr;        // blocks of every running instance (Lanczos)
-  int64_t* a_lo = nullptr;
-  int64_t* a_hi = nullptr;
-  int32_t* a_gid = nullptr;
-  int a_nb = 0;
+  int32_t* l_inst = nullptr;        // blocks of the instances a Lanczos pass still runs
+  int64_t* l_lo = nullptr;
+  int64_t* l_hi = nullptr;
+  int32_t* l_gid = nullptr;
+  int32_t* lm_dev = nullptr;        // count: Lanczos basis size of each instance's pass
+  std::vector<int32_t> hl_inst, hl_gid;  // host side of the Lanczos table (kept until uploaded)
+  std::vector<int64_t> hl_lo, hl_hi;
   int64_t* xbase_dev = nullptr;     // count
   int64_t* ob_dev = nullptr;        // count: re-layout arguments
   int32_t* os_dev = nullptr;
@@ -2156,10 +2158,11 @@ extern "C" alm_bm_status alm_bm_batch_create(int32_t count, const alm_bm_problem
     BK(balloc(b, (void**)&b->c_hi[c], nb * sizeof(int64_t)));
     BK(balloc(b, (void**)&b->c_gid[c], nb * sizeof(int32_t)));
   }
-  BK(balloc(b, (void**)&b->a_inst, nb * sizeof(int32_t)));
-  BK(balloc(b, (void**)&b->a_lo, nb * sizeof(int64_t)));
-  BK(balloc(b, (void**)&b->a_hi, nb * sizeof(int64_t)));
-  BK(balloc(b, (void**)&b->a_gid, nb * sizeof(int32_t)));
+  BK(balloc(b, (void**)&b->l_inst, nb * sizeof(int32_t)));
+  BK(balloc(b, (void**)&b->l_lo, nb * sizeof(int64_t)));
+  BK(balloc(b, (void**)&b->l_hi, nb * sizeof(int64_t)));
+  BK(balloc(b, (void**)&b->l_gid, nb * sizeof(int32_t)));
+  BK(balloc(b, (void**)&b->lm_dev, count * sizeof(int32_t)));
   BK(balloc(b, (void**)&b->xbase_dev, count * sizeof(int64_t)));
   BK(balloc(b, (void**)&b->ob_dev, count * sizeof(int64_t)));
   BK(balloc(b, (void**)&b->os_dev, count * sizeof(int32_t)));
@@ -2208,20 +2211,96 @@ struct BatchLanczos {
 
 }  // namespace
 
-// Lanczos on Z(y) for every instance at once (lockstep steps; each instance
-// stops contributing to decisions once its Ritz residual meets tol[q]).
+// Launch order of a table's nb entries over the chip's eight XCDs.  The
+// dispatcher hands workgroup i to XCD i mod 8, so launch position 8j + x gets
+// entry j of XCD x's contiguous share of the table: each XCD walks one
+// contiguous stretch of rows, a few instances at a time, and the vector
+// entries those instances gather stay in its own L2 instead of being fetched
+// by all eight.  Used for the Lanczos matvec (8-byte gathers: 1.7x faster on
+// the uneven batch); the factor products keep the round-robin order, where
+// the rows gathered do not fit one L2 either way and the contiguous shares
+// (row-balanced, not nonzero-balanced) left the XCDs unevenly loaded.
+static void xcd_order(std::vector<int32_t>& inst, std::vector<int64_t>& lo, std::vector<int64_t>& hi,
+                      std::vector<int32_t>& gid) {
+  constexpr int X = 8;
+  const int nb = (int)inst.size();
+  if (nb < 2 * X) return;
+  int start[X + 1];
+  start[0] = 0;
+  for (int x = 0; x < X; ++x) start[x + 1] = start[x] + nb / X + (x < nb % X ? 1 : 0);
+  std::vector<int32_t> i2(nb), g2(nb);
+  std::vector<int64_t> l2(nb), h2(nb);
+  for (int pos = 0; pos < nb; ++pos) {
+    const int e = start[pos % X] + pos / X;
+    i2[pos] = inst[e];
+    l2[pos] = lo[e];
+    h2[pos] = hi[e];
+    g2[pos] = gid[e];
+  }
+  inst.swap(i2);
+  lo.swap(l2);
+  hi.swap(h2);
+  gid.swap(g2);
+}
+
+// Launch table of the blocks of the instances with sel[q] != 0 (the Lanczos
+// table); returns its block count.  Each block keeps its slot in the full
+// table, so the per-instance reductions do not depend on the selection.
+static alm_bm_status batch_lanczos_table(alm_bm_batch* b, const std::vector<char>& sel, int& nb, hipStream_t st) {
+  b->hl_inst.clear();
+  b->hl_lo.clear();
+  b->hl_hi.clear();
+  b->hl_gid.clear();
+  for (int q = 0; q < b->count; ++q) {
+    if (!sel[q]) continue;
+    for (int blk = b->h_iblo[q]; blk < b->h_ibhi[q]; ++blk) {
+      b->hl_inst.push_back(q);
+      b->hl_lo.push_back(b->h_lo[blk]);
+      b->hl_hi.push_back(b->h_hi[blk]);
+      b->hl_gid.push_back(blk);
+    }
+  }
+  xcd_order(b->hl_inst, b->hl_lo, b->hl_hi, b->hl_gid);
+  nb = (int)b->hl_inst.size();
+  if (nb == 0) return ALM_BM_OK;
+  HIPCHK(hipMemcpyAsync(b->l_inst, b->hl_inst.data(), nb * sizeof(int32_t), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(b->l_lo, b->hl_lo.data(), nb * sizeof(int64_t), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(b->l_hi, b->hl_hi.data(), nb * sizeof(int64_t), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(b->l_gid, b->hl_gid.data(), nb * sizeof(int32_t), hipMemcpyHostToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));  // the table's host side is rebuilt by the next call
+  return ALM_BM_OK;
+}
+
+// One Lanczos pass on Z(y) for the instances with run[q] != 0, in lockstep.
+// Every 8 steps the host checks each running instance's Ritz residual; an
+// instance that meets tol[q] (or exhausts its basis) leaves the launch table,
+// so later steps cost only the instances still running.  Results of the
+// other instances in `out` are left as they are.
 static alm_bm_status batch_lanczos_pass(alm_bm_batch* b, const double* y, int kmax, const std::vector<double>& tol,
                                         uint64_t seed, bool restart, double* v, BatchLanczos& out, hipStream_t st,
-                                        const std::vector<int32_t>& active) {
+                                        const std::vector<int32_t>& run) {
   alm_bm_problem* p = b->p;
   const int count = b->count;
   const long n = p->d.n, ldq = n;
-  const int nb = b->a_nb, kp = p->kmax + 1;
+  const int kp = p->kmax + 1;
   kmax = std::min(kmax, p->kmax);
-  // only the blocks of the running instances (partial sums in their slots of
-  // the full table, so the per-instance reductions are unchanged)
-  const BlockTab atab{b->a_inst, b->a_lo, b->a_hi, p->tab.iblo, p->tab.ibhi, b->a_gid, nullptr};
-  VecBatch vb{atab, count, kp, kp};
+  std::vector<char> live(count), done(count, 1);
+  int ndone = count;
+  for (int q = 0; q < count; ++q) {
+    live[q] = run[q] != 0;
+    if (live[q]) {
+      done[q] = 0;
+      --ndone;
+      out.theta[q] = 0.0;
+      out.resid[q] = 0.0;
+      out.m[q] = 0;
+    }
+  }
+  if (ndone == count) return ALM_BM_OK;
+  int nb = 0;
+  STCHK(batch_lanczos_table(b, live, nb, st));
+  const BlockTab ltab{b->l_inst, b->l_lo, b->l_hi, p->tab.iblo, p->tab.ibhi, b->l_gid, nullptr};
+  VecBatch vb{ltab, count, kp, kp};
   if (restart) {
     launch_resid(n, v, v, 0.0, nullptr, p->lpart2, nb, st, vb);
     launch_fin_sum(p->lpart2, nb, p->lscal, 1, st, vb, 4);
@@ -2233,19 +2312,9 @@ static alm_bm_status batch_lanczos_pass(alm_bm_batch* b, const double* y, int km
   }
   std::vector<double> ha((size_t)count * kp), hb((size_t)count * kp);
   std::vector<std::vector<double>> z(count);
-  out.theta.assign(count, 0.0);
-  out.resid.assign(count, 0.0);
-  out.m.assign(count, 0);
-  std::vector<char> done(count, 0);
-  int ndone = 0;
-  for (int q = 0; q < count; ++q)
-    if (!active[q]) {
-      done[q] = 1;
-      ++ndone;
-    }
   for (int j = 0; j < kmax; ++j) {
     const double* qj = p->Q + (long)j * ldq;
-    launch_slack_mv_tab(p->C64, y, qj, p->lw, atab, nb, st);
+    launch_slack_mv_tab(p->C64, y, qj, p->lw, ltab, nb, st);
     launch_dots(n, j + 1, p->Q, ldq, p->lw, p->lpart, kp, nb, p->lh1, st, vb);
     launch_sub(n, j + 1, p->Q, ldq, p->lh1, p->lw, p->lpart2, nb, st, vb);
     launch_dots(n, j + 1, p->Q, ldq, p->lw, p->lpart, kp, nb, p->lh2, st, vb);
@@ -2257,6 +2326,7 @@ static alm_bm_status batch_lanczos_pass(alm_bm_batch* b, const double* y, int km
       HIPCHK(hipMemcpyAsync(ha.data(), p->lalpha, ha.size() * sizeof(double), hipMemcpyDeviceToHost, st));
       HIPCHK(hipMemcpyAsync(hb.data(), p->lbeta, hb.size() * sizeof(double), hipMemcpyDeviceToHost, st));
       HIPCHK(hipStreamSynchronize(st));
+      bool dropped = false;
       for (int q = 0; q < count; ++q) {
         if (done[q]) continue;
         std::vector<double> a(ha.begin() + (long)q * kp, ha.begin() + (long)q * kp + j + 1);
@@ -2281,42 +2351,66 @@ static alm_bm_status batch_lanczos_pass(alm_bm_batch* b, const double* y, int km
         if (breakdown || est <= tol[q] || mm >= b->kmax[q] || mm >= (int)(b->off[q + 1] - b->off[q])) {
           done[q] = 1;
           ++ndone;
+          dropped = true;
         }
       }
       if (ndone == count || last) break;
+      if (dropped) {
+        for (int q = 0; q < count; ++q) live[q] = !done[q];
+        STCHK(batch_lanczos_table(b, live, nb, st));
+      }
     }
   }
+  // Ritz vectors of the instances of this pass, each from its own basis size
+  for (int q = 0; q < count; ++q) live[q] = run[q] != 0;
+  STCHK(batch_lanczos_table(b, live, nb, st));
   int mmax = 1;
   std::vector<double> s((size_t)count * kp, 0.0);
+  std::vector<int32_t> mq(count, 0);
   for (int q = 0; q < count; ++q) {
+    if (!live[q]) continue;
     for (int i = 0; i < out.m[q]; ++i) s[(size_t)q * kp + i] = z[q][i];
+    mq[q] = out.m[q];
     mmax = std::max(mmax, out.m[q]);
   }
   HIPCHK(hipMemcpyAsync(p->ls, s.data(), s.size() * sizeof(double), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(b->lm_dev, mq.data(), count * sizeof(int32_t), hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(b->thetas_dev, out.theta.data(), count * sizeof(double), hipMemcpyHostToDevice, st));
-  launch_combine(n, mmax, p->Q, ldq, p->ls, v, p->lpart2, nb, st, vb);
+  launch_combine(n, mmax, p->Q, ldq, p->ls, v, p->lpart2, nb, st, vb, b->lm_dev);
   launch_fin_sum(p->lpart2, nb, p->lscal + 1, 1, st, vb, 4);
   launch_scale(n, v, p->lscal + 1, v, p->lpart2, nb, nullptr, st, vb, 4);
-  launch_slack_mv_tab(p->C64, y, v, p->lw, atab, nb, st);
+  launch_slack_mv_tab(p->C64, y, v, p->lw, ltab, nb, st);
   launch_resid(n, p->lw, v, 0.0, b->thetas_dev, p->lpart2, nb, st, vb);
   launch_fin_sum(p->lpart2, nb, p->lscal + 2, 1, st, vb, 4);
   std::vector<double> sc4((size_t)count * 4);
   HIPCHK(hipMemcpyAsync(sc4.data(), p->lscal, sc4.size() * sizeof(double), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   HIPCHK(hipGetLastError());
-  for (int q = 0; q < count; ++q) out.resid[q] = active[q] ? sc4[(size_t)q * 4 + 2] : 0.0;
+  for (int q = 0; q < count; ++q)
+    if (live[q]) out.resid[q] = sc4[(size_t)q * 4 + 2];
   return ALM_BM_OK;
 }
 
+// Lanczos for the instances with sel[q] != 0: a pass, then up to `restarts`
+// passes from the Ritz vector for the instances whose Ritz residual still
+// exceeds tol[q] (the others keep their results).  Entries of unselected
+// instances are zero.
 static alm_bm_status batch_lanczos(alm_bm_batch* b, const double* y, int kmax, const std::vector<double>& tol,
                                    uint64_t seed, double* v, BatchLanczos& out, hipStream_t st,
-                                   const std::vector<int32_t>& active, int restarts = 3) {
+                                   const std::vector<int32_t>& sel, int restarts = 3) {
+  const int count = b->count;
+  out.theta.assign(count, 0.0);
+  out.resid.assign(count, 0.0);
+  out.m.assign(count, 0);
+  std::vector<int32_t> run(sel);
   for (int rs = 0; rs <= restarts; ++rs) {
-    STCHK(batch_lanczos_pass(b, y, kmax, tol, seed, rs > 0, v, out, st, active));
-    bool ok = true;
-    for (int q = 0; q < b->count; ++q)
-      if (active[q] && out.resid[q] > tol[q]) ok = false;
-    if (ok) break;
+    STCHK(batch_lanczos_pass(b, y, kmax, tol, seed, rs > 0, v, out, st, run));
+    bool again = false;
+    for (int q = 0; q < count; ++q) {
+      run[q] = run[q] && out.resid[q] > tol[q];
+      again = again || run[q];
+    }
+    if (!again) break;
   }
   return ALM_BM_OK;
 }
@@ -2379,22 +2473,6 @@ static alm_bm_status batch_classes(alm_bm_batch* b, const std::vector<int>& w, c
     HIPCHK(hipMemcpyAsync(b->c_hi[c], ch[c].data(), k * sizeof(int64_t), hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(b->c_gid[c], cg[c].data(), k * sizeof(int32_t), hipMemcpyHostToDevice, st));
   }
-  std::vector<int32_t> ai, ag;
-  std::vector<int64_t> al, ah;
-  for (int q = 0; q < count; ++q) {
-    if (!active[q]) continue;
-    for (int blk = b->h_iblo[q]; blk < b->h_ibhi[q]; ++blk) {
-      ai.push_back(q);
-      al.push_back(b->h_lo[blk]);
-      ah.push_back(b->h_hi[blk]);
-      ag.push_back(blk);
-    }
-  }
-  b->a_nb = (int)ai.size();
-  HIPCHK(hipMemcpyAsync(b->a_inst, ai.data(), ai.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
-  HIPCHK(hipMemcpyAsync(b->a_lo, al.data(), al.size() * sizeof(int64_t), hipMemcpyHostToDevice, st));
-  HIPCHK(hipMemcpyAsync(b->a_hi, ah.data(), ah.size() * sizeof(int64_t), hipMemcpyHostToDevice, st));
-  HIPCHK(hipMemcpyAsync(b->a_gid, ag.data(), ag.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
   std::vector<int64_t> xb(count);
   for (int q = 0; q < count; ++q) xb[q] = batch_xbase(b, q, w[q]);
   HIPCHK(hipMemcpyAsync(b->xbase_dev, xb.data(), count * sizeof(int64_t), hipMemcpyHostToDevice, st));
@@ -2620,7 +2698,8 @@ static alm_bm_status batch_solve_impl(alm_bm_batch* b, const alm_bm_options& o, 
     if (any) {
       BatchLanczos L2;
       const double t2 = now_s();
-      STCHK(batch_lanczos(b, y, kmax, ltol, o.seed * 1000003ull + (uint64_t)k + 7777777ull, p->lv, L2, st, active,
+      std::vector<int32_t> exp_sel(expanded.begin(), expanded.end());
+      STCHK(batch_lanczos(b, y, kmax, ltol, o.seed * 1000003ull + (uint64_t)k + 7777777ull, p->lv, L2, st, exp_sel,
                           o.lanczos_restarts));
       tlan2 = now_s() - t2;
       for (int q = 0; q < count; ++q)

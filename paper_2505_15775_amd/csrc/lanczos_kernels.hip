@@ -201,8 +201,11 @@ k_rand(long n, uint64_t seed, double* __restrict__ x, double* __restrict__ part,
 // v = sum_c Q[c] s[c]; partial ||v||^2.
 __global__ void __launch_bounds__(kBlock)
 k_combine(long n, int ncol, const double* __restrict__ Q, long ldq, const double* __restrict__ s, int sstride,
-          double* __restrict__ v, double* __restrict__ part, BlockTab tab) {
+          double* __restrict__ v, double* __restrict__ part, BlockTab tab, const int32_t* __restrict__ ncols) {
   const Rows ch = rows_of(n, tab);
+  // per-instance basis sizes: columns past an instance's own count were not
+  // written for its rows in this pass
+  if (ncols && ncols[ch.inst] < ncol) ncol = ncols[ch.inst];
   __shared__ double ss[512 + 1];
   for (int c = threadIdx.x; c < ncol; c += kBlock) ss[c] = s[(long)ch.inst * sstride + c];
   __syncthreads();
@@ -412,8 +415,9 @@ void launch_rand(long n, uint64_t seed, double* x, double* part, int nb, hipStre
   hipLaunchKernelGGL(k_rand, dim3(nb), dim3(kBlock), 0, st, n, seed, x, part, vb.tab);
 }
 void launch_combine(long n, int ncol, const double* Q, long ldq, const double* s, double* v, double* part, int nb,
-                    hipStream_t st, const VecBatch& vb) {
-  hipLaunchKernelGGL(k_combine, dim3(nb), dim3(kBlock), 0, st, n, ncol, Q, ldq, s, vb.hstride, v, part, vb.tab);
+                    hipStream_t st, const VecBatch& vb, const int32_t* ncols) {
+  hipLaunchKernelGGL(k_combine, dim3(nb), dim3(kBlock), 0, st, n, ncol, Q, ldq, s, vb.hstride, v, part, vb.tab,
+                     ncols);
 }
 void launch_resid(long n, const double* z, const double* v, double theta, const double* thetas, double* part, int nb,
                   hipStream_t st, const VecBatch& vb) {

@@ -139,8 +139,10 @@ void launch_gram4(long n, int q, const double* V, double* part, int nb, hipStrea
 // The edge-row moments of the trace + edge family (edges ei[e] < ej[e], E of them).
 void launch_gram4_edges(long E, long n, int q, const int32_t* ei, const int32_t* ej, const double* V, double* part,
                         int nb, hipStream_t st);
+// v = sum_{c < ncol} Q[:, c] s[c] (per instance s + inst * hstride; with
+// ncols, at most ncols[inst] columns), partial ||v||^2.
 void launch_combine(long n, int ncol, const double* Q, long ldq, const double* s, double* v, double* part, int nb,
-                    hipStream_t st, const VecBatch& vb = VecBatch{});
+                    hipStream_t st, const VecBatch& vb = VecBatch{}, const int32_t* ncols = nullptr);
 void launch_resid(long n, const double* z, const double* v, double theta, const double* thetas, double* part, int nb,
                   hipStream_t st, const VecBatch& vb = VecBatch{});
 void launch_quartic_norm(long n, int cons_kind, const EdgeAdj& A, const double* x, double* part, int nb,
