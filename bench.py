@@ -589,6 +589,8 @@ def main():
     ap.add_argument("--batch", type=int, default=0, help="also the batched solve of this many instances vs a loop")
     ap.add_argument("--batch-eps", type=float, default=1e-4)
     ap.add_argument("--batch-no-loop", action="store_true", help="skip the per-instance loop of the batch leg")
+    ap.add_argument("--only-batch", action="store_true",
+                    help="run only the batch leg (--batch N) and print its JSON (profiling; no metric line)")
     ap.add_argument("--batch-no-tune", action="store_true", help="batch leg with the default tiles")
     ap.add_argument("--batch-inner", choices=["lbfgs", "gd"], default="lbfgs",
                     help="subproblem solver of the batch leg (both the batch and the loop)")
@@ -614,6 +616,14 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.calibrate_copy:
         calibrate_copy()
+    if args.only_batch:
+        if args.batch < 1:
+            print("--only-batch needs --batch N", file=sys.stderr)
+            sys.exit(2)
+        out = batch_leg(args.batch, args.batch_eps, args.sigma, "f64", loop=not args.batch_no_loop,
+                        tune=not args.batch_no_tune, inner=args.batch_inner)
+        print(json.dumps({"batched_solve": out}))
+        return
     t0 = time.time()
     M = int(args.n * args.deg / 2)
     g = gen.er_graph(args.n, M, args.seed, "gauss")
