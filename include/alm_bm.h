@@ -211,10 +211,12 @@ typedef struct {
   double inner_tol;          /* tolerance of the last subproblem (for resume_inner_tol) */
   double lanczos_resid;      /* Ritz residual ||Z v - theta v|| of the Lanczos run
                                 behind lam_min.  A solve returns ALM_BM_OK only when
-                                this met the Lanczos tolerance and theta did not
-                                exceed the Rayleigh quotient <Z, RR^T>/||R||_F^2
-                                (else the Ritz value is not the bottom of the
-                                spectrum and dinf is not certified)               */
+                                the low end of the Ritz interval is dual feasible to
+                                the tolerance, resid - theta <= eps_kkt (1 + ||C||_F),
+                                and theta did not exceed the Rayleigh quotient
+                                <Z, RR^T>/||R||_F^2 by more than the Lanczos
+                                tolerance (else the Ritz value is not the bottom of
+                                the spectrum and dinf is not certified)           */
 } alm_bm_result;
 
 /* --------------------------------------------------------------------------- */

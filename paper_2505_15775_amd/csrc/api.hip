@@ -1403,11 +1403,18 @@ static alm_bm_status kkt_eval(alm_bm_problem* p, int r, const T* R, const double
   return ALM_BM_OK;
 }
 
-// A Ritz value certifies the dual infeasibility term only if its residual met
-// the Lanczos tolerance and it does not exceed the Rayleigh quotient of X (a
-// Ritz value above it belongs to an eigenvalue other than the smallest).
-static bool lanczos_certifies(double theta, double resid, double ltol, double rq) {
-  return std::isfinite(theta) && resid <= ltol && theta <= rq + ltol;
+// A Ritz pair (theta, residual) bounds an eigenvalue of the slack to
+// [theta - resid, theta + resid]; taken as the bottom of the spectrum (what a
+// Krylov space from a random start finds first), it certifies the dual
+// infeasibility term when even the low end theta - resid meets the tolerance:
+// resid - theta <= dtol = eps (1 + ||C||_F).  A Ritz value above the Rayleigh
+// quotient of X (plus ltol) belongs to an eigenvalue other than the smallest
+// and certifies nothing.  Near an optimum the bottom of the spectrum is a
+// cluster of about rank-many eigenvalues near zero, where the Ritz residual
+// stalls far above its own tolerance while theta itself is tiny; this test
+// accepts such a pair when its whole interval is dual feasible to dtol.
+static bool lanczos_certifies(double theta, double resid, double ltol, double rq, double dtol) {
+  return std::isfinite(theta) && std::isfinite(resid) && theta <= rq + ltol && resid - theta <= dtol;
 }
 
 extern "C" alm_bm_status alm_bm_kkt(alm_bm_problem* p, int32_t r, const void* R, const double* y, double lam_min,
@@ -1687,11 +1694,23 @@ static alm_bm_status solve_impl(alm_bm_problem* p, const alm_bm_options& o, T* R
     STCHK(lanczos_run(p, p->ybuf, kmax, ltol, o.seed * 1000003ull + (uint64_t)k, p->lv, lo, st,
                       o.lanczos_restarts));
     acc.time_lanczos_s += now_s() - tl;
+    // KKT of the point as it stands (the final one unless a rank step follows)
+    KktVals kv{};
+    STCHK(kkt_eval<T>(p, w, R, p->ybuf, lo.theta, kv, st));
+    // The rank test of Alg. 1 asks for theta < -tau.  A point that meets the KKT
+    // tolerance but whose Ritz interval reaches below -dtol although the
+    // residual alone would allow a certificate (resid < dtol) has negative
+    // curvature that blocks the certificate while staying above -tau; it
+    // takes the rank step too, or the solve would repeat the same outer
+    // iteration until max_outer.
+    const double dtol = o.eps_kkt * (1.0 + p->cnorm);
+    const bool blocked = kv.kkt <= o.eps_kkt && lo.resid < dtol && lo.resid - lo.theta > dtol;
+    const double tau_k = blocked ? 0.0 : tau_rank;
     bool expanded = false;
     const bool gate = (flag == 1) || !o.expand_needs_inner;
-    if (o.rank_policy == ALM_BM_RANK_ADAPT && gate && lo.theta < -tau_rank && r < r_cap && o.rank_block > 1) {
+    if (o.rank_policy == ALM_BM_RANK_ADAPT && gate && lo.theta < -tau_k && r < r_cap && o.rank_block > 1) {
       int added = 0;
-      STCHK(block_rank_step<T>(p, R, r, w, r_cap, o.rank_block, sigma, kmax, tau_rank,
+      STCHK(block_rank_step<T>(p, R, r, w, r_cap, o.rank_block, sigma, kmax, tau_k,
                                o.seed * 1000003ull + (uint64_t)k + 3333333ull, gc, added, st));
       if (added > 0) {
         expanded = true;
@@ -1700,7 +1719,7 @@ static alm_bm_status solve_impl(alm_bm_problem* p, const alm_bm_options& o, T* R
         launch_dual(d.m, p->Av, d.b, y, p->ybuf, sigma, p->part_vec, p->sc_solve, p->bnorm, nullptr, st,
                     sigma * p->rho);
       }
-    } else if (o.rank_policy == ALM_BM_RANK_ADAPT && gate && lo.theta < -tau_rank && r < r_cap) {
+    } else if (o.rank_policy == ALM_BM_RANK_ADAPT && gate && lo.theta < -tau_k && r < r_cap) {
       // ||A(v v^T)||^2 for the unit Ritz vector
       launch_quartic_norm(n, d.cons_kind == ALM_BM_CONS_DIAG ? 0 : 1, p->adj, p->lv, p->lpart2, p->lnb, st);
       launch_fin_sum(p->lpart2, p->lnb, p->lscal + 3, 0, st);
@@ -1739,9 +1758,8 @@ static alm_bm_status solve_impl(alm_bm_problem* p, const alm_bm_options& o, T* R
       acc.time_lanczos_s += now_s() - tl2;
       lam = l2.theta;
       lres = l2.resid;
+      STCHK(kkt_eval<T>(p, w, R, y, lam, kv, st));
     }
-    KktVals kv{};
-    STCHK(kkt_eval<T>(p, w, R, y, lam, kv, st));
     if (p->sc_host->numeric_error) return fail(ALM_BM_ERR_NUMERIC, "solve: NaN/Inf in objective or step");
     HIPCHK(hipMemcpyAsync(p->sc_host, p->sc_solve, sizeof(DevScalars), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
@@ -1759,7 +1777,7 @@ static alm_bm_status solve_impl(alm_bm_problem* p, const alm_bm_options& o, T* R
     acc.lanczos_resid = lres;
     pinf_prev = kv.pinf;
     k_done = k + 1;
-    const bool cert = lanczos_certifies(lam, lres, ltol, kv.rq);
+    const bool cert = lanczos_certifies(lam, lres, ltol, kv.rq, o.eps_kkt * (1.0 + p->cnorm));
     if (o.verbose)
       std::fprintf(stderr,
                    "[almbm] k=%d inner=%d flag=%d r=%d theta=%.3e rq=%.3e lres=%.2e%s lanczos=%d pinf=%.3e "
@@ -2632,7 +2650,22 @@ static alm_bm_status batch_solve_impl(alm_bm_batch* b, const alm_bm_options& o, 
     STCHK(batch_lanczos(b, p->ybuf, kmax, ltol, o.seed * 1000003ull + (uint64_t)k, p->lv, L, st, active,
                         o.lanczos_restarts));
     const double tlan = now_s() - tl;
-    // rank expansion decisions
+    // KKT per instance at the point as it stands (R, the updated dual):
+    // <C, RR^T> and pinf at R, b^T y at y; the final values unless a rank step
+    // follows
+    std::vector<DevScalars> hs(count);
+    auto batch_kkt = [&](const double* yv) -> alm_bm_status {
+      batch_enqueue_objgrad<T>(b, R, yv, 0.0, st);
+      launch_dual_batch(N, p->Av, p->d.b, yv, nullptr, 0.0, p->part_vec, p->sc_api, b->bnorm_dev, p->tab, p->nblk,
+                        count, st);
+      HIPCHK(hipMemcpyAsync(hs.data(), p->sc_api, count * sizeof(DevScalars), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      HIPCHK(hipGetLastError());
+      return ALM_BM_OK;
+    };
+    STCHK(batch_kkt(p->ybuf));
+    // rank expansion decisions (the rank test of Alg. 1, plus the blocked
+    // certificate case of the single solve)
     std::vector<int32_t> col(count, 0);
     std::vector<double> scale(count, -1.0);
     std::vector<char> expanded(count, 0);
@@ -2648,7 +2681,13 @@ static alm_bm_status batch_solve_impl(alm_bm_batch* b, const alm_bm_options& o, 
         if (!active[q]) continue;
         const bool gate = (fl[2 * q] == 1) || !o.expand_needs_inner;
         const double q4 = sc4[(size_t)q * 4 + 3];
-        if (gate && L.theta[q] < -tau[q] && r[q] < rcap[q] && q4 > 0.0) {
+        KktVals k0{};
+        const double rq0 = slack_rq(hs[q].tot[P_C0], hs[q].dobj, hs[q].tot[P_YBMA], hs[q].tot[P_RR]);
+        kkt_terms(hs[q].tot[P_C0], hs[q].dobj, hs[q].pinf, L.theta[q], rq0, b->cnorm[q], k0);
+        const double dtol = o.eps_kkt * (1.0 + b->cnorm[q]);
+        const bool blocked = k0.kkt <= o.eps_kkt && L.resid[q] < dtol && L.resid[q] - L.theta[q] > dtol;
+        const double tau_q = blocked ? 0.0 : tau[q];
+        if (gate && L.theta[q] < -tau_q && r[q] < rcap[q] && q4 > 0.0) {
           col[q] = r[q];
           scale[q] = std::sqrt(std::max(0.0, -L.theta[q] / (sigma * q4)));
           expanded[q] = 1;
@@ -2708,14 +2747,7 @@ static alm_bm_status batch_solve_impl(alm_bm_batch* b, const alm_bm_options& o, 
           lres[q] = L2.resid[q];
         }
     }
-    // KKT per instance: <C, RR^T> and pinf at R, b^T y at y
-    batch_enqueue_objgrad<T>(b, R, y, 0.0, st);
-    launch_dual_batch(N, p->Av, p->d.b, y, nullptr, 0.0, p->part_vec, p->sc_api, b->bnorm_dev, p->tab, p->nblk, count,
-                      st);
-    std::vector<DevScalars> hs(count);
-    HIPCHK(hipMemcpyAsync(hs.data(), p->sc_api, count * sizeof(DevScalars), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    HIPCHK(hipGetLastError());
+    if (any) STCHK(batch_kkt(y));  // after rank steps: the KKT at the new point
     for (int q = 0; q < count; ++q) {
       if (!active[q]) continue;
       KktVals kv{};
@@ -2735,7 +2767,7 @@ static alm_bm_status batch_solve_impl(alm_bm_batch* b, const alm_bm_options& o, 
       res[q].lanczos_resid = lres[q];
       res[q].time_lanczos_s += (tlan + tlan2) / nactive;
       pinf_prev[q] = kv.pinf;
-      if (kv.kkt <= o.eps_kkt && lanczos_certifies(lam[q], lres[q], ltol[q], rq)) {
+      if (kv.kkt <= o.eps_kkt && lanczos_certifies(lam[q], lres[q], ltol[q], rq, o.eps_kkt * (1.0 + b->cnorm[q]))) {
         active[q] = 0;
         st_q[q] = ALM_BM_OK;
         res[q].time_s = now_s() - t0;

@@ -16,6 +16,7 @@ Command line (GPU):  python -m paper_2505_15775_amd.warmstart train --count 200 
 
 import argparse
 import ctypes as C
+import json
 import math
 import os
 import sys
@@ -264,16 +265,114 @@ def generate_training_set(graphs, eps=1e-5, r0=16, r_max=64, sigma=16.0, device=
     return feats, targets, pools, ns, ranks
 
 
+def generate_training_set_batched(graphs, eps=1e-5, r0=16, r_max=64, sigma=16.0, batch=48, device="cuda",
+                                  log=None):
+    """As generate_training_set, with the labelling solves run `batch` graphs
+    at a time by the batched solver (L-BFGS subproblems of at most 100 steps)."""
+    import gen
+
+    from . import Batch
+
+    feats, targets, pools, ns, ranks = [], [], [], [], []
+    for start in range(0, len(graphs), batch):
+        chunk = graphs[start:start + batch]
+        probs = [Problem.maxcut(g.n, g.ei, g.ej, g.w, precision="f64", r_max=r_max, lanczos_kmax=60, device=device,
+                                validate=False, lbfgs_memory_max=3) for g in chunk]
+        b = Batch(probs, rank_stride=r_max)
+        t0 = time.time()
+        _, sts, res, R, rk, y = b.solve([gen.init_factor(g.n, r0, 1) for g in chunk], eps_kkt=eps, sigma=sigma,
+                                        max_outer=300, inner_solver=1, lbfgs_memory=3, max_inner=100)
+        for q, (g, p) in enumerate(zip(chunk, probs)):
+            if sts[q] != 0:
+                if log:
+                    log(f"[warmstart] graph {start + q} n={g.n}: not converged (kkt {res[q]['kkt']:.2e}), skipped")
+                continue
+            _, yq = b.instance(q, R, y, rk[q])
+            F = features(p)
+            feats.append(F)
+            targets.append(yq.float().clone())
+            pools.append(pooled(F))
+            ns.append(g.n)
+            ranks.append(rk[q])
+        if log:
+            log(f"[warmstart] labelled graphs {start}..{start + len(chunk) - 1} in {time.time() - t0:.1f}s "
+                f"(ranks {min(rk)}..{max(rk)})")
+        b.close()
+        for p in probs:
+            p.close()
+    return feats, targets, pools, ns, ranks
+
+
+def _fit(feats, targets, pools, ns, ranks, hidden, seed, steps, log=None):
+    model = WarmStartModel(h=hidden, seed=seed)
+    X = torch.cat(feats).contiguous()
+    T = torch.cat(targets).contiguous()
+    hist = model.fit(X, T, steps=steps, log=log)
+    model.fit_rank(pools, ns, ranks)
+    return model, hist, int(X.shape[0])
+
+
+def _held_out_errors(model, feats, targets, pools, ns, ranks):
+    """Mean relative error of y0 and mean |r0 - r*| over labelled graphs."""
+    ey, er = [], []
+    for F, T, pl, n, r in zip(feats, targets, pools, ns, ranks):
+        out = torch.empty(n, dtype=torch.float64, device=F.device)
+        check(lib.alm_bm_ws_forward(_ptr(model.params), model.nin, model.h, _ptr(model.mu), _ptr(model.inv_sd), n,
+                                    _ptr(F), _ptr(out), _stream()), "ws_forward")
+        t = T.double()
+        ey.append(float(torch.linalg.norm(out - t) / torch.linalg.norm(t)))
+        er.append(abs(model.predict_r0(pl, n) - r))
+    return float(np.mean(ey)), float(np.mean(er))
+
+
+def ablation(graphs, model, eps=1e-5, sigma=16.0, r_default=16, log=None):
+    """Solves of each graph from four starts: the default (y = 0, rank 16), the
+    learned y0 at rank 16, y = 0 at the learned r0, and both (solve_warm's
+    start, without its fallback test).  L-BFGS subproblems of at most 100
+    steps.  Returns per-start totals of outer iterations and seconds."""
+    import gen
+
+    opts = dict(eps_kkt=eps, sigma=sigma, max_outer=300, inner_solver=1, lbfgs_memory=3, max_inner=100)
+    tot = {k: {"outer": 0, "time_s": 0.0, "converged": 0} for k in ("default", "y0_only", "r0_only", "both")}
+    for g in graphs:
+        prob = Problem.maxcut(g.n, g.ei, g.ej, g.w, precision="f64", r_max=64, lanczos_kmax=60, validate=False,
+                              lbfgs_memory_max=3)
+        F = features(prob)
+        y0 = model.predict_y0(prob, F)
+        r0 = model.predict_r0(pooled(F), g.n, prob.r_max)
+        line = f"[warmstart] ablation n={g.n} r0={r0}:"
+        for k, (r, yy) in {"default": (r_default, None), "y0_only": (r_default, y0), "r0_only": (r0, None),
+                           "both": (r0, y0)}.items():
+            st, res, _, _ = prob.solve(gen.init_factor(g.n, r, 1), yy, **opts)
+            tot[k]["outer"] += res["outer"]
+            tot[k]["time_s"] += res["time_s"]
+            tot[k]["converged"] += int(st == 0)
+            line += f" {k} {res['outer']} outer {res['time_s']:.2f}s rank {res['rank']};"
+        if log:
+            log(line)
+        prob.close()
+    return tot
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
-    t = sub.add_parser("train")
+    t = sub.add_parser("train", help="label seeded graphs with solves and fit the model")
     t.add_argument("--count", type=int, default=120)
     t.add_argument("--seed", type=int, default=6)
     t.add_argument("--steps", type=int, default=600)
     t.add_argument("--hidden", type=int, default=32)
     t.add_argument("--sigma", type=float, default=16.0, help="penalty of the labelling solves")
+    t.add_argument("--batched", action="store_true", help="label with the batched solver (L-BFGS subproblems)")
     t.add_argument("--out", default=MODEL_PATH)
+    c = sub.add_parser("curve", help="learning curve over training-set sizes, then the start ablation")
+    c.add_argument("--count", type=int, default=600)
+    c.add_argument("--seed", type=int, default=6)
+    c.add_argument("--steps", type=int, default=1200)
+    c.add_argument("--hidden", type=int, default=32)
+    c.add_argument("--sigma", type=float, default=16.0)
+    c.add_argument("--ablation", type=int, default=12, help="held-out graphs solved from the four starts")
+    c.add_argument("--out", default=None, help="save the model fitted on the whole training part here")
     args = ap.parse_args()
 
     def log(s):
@@ -282,16 +381,35 @@ def main():
     graphs = training_graphs(args.count, args.seed)
     n_hold = max(1, args.count // 10)
     t0 = time.time()
-    feats, targets, pools, ns, ranks = generate_training_set(graphs[n_hold:], sigma=args.sigma, log=log)
-    log(f"[warmstart] {len(feats)} labelled solves in {time.time() - t0:.1f}s")
-    X = torch.cat(feats).contiguous()
-    T = torch.cat(targets).contiguous()
-    model = WarmStartModel(h=args.hidden, seed=args.seed)
-    hist = model.fit(X, T, steps=args.steps, log=log)
-    model.fit_rank(pools, ns, ranks)
-    model.save(args.out, meta={"count": args.count, "seed": args.seed, "holdout": n_hold, "vertices": int(X.shape[0]),
-                               "loss": hist[-1][1], "sigma": args.sigma})
-    log(f"[warmstart] saved {args.out}")
+    if args.cmd == "train":
+        gen_set = generate_training_set_batched if args.batched else generate_training_set
+        feats, targets, pools, ns, ranks = gen_set(graphs[n_hold:], sigma=args.sigma, log=log)
+        log(f"[warmstart] {len(feats)} labelled solves in {time.time() - t0:.1f}s")
+        model, hist, nv = _fit(feats, targets, pools, ns, ranks, args.hidden, args.seed, args.steps, log)
+        model.save(args.out, meta={"count": args.count, "seed": args.seed, "holdout": n_hold, "vertices": nv,
+                                   "loss": hist[-1][1], "sigma": args.sigma})
+        log(f"[warmstart] saved {args.out}")
+        return
+    # learning curve: held-out errors of models fitted on growing prefixes of the training part
+    hold = generate_training_set_batched(graphs[:n_hold], sigma=args.sigma, log=log)
+    train = generate_training_set_batched(graphs[n_hold:], sigma=args.sigma, log=log)
+    log(f"[warmstart] {len(hold[0])} held-out and {len(train[0])} training graphs labelled in {time.time() - t0:.1f}s")
+    sizes = [k for k in (10, 25, 50, 100, 200, 400, 800, 1600) if k < len(train[0])] + [len(train[0])]
+    curve = []
+    model = None
+    for k in sizes:
+        model, hist, nv = _fit(*(x[:k] for x in train), args.hidden, args.seed, args.steps)
+        ey, er = _held_out_errors(model, *hold)
+        curve.append({"graphs": k, "vertices": nv, "train_loss": round(hist[-1][1], 6),
+                      "held_out_y0_rel_err": round(ey, 4), "held_out_r0_abs_err": round(er, 2)})
+        log(f"[warmstart] curve {curve[-1]}")
+    if args.out:
+        model.save(args.out, meta={"count": args.count, "seed": args.seed, "holdout": n_hold, "graphs": sizes[-1],
+                                   "vertices": curve[-1]["vertices"], "loss": curve[-1]["train_loss"],
+                                   "sigma": args.sigma, "labels": "batched L-BFGS solves to 1e-5 KKT"})
+        log(f"[warmstart] saved {args.out}")
+    abl = ablation(graphs[:min(args.ablation, n_hold)], model, sigma=args.sigma, log=log)
+    print(json.dumps({"learning_curve": curve, "ablation": abl}), flush=True)
 
 
 if __name__ == "__main__":

@@ -106,9 +106,9 @@ def test_solve_max_outer_exit_returns_valid_outputs():
 def test_solve_refuses_ok_without_a_certified_lanczos_value():
     """dinf needs lambda_min of the slack.  A solve restarted at a converged
     point with a 2-vector Krylov space and no restarts measures a KKT value
-    below eps, but its Ritz residual misses the Lanczos tolerance, so the
-    value is not certified and the solve must not return OK; the residual is
-    reported."""
+    below eps, but its Ritz interval [theta - resid, theta + resid] reaches
+    below -eps (1 + ||C||_F), so the value is not certified and the solve must
+    not return OK; the residual is reported."""
     g = gen.er_graph(700, 4000, 21, "gauss")
     prob = _maxcut(g, r_max=32, kmax=80)
     st, res, R, y = prob.solve(gen.init_factor(700, 4, 3), eps_kkt=1e-5, max_outer=300)
@@ -119,7 +119,31 @@ def test_solve_refuses_ok_without_a_certified_lanczos_value():
     st2, res2, _, _ = prob.solve(R.clone(), y, eps_kkt=1e-5, max_outer=3, lanczos_kmax=2, lanczos_restarts=0)
     print(f"kmax 2: status {st2} kkt {res2['kkt']:.3e} lanczos resid {res2['lanczos_resid']:.3e} (tol {ltol:.3e})")
     assert st2 == 1 and res2["lanczos_resid"] > ltol
+    assert res2["lanczos_resid"] - res2["lam_min"] > 1e-5 * (1.0 + cn)
     assert res2["kkt"] <= 1e-5  # only the missing certificate keeps it from OK
+    prob.close()
+
+
+def test_certified_stop_at_a_clustered_spectrum_is_sound():
+    """At a tight tolerance the bottom of the slack's spectrum is a cluster of
+    about rank-many eigenvalues near zero, where the Ritz residual stalls above
+    its own tolerance.  The solve stops once the low end of the Ritz interval
+    is dual feasible; the oracle's exact lambda_min at the returned dual must
+    then meet the tolerance as well, so the stop is sound."""
+    g = gen.er_graph(5000, 30000, 23, "gauss")
+    po = oracle.maxcut_sdp(g)
+    cn = float(np.sqrt(po.C.multiply(po.C).sum()))
+    prob = _maxcut(g, r_max=64, kmax=60)
+    st, res, R, y = prob.solve(gen.init_factor(g.n, 16, 1), eps_kkt=1e-5, sigma=16.0, max_outer=300)
+    print(f"status {st} outer {res['outer']} kkt {res['kkt']:.2e} theta {res['lam_min']:.3e} "
+          f"resid {res['lanczos_resid']:.3e} dtol {1e-5 * (1 + cn):.3e}")
+    assert st == 0
+    assert res["lanczos_resid"] - res["lam_min"] <= 1e-5 * (1.0 + cn) * (1 + 1e-12)
+    yh = y.cpu().numpy()
+    lam = oracle.min_eig(po, yh)
+    k = oracle.kkt(po, R.cpu().numpy(), yh, lam_min=lam)
+    print(f"oracle lambda_min {lam:.3e}: kkt {k['kkt']:.2e} (dinf {k['dinf']:.2e})")
+    assert k["dinf"] <= 1e-5 and k["kkt"] <= 1.2e-5
     prob.close()
 
 
