@@ -11,7 +11,11 @@ Training data are the project's own solves: seeded generated graphs, solved
 from the default start, labelled with the final dual y* (per vertex) and the
 final rank r* (per graph).
 
-Command line (GPU):  python -m paper_2505_15775_amd.warmstart train --count 200 --out MODEL.npz
+Command line (GPU):
+  python -m paper_2505_15775_amd.warmstart train --count 200 --batched --out MODEL.npz
+  python -m paper_2505_15775_amd.warmstart curve --count 600 --out MODEL.npz
+(curve: held-out errors of models fitted on growing training sets, then
+solves of held-out graphs from the default, y0-only, r0-only and full starts)
 """
 
 import argparse
