@@ -41,8 +41,8 @@
  *   - Indices are 0-based int32.
  *   - All work is enqueued on the given stream.  Calls that return host
  *     results synchronise it: alm_bm_solve, alm_bm_inner_solve,
- *     alm_bm_lanczos_min_eig (its small tridiagonal eigensolve runs on the
- *     host), alm_bm_kkt, alm_bm_autotune, alm_bm_batch_autotune and
+ *     alm_bm_lanczos_min_eig and alm_bm_lanczos_block (their small
+ *     eigensolves run on the host), alm_bm_kkt, alm_bm_autotune, alm_bm_batch_autotune and
  *     alm_bm_batch_solve;
  *     alm_bm_set_hub_threshold synchronises the device.
  *   - A handle is not thread-safe.  Calls that overlap on one handle race.
@@ -305,6 +305,23 @@ alm_bm_status alm_bm_dual_update(alm_bm_problem* prob, const double* Av, double 
 alm_bm_status alm_bm_lanczos_min_eig(alm_bm_problem* prob, const double* y, int32_t max_iter,
                                      double tol, uint64_t seed, double* theta, double* v,
                                      double* resid, int32_t* iters, hipStream_t stream);
+
+/* The q smallest eigenpairs of Z(y) (Sec. 5: the rank step of Alg. 1 uses the
+ * negative ones) by block Lanczos: a block Krylov space span{V0, Z V0, ...} of
+ * min(max_iter + 1, n) columns from q counter-based random start vectors (seed),
+ * each new column orthogonalised against all earlier ones (two classical
+ * Gram-Schmidt passes, FP64), then Rayleigh-Ritz on the projected matrix on the
+ * host.  A block of q vectors captures an eigenvalue of multiplicity up to q,
+ * which a single Krylov vector cannot.  q in 1..8; max_iter in 1..lanczos_kmax
+ * and the basis must exceed q.
+ * theta: host q doubles, ascending Ritz values (upper bounds on the q smallest
+ * eigenvalues; NaN past the basis size); V: device n x q column-major, the unit
+ * Ritz vectors (nullable when the handle's rank_block_max >= q); resid: host q
+ * doubles ||Z v - theta v|| (nullable; one more product each); basis: host 1
+ * int32, the basis size used (nullable).  Synchronises stream.                */
+alm_bm_status alm_bm_lanczos_block(alm_bm_problem* prob, const double* y, int32_t q, int32_t max_iter,
+                                   uint64_t seed, double* theta, double* V, double* resid, int32_t* basis,
+                                   hipStream_t stream);
 
 /* The inner loop of alm_bm_solve on its own: gradient descent with exact line
  * search on eq. (AL-BM) at fixed y from R (in place, device n x r), until

@@ -279,6 +279,18 @@ class Problem:
                                          _ptr(rs), _ptr(it), _stream(stream)), "lanczos_min_eig")
         return float(th.item()), v, float(rs.item()), int(it.item())
 
+    def lanczos_block(self, y, q, max_iter=60, seed=1, stream=None):
+        """(theta[q] host, V n x q device column-major, resid[q] host, basis size)
+        for the q smallest eigenpairs of C - A*(y) by block Lanczos."""
+        self._check_y(y)
+        th = np.zeros(int(q), dtype=np.float64)
+        rs = np.zeros(int(q), dtype=np.float64)
+        V = torch.empty((int(q), self.n), dtype=torch.float64, device=self.device)  # row k = column k of n x q
+        m = C.c_int32(0)
+        check(lib.alm_bm_lanczos_block(self._h, _ptr(y), int(q), int(max_iter), int(seed), th.ctypes.data, _ptr(V),
+                                       rs.ctypes.data, C.byref(m), _stream(stream)), "lanczos_block")
+        return th, V.t(), rs, m.value
+
     def set_tiles(self, variant=0, row_blocks=0):
         check(lib.alm_bm_set_tiles(self._h, int(variant), int(row_blocks)), "set_tiles")
 

@@ -90,6 +90,9 @@ struct alm_bm_problem {
   double* ls = nullptr;
   double* lscal = nullptr;
   std::vector<void*> allocs;
+  double* bk_h = nullptr;         // block Krylov: (kmax+1)^2 projected matrix, column sums, Ritz coefficients
+  double* bk_colsum = nullptr;
+  double* bk_coef = nullptr;
   double* vblk = nullptr;         // block rank step: n x rank_block_max directions, their coefficients,
   double* ycoef = nullptr;        //   fourth-moment partials (reserved at create)
   double* gpart = nullptr;
@@ -563,6 +566,9 @@ extern "C" alm_bm_status alm_bm_create(const alm_bm_problem_desc* desc, hipStrea
     CK(dalloc_t(p, &p->lscal, 8));
     CK(dalloc_t(p, &p->lpart, (size_t)p->lnb * (p->kmax + 1)));
     CK(dalloc_t(p, &p->lpart2, (size_t)p->lnb));
+    CK(dalloc_t(p, &p->bk_h, (size_t)(p->kmax + 1) * (p->kmax + 1)));
+    CK(dalloc_t(p, &p->bk_colsum, (size_t)(p->kmax + 1)));
+    CK(dalloc_t(p, &p->bk_coef, (size_t)(p->kmax + 1) * kMaxBlockQ));
   }
   // ---- workspace of optional solve features, reserved here so that no later
   // call allocates: block rank step, L-BFGS rings, the BF16 ladder's float factor
@@ -1071,25 +1077,6 @@ static void tri_eigvec(const std::vector<double>& a, const std::vector<double>& 
   }
 }
 
-// (k+1)-th smallest eigenvalue of the symmetric tridiagonal by bisection on
-// the Sturm count.
-static double tri_kth_eig(const std::vector<double>& a, const std::vector<double>& b, int m, int k) {
-  double lo = INFINITY, hi = -INFINITY;
-  for (int i = 0; i < m; ++i) {
-    const double rad = (i > 0 ? std::fabs(b[i - 1]) : 0.0) + (i + 1 < m ? std::fabs(b[i]) : 0.0);
-    lo = std::min(lo, a[i] - rad);
-    hi = std::max(hi, a[i] + rad);
-  }
-  const double scale = std::max(std::fabs(lo), std::fabs(hi));
-  for (int it = 0; it < 300; ++it) {
-    const double mid = 0.5 * (lo + hi);
-    if (hi - lo <= 2.0 * DBL_EPSILON * scale || mid <= lo || mid >= hi) break;
-    if (sturm_count(a, b, m, mid) >= k + 1) hi = mid;
-    else lo = mid;
-  }
-  return 0.5 * (lo + hi);
-}
-
 // Eigen-decomposition of a small symmetric q x q matrix (row-major) by cyclic
 // Jacobi rotations: A = U diag(lam) U^T, U row-major with eigenvectors in columns.
 static void small_sym_eig(int q, std::vector<double> A, std::vector<double>& lam, std::vector<double>& U) {
@@ -1357,6 +1344,156 @@ extern "C" alm_bm_status alm_bm_lanczos_min_eig(alm_bm_problem* p, const double*
   return ALM_BM_OK;
 }
 
+// --------------------------------------------------------------------- block Krylov
+
+// The q smallest Ritz pairs of Z(y) from the block Krylov space
+// span{V0, Z V0, Z^2 V0, ...} (V0: q counter-based random vectors), m <=
+// kmax + 1 orthonormal columns.  The columns are built one at a time: column c
+// is Z q_{c-q} orthogonalised against columns 0..c-1 (two classical
+// Gram-Schmidt passes) and normalised, which is the block Lanczos recurrence
+// with full reorthogonalisation.  The first-pass coefficients are the entries
+// q_i^T Z q_j (i <= j) of H = Q^T Z Q; the last q columns take one more
+// product each.  The host diagonalises H and V = Q U for the q smallest
+// eigenvalues.  Unlike a single Krylov vector, a block of q vectors spans a
+// whole eigenspace of multiplicity up to q.  theta: ascending Ritz values;
+// V: device n x q column-major (unit, orthonormal); resid (optional): Ritz
+// residuals ||Z v - theta v||, one product each.
+static alm_bm_status block_krylov(alm_bm_problem* p, const double* y, int q, int kmax, uint64_t seed,
+                                  std::vector<double>& theta, double* V, std::vector<double>* resid, int& m_out,
+                                  hipStream_t st) {
+  const auto& d = p->d;
+  const long n = d.n, ldq = n;
+  const int nb = p->lnb, pstride = p->kmax + 1, ld = p->kmax + 1;
+  kmax = std::min(kmax, p->kmax);
+  const int m = (int)std::min<long>(kmax + 1, n);
+  if (q < 1 || q > kMaxBlockQ) return fail(ALM_BM_ERR_INVALID_ARG, "block Lanczos: q must be in 1..8");
+  if (kmax < 1 || m < q + 1) return fail(ALM_BM_ERR_INVALID_ARG, "block Lanczos: basis smaller than q + 1");
+  double* qsum = (d.j_coef != 0.0) ? &p->sc_api->qsum : nullptr;
+  const int cons = d.cons_kind == ALM_BM_CONS_DIAG ? 0 : 1;
+  // lw against columns 0..c-1 (two passes; partial ||lw||^2 left in lpart2)
+  auto second_pass = [&](int c) {
+    launch_dots(n, c, p->Q, ldq, p->lw, p->lpart, pstride, nb, p->lh2, st);
+    launch_sub(n, c, p->Q, ldq, p->lh2, p->lw, p->lpart2, nb, st);
+  };
+  auto normalise_into = [&](int c) -> alm_bm_status {
+    launch_fin_sum(p->lpart2, nb, p->lscal, 1, st);
+    launch_scale(n, p->lw, p->lscal, p->Q + (long)c * ldq, p->lpart2, nb, qsum, st);
+    if (qsum) HIPCHK(hipMemcpyAsync(p->bk_colsum + c, qsum, sizeof(double), hipMemcpyDeviceToDevice, st));
+    return ALM_BM_OK;
+  };
+  auto product = [&](int j) -> alm_bm_status {
+    if (qsum) HIPCHK(hipMemcpyAsync(qsum, p->bk_colsum + j, sizeof(double), hipMemcpyDeviceToDevice, st));
+    launch_slack_mv(p->C64, cons, p->adj, y, d.trace_coef, d.j_coef, p->sc_api, p->Q + (long)j * ldq, p->lw, st);
+    return ALM_BM_OK;
+  };
+  for (int i = 0; i < q; ++i) {
+    launch_rand(n, seed * 1000003ull + (uint64_t)i, p->lw, p->lpart2, nb, st);
+    if (i > 0) {
+      launch_dots(n, i, p->Q, ldq, p->lw, p->lpart, pstride, nb, p->lh1, st);
+      launch_sub(n, i, p->Q, ldq, p->lh1, p->lw, p->lpart2, nb, st);
+      second_pass(i);
+    }
+    STCHK(normalise_into(i));
+  }
+  for (int c = q; c < m; ++c) {
+    const int j = c - q;
+    STCHK(product(j));
+    launch_dots(n, c, p->Q, ldq, p->lw, p->lpart, pstride, nb, p->lh1, st);
+    HIPCHK(hipMemcpyAsync(p->bk_h + (long)j * ld, p->lh1, c * sizeof(double), hipMemcpyDeviceToDevice, st));
+    launch_sub(n, c, p->Q, ldq, p->lh1, p->lw, p->lpart2, nb, st);
+    second_pass(c);
+    launch_fin_sum(p->lpart2, nb, p->lscal, 1, st);
+    // the new column's norm before scaling: H[c][j] (breakdown test)
+    HIPCHK(hipMemcpyAsync(p->bk_h + (long)j * ld + c, p->lscal, sizeof(double), hipMemcpyDeviceToDevice, st));
+    launch_scale(n, p->lw, p->lscal, p->Q + (long)c * ldq, p->lpart2, nb, qsum, st);
+    if (qsum) HIPCHK(hipMemcpyAsync(p->bk_colsum + c, qsum, sizeof(double), hipMemcpyDeviceToDevice, st));
+  }
+  for (int j = m - q; j < m; ++j) {
+    STCHK(product(j));
+    launch_dots(n, m, p->Q, ldq, p->lw, p->lpart, pstride, nb, p->lh1, st);
+    HIPCHK(hipMemcpyAsync(p->bk_h + (long)j * ld, p->lh1, m * sizeof(double), hipMemcpyDeviceToDevice, st));
+  }
+  std::vector<double> Hd((size_t)ld * m), cs(m, 0.0);
+  HIPCHK(hipMemcpyAsync(Hd.data(), p->bk_h, Hd.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+  if (qsum) HIPCHK(hipMemcpyAsync(cs.data(), p->bk_colsum, m * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  // the basis ends before the first column whose unnormalised norm vanished
+  // (an invariant subspace): later columns are normalised rounding noise
+  double hmax = 0.0;
+  for (int j = 0; j < m; ++j)
+    for (int i = 0; i <= j; ++i) hmax = std::max(hmax, std::fabs(Hd[(size_t)j * ld + i]));
+  int mm = m;
+  for (int c = q; c < m; ++c) {
+    const double beta = Hd[(size_t)(c - q) * ld + c];
+    if (!(beta > 1e-12 * std::max(hmax, 1e-300))) {
+      mm = c;
+      break;
+    }
+  }
+  std::vector<double> Hs((size_t)mm * mm);
+  for (int j = 0; j < mm; ++j)
+    for (int i = 0; i <= j; ++i) {
+      const double h = Hd[(size_t)j * ld + i];
+      if (!std::isfinite(h)) return fail(ALM_BM_ERR_NUMERIC, "block Lanczos: NaN/Inf");
+      Hs[(size_t)i * mm + j] = Hs[(size_t)j * mm + i] = h;
+    }
+  std::vector<double> lam, U;
+  small_sym_eig(mm, Hs, lam, U);
+  std::vector<int> ord(mm);
+  for (int k = 0; k < mm; ++k) ord[k] = k;
+  std::sort(ord.begin(), ord.end(), [&](int a, int b) { return lam[a] < lam[b]; });
+  const int qv = std::min(q, mm);
+  theta.assign(qv, 0.0);
+  std::vector<double> coef((size_t)qv * mm);
+  for (int k = 0; k < qv; ++k) {
+    theta[k] = lam[ord[k]];
+    for (int i = 0; i < mm; ++i) coef[(size_t)k * mm + i] = U[(size_t)i * mm + ord[k]];
+  }
+  HIPCHK(hipMemcpyAsync(p->bk_coef, coef.data(), coef.size() * sizeof(double), hipMemcpyHostToDevice, st));
+  for (int k = 0; k < qv; ++k)
+    launch_combine(n, mm, p->Q, ldq, p->bk_coef + (long)k * mm, V + (long)k * n, p->lpart2, nb, st);
+  if (resid) {
+    resid->assign(qv, 0.0);
+    for (int k = 0; k < qv; ++k) {
+      double qs = 0.0;  // 1^T v for the -J term, from the columns' sums
+      for (int i = 0; i < mm; ++i) qs += coef[(size_t)k * mm + i] * cs[i];
+      if (qsum) HIPCHK(hipMemcpyAsync(qsum, &qs, sizeof(double), hipMemcpyHostToDevice, st));
+      launch_slack_mv(p->C64, cons, p->adj, y, d.trace_coef, d.j_coef, p->sc_api, V + (long)k * n, p->lw, st);
+      launch_resid(n, p->lw, V + (long)k * n, theta[k], nullptr, p->lpart2, nb, st);
+      launch_fin_sum(p->lpart2, nb, p->lscal + 2, 1, st);
+      HIPCHK(hipMemcpyAsync(&(*resid)[k], p->lscal + 2, sizeof(double), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));  // qs and the result are host values of this iteration
+    }
+  }
+  HIPCHK(hipStreamSynchronize(st));
+  HIPCHK(hipGetLastError());
+  m_out = mm;
+  return ALM_BM_OK;
+}
+
+extern "C" alm_bm_status alm_bm_lanczos_block(alm_bm_problem* p, const double* y, int32_t q, int32_t max_iter,
+                                             uint64_t seed, double* theta, double* V, double* resid,
+                                             int32_t* basis, hipStream_t st) {
+  if (!p || !y || !theta) return fail(ALM_BM_ERR_INVALID_ARG, "lanczos_block: null argument");
+  if (q < 1 || q > kMaxBlockQ) return fail(ALM_BM_ERR_INVALID_ARG, "lanczos_block: q must be in 1..8");
+  if (max_iter < 1 || max_iter > p->kmax)
+    return fail(ALM_BM_ERR_INVALID_ARG, "lanczos_block: max_iter must be in 1..lanczos_kmax");
+  if (std::min<long>(max_iter + 1, p->d.n) < q + 1)
+    return fail(ALM_BM_ERR_INVALID_ARG, "lanczos_block: basis (min(max_iter + 1, n)) must exceed q");
+  if (!V && (!p->vblk || q > p->d.rank_block_max))
+    return fail(ALM_BM_ERR_INVALID_ARG, "lanczos_block: V is required unless rank_block_max >= q");
+  HIPCHK(hipStreamSynchronize(st));
+  std::vector<double> th, rs;
+  int m = 0;
+  STCHK(block_krylov(p, y, q, max_iter, seed, th, V ? V : p->vblk, resid ? &rs : nullptr, m, st));
+  for (int k = 0; k < q; ++k) {
+    theta[k] = k < (int)th.size() ? th[k] : NAN;
+    if (resid) resid[k] = k < (int)rs.size() ? rs[k] : NAN;
+  }
+  if (basis) *basis = m;
+  return ALM_BM_OK;
+}
+
 // --------------------------------------------------------------------- KKT
 
 struct KktVals {
@@ -1597,38 +1734,17 @@ static alm_bm_status block_rank_step(alm_bm_problem* p, T* R, int& r, int& w, in
   if (q < 1) return ALM_BM_OK;
   if (!p->vblk || rank_block > d.rank_block_max)
     return fail(ALM_BM_ERR_INVALID_ARG, "block rank step: rank_block exceeds the handle's rank_block_max");
-  LanczosOut lf;
-  STCHK(lanczos_pass(p, p->ybuf, kmax, 0.0, seed, false, p->lv, lf, st));
-  const int m = lf.iters;
-  std::vector<double> ha(m), hb(m);
-  HIPCHK(hipMemcpyAsync(ha.data(), p->lalpha, m * sizeof(double), hipMemcpyDeviceToHost, st));
-  HIPCHK(hipMemcpyAsync(hb.data(), p->lbeta, m * sizeof(double), hipMemcpyDeviceToHost, st));
-  HIPCHK(hipStreamSynchronize(st));
-  std::vector<double> th;
-  std::vector<double> Y;  // column j at j * m
-  for (int k = 0; k < std::min(q, m); ++k) {
-    const double t = tri_kth_eig(ha, hb, m, k);
-    if (!(t < -tau_rank)) break;
-    std::vector<double> z;
-    tri_eigvec(ha, hb, m, t, z);
-    for (size_t j = 0; j < th.size(); ++j) {  // keep the Ritz vectors orthonormal (close Ritz values)
-      double s = 0.0;
-      for (int i = 0; i < m; ++i) s += z[i] * Y[j * m + i];
-      for (int i = 0; i < m; ++i) z[i] -= s * Y[j * m + i];
-    }
-    double nz = 0.0;
-    for (double v : z) nz += v * v;
-    nz = std::sqrt(nz);
-    if (!(nz > 1e-8)) break;
-    for (double& v : z) v /= nz;
-    th.push_back(t);
-    Y.insert(Y.end(), z.begin(), z.end());
-  }
-  const int qv = (int)th.size();
+  // the q smallest Ritz pairs of a block Krylov space of block size q (a
+  // repeated eigenvalue contributes its whole eigenspace), V into vblk
+  const int qk = (int)std::min<long>(q, std::min<long>(std::min(kmax, p->kmax) + 1, n) - 1);
+  if (qk < 1) return ALM_BM_OK;
+  std::vector<double> thb;
+  int m = 0;
+  STCHK(block_krylov(p, p->ybuf, qk, kmax, seed, thb, p->vblk, nullptr, m, st));
+  int qv = 0;
+  while (qv < (int)thb.size() && thb[qv] < -tau_rank) ++qv;
   if (qv == 0) return ALM_BM_OK;
-  HIPCHK(hipMemcpyAsync(p->ycoef, Y.data(), Y.size() * sizeof(double), hipMemcpyHostToDevice, st));
-  for (int j = 0; j < qv; ++j)
-    launch_combine(n, m, p->Q, n, p->ycoef + (long)j * m, p->vblk + (long)j * n, p->lpart2, p->lnb, st);
+  const std::vector<double> th(thb.begin(), thb.begin() + qv);
   const int np = qv * (qv + 1) / 2;
   std::vector<double> M4;
   STCHK(block_moments(p, qv, p->vblk, p->rho, M4, st));

@@ -24,6 +24,7 @@ enum PartialSlot {
 };
 
 constexpr int kMaxR = 128;
+constexpr int kMaxBlockQ = 8;  // block size of the block Krylov eigensolver
 
 // Device-resident scalars of one handle.  Written by finalize kernels so that
 // the inner loop needs no host round trip; the host reads them after syncs.
