@@ -522,7 +522,8 @@ def solve_legs(g, args):
         log(f"[bench] solve leg {name}")
         ps = almbm.Problem.maxcut(g.n, g.ei, g.ej, g.w, precision=pm, r_max=64, lanczos_kmax=60, device="cuda:0",
                                   validate=False, lbfgs_memory_max=args.lbfgs_memory if lbfgs else 0)
-        opts = dict(eps_kkt=1e-4, sigma=args.sigma, max_inner=max_inner, time_limit_s=args.solve_time_limit,
+        limit = args.solve_time_limit_f64 if pm == "f64" else args.solve_time_limit
+        opts = dict(eps_kkt=1e-4, sigma=args.sigma, max_inner=max_inner, time_limit_s=limit,
                     verbose=1, inner_solver=1 if lbfgs else 0, lbfgs_memory=args.lbfgs_memory)
         if args.sigma_growth != 1.0:
             opts["sigma_growth"] = args.sigma_growth
@@ -563,8 +564,8 @@ def solve_legs(g, args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--precision", default="bf16", choices=["bf16", "f32", "f64"])
     ap.add_argument("--n", type=int, default=10_000_000)
     ap.add_argument("--deg", type=float, default=8.0)
@@ -577,6 +578,8 @@ def main():
                     help="comma list of solve legs: f64 (FP64 default start), default (bench precision, default "
                          "start), learned (bench precision, learned warm start)")
     ap.add_argument("--solve-time-limit", type=float, default=120.0)
+    ap.add_argument("--solve-time-limit-f64", type=float, default=240.0,
+                    help="time limit of the FP64 solve leg (its steps at width 64 cost about 2.5x the float ones)")
     ap.add_argument("--sigma", type=float, default=16.0, help="penalty of the --solve leg")
     ap.add_argument("--refresh-every", type=int, default=0,
                     help="inner steps between full sparse evaluations (0: the library default for the precision)")
