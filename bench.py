@@ -497,6 +497,19 @@ def certified_bracket(pb, Rf, yf, lanczos_steps=200):
             "theta_resid": resid, "lanczos_steps": iters}
 
 
+def fp64_check(pb, Rf, leg):
+    """<C, RR^T> and the primal infeasibility of the returned factor evaluated in
+    FP64 (handle pb), against the values the solve reported in its precision."""
+    import torch
+
+    R64 = Rf.to(dtype=torch.float64).contiguous()
+    zero = torch.zeros(pb.n, dtype=torch.float64, device=R64.device)
+    f, _, Av = pb.objective_grad(R64, zero, 0.0, want_G=False)
+    pobj = f.item()
+    pinf = float(torch.linalg.norm(Av - 1.0).item()) / (1.0 + pb.n ** 0.5)
+    return {"pobj": pobj, "rel_pobj_diff_vs_reported": abs(pobj - leg["pobj"]) / abs(pobj), "pinf": pinf}
+
+
 def solve_legs(g, args):
     """Solves to 1e-4 relative KKT on the benchmark graph (the metric's third
     part): FP64 from the default start (R0 of rank r with unit rows, y = 0),
@@ -542,7 +555,12 @@ def solve_legs(g, args):
                      "inner_solver": args.inner, "lbfgs_memory": args.lbfgs_memory if lbfgs else None,
                      **{k: res[k] for k in keys}, **extra}
         log(f"[bench] {name}: {out[name]}")
-        finals[name] = (Rf.clone(), yf.clone())
+        if pm == "bf16" and res["promoted_at_outer"] >= 0:
+            # the point the solve certified is its float factor (R holds it rounded to BF16)
+            finals[name] = (ps.ladder_factor(res["rank"]), yf.clone())
+            out[name]["factor"] = "float (after the ladder)"
+        else:
+            finals[name] = (Rf.clone(), yf.clone())
         ps.close()
         del ps, Rf, yf
         torch.cuda.empty_cache()
@@ -551,7 +569,8 @@ def solve_legs(g, args):
                                   device="cuda:0", validate=False)
         for name, (Rf, yf) in finals.items():
             out[name]["bracket"] = certified_bracket(pb, Rf, yf)
-            log(f"[bench] {name} bracket: {out[name]['bracket']}")
+            out[name]["fp64_check"] = fp64_check(pb, Rf, out[name])
+            log(f"[bench] {name} bracket: {out[name]['bracket']} fp64 check: {out[name]['fp64_check']}")
         pb.close()
         ref = out.get("f64_default_start")
         if ref:

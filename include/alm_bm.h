@@ -339,7 +339,12 @@ alm_bm_status alm_bm_inner_solve(alm_bm_problem* prob, const alm_bm_options* opt
  * the returned *r).  r: host in/out.  y: device m, in/out (start and final dual).
  * opts: host, NULL = defaults.  out: host, nullable.  Synchronous.
  * Returns ALM_BM_OK when the KKT measure met eps_kkt, ALM_BM_NOT_CONVERGED when
- * max_outer or the time limit ran out (outputs still valid).                   */
+ * max_outer or the time limit ran out (outputs still valid).
+ * A BF16 handle whose solve switched to float storage (bf16_promote,
+ * out->promoted_at_outer >= 0) measured and certified its float factor; R
+ * receives that factor rounded to BF16, whose row norms are off by up to about
+ * 2^-8 relative, so A(RR^T) - b there can exceed the tolerance.  The float
+ * factor itself is available from alm_bm_ladder_factor.                       */
 alm_bm_status alm_bm_solve(alm_bm_problem* prob, const alm_bm_options* opts, void* R,
                            int32_t* r, double* y, alm_bm_result* out, hipStream_t stream);
 
@@ -438,6 +443,13 @@ alm_bm_status alm_bm_batch_solve(alm_bm_batch* batch, const alm_bm_options* opts
 #define ALM_BM_BATCH_TUNE_MAX 16
 alm_bm_status alm_bm_batch_autotune(alm_bm_batch* batch, int32_t reps, int32_t* widths, int32_t* variants,
                                     int32_t* n_out, hipStream_t stream);
+
+/* The float factor of the last alm_bm_solve on this BF16 handle that switched to
+ * float storage (the point its KKT measure and status refer to).  r: the rank
+ * that solve returned; R: device n x r floats, row-major (caller-owned).  Valid
+ * until the next alm_bm_solve on the handle; INVALID_ARG when the last solve did
+ * not switch or r differs.  Enqueued on stream.                               */
+alm_bm_status alm_bm_ladder_factor(alm_bm_problem* prob, int32_t r, float* R, hipStream_t stream);
 
 /* Relative KKT measure of Sec. 6 at (RR^T, y) with lambda_min supplied by the
  * caller (host double); kkt_out: host array of 6 doubles

@@ -279,6 +279,13 @@ class Problem:
                                          _ptr(rs), _ptr(it), _stream(stream)), "lanczos_min_eig")
         return float(th.item()), v, float(rs.item()), int(it.item())
 
+    def ladder_factor(self, r, stream=None):
+        """Float factor (n x r, device) of the last solve on this BF16 handle that
+        switched to float storage: the point its status and KKT values refer to."""
+        R = torch.empty((self.n, int(r)), dtype=torch.float32, device=self.device)
+        check(lib.alm_bm_ladder_factor(self._h, int(r), _ptr(R), _stream(stream)), "ladder_factor")
+        return R
+
     def lanczos_block(self, y, q, max_iter=60, seed=1, stream=None):
         """(theta[q] host, V n x q device column-major, resid[q] host, basis size)
         for the q smallest eigenpairs of C - A*(y) by block Lanczos."""

@@ -129,7 +129,7 @@ EXPORTS = [
     "alm_bm_inner_solve", "alm_bm_ws_features", "alm_bm_ws_pool", "alm_bm_ws_param_count", "alm_bm_ws_work_size",
     "alm_bm_ws_forward", "alm_bm_ws_loss_grad", "alm_bm_ws_adam", "alm_bm_ws_ridge_fit",
     "alm_bm_batch_create", "alm_bm_batch_destroy", "alm_bm_batch_offsets", "alm_bm_batch_solve",
-    "alm_bm_batch_autotune", "alm_bm_lanczos_block",
+    "alm_bm_batch_autotune", "alm_bm_lanczos_block", "alm_bm_ladder_factor",
     "alm_bm_objective_grad_noalloc", "alm_bm_block_moments", "alm_bm_gather_probe", "alm_bm_gather_probe_out_size",
 ]
 
@@ -180,6 +180,7 @@ def _load():
         "alm_bm_batch_solve": (i32, [vp, C.POINTER(Options), vp, vp, vp, vp, vp, vp]),
         "alm_bm_batch_autotune": (i32, [vp, i32, vp, vp, C.POINTER(i32), vp]),
         "alm_bm_lanczos_block": (i32, [vp, vp, i32, i32, C.c_uint64, vp, vp, vp, C.POINTER(i32), vp]),
+        "alm_bm_ladder_factor": (i32, [vp, i32, vp, vp]),
         "alm_bm_inner_solve": (i32, [vp, C.POINTER(Options), i32, vp, vp, f64, i32, C.POINTER(i32), C.POINTER(i32),
                                      C.POINTER(f64), vp]),
         "alm_bm_autotune": (i32, [vp, i32, i32, C.POINTER(i32), C.POINTER(i32), vp]),

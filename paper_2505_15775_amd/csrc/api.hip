@@ -69,6 +69,7 @@ struct alm_bm_problem {
   void* G = nullptr;              // n * r_max storage
   void* Rtmp = nullptr;           // n * r_max storage
   void* Qbuf = nullptr;           // n * r_max arithmetic type: C G of the inner loop
+  int ladder_r = 0;               // rank of the float factor in R32 after a promoted solve (0: none)
   void* R32 = nullptr;            // float factor, gradient and relayout scratch for
   void* G32 = nullptr;            //   the BF16 -> float precision ladder
   void* Rt32 = nullptr;
@@ -2005,6 +2006,7 @@ extern "C" alm_bm_status alm_bm_solve(alm_bm_problem* p, const alm_bm_options* o
   acc.sigma_final = sigma;
   bool stalled = false;
   alm_bm_status s;
+  p->ladder_r = 0;
   if (p->d.precision == ALM_BM_BF16 && o.bf16_promote) {
     bf16* Rb = static_cast<bf16*>(R);
     STCHK(restride<bf16>(p, Rb, r, r, w, st));
@@ -2029,6 +2031,7 @@ extern "C" alm_bm_status alm_bm_solve(alm_bm_problem* p, const alm_bm_options* o
       launch_convert<float, bf16>((long)n * r, Rf, Rb, st);
       HIPCHK(hipStreamSynchronize(st));
       if (s < 0) return s;
+      p->ladder_r = r;  // the certified point stays in R32 (alm_bm_ladder_factor)
     } else {
       STCHK(restride<bf16>(p, Rb, w, r, r, st));
       if (s < 0) return s;
@@ -2050,6 +2053,15 @@ extern "C" alm_bm_status alm_bm_solve(alm_bm_problem* p, const alm_bm_options* o
   acc.time_s = now_s() - t0;
   if (out) *out = acc;
   return s;
+}
+
+extern "C" alm_bm_status alm_bm_ladder_factor(alm_bm_problem* p, int32_t r, float* R, hipStream_t st) {
+  if (!p || !R) return fail(ALM_BM_ERR_INVALID_ARG, "ladder_factor: null argument");
+  if (p->d.precision != ALM_BM_BF16 || p->ladder_r <= 0)
+    return fail(ALM_BM_ERR_INVALID_ARG, "ladder_factor: the last solve did not switch to float storage");
+  if (r != p->ladder_r) return fail(ALM_BM_ERR_INVALID_ARG, "ladder_factor: r differs from the solve's rank");
+  HIPCHK(hipMemcpyAsync(R, p->R32, (size_t)p->d.n * r * sizeof(float), hipMemcpyDeviceToDevice, st));
+  return ALM_BM_OK;
 }
 
 // ===================================================================== batched solves

@@ -177,6 +177,38 @@ def test_solve_mixed_precision_reports_error(prec):
     assert st == 0 and err <= 2e-4
 
 
+def test_bf16_ladder_factor_is_the_certified_point():
+    """A BF16 solve to 1e-5 has to switch to float storage (BF16 rounding of R
+    alone moves A(RR^T) by about 2^-9 per row).  Its status and KKT values refer
+    to the float factor, which alm_bm_ladder_factor returns: the oracle's KKT
+    measure with the exact lambda_min at that factor meets the tolerance, while
+    the BF16 copy left in R is farther from feasibility."""
+    g = gen.er_graph(2000, 10000, 1, "unit")
+    po = oracle.maxcut_sdp(g)
+    prob = _maxcut(g, prec="bf16", r_max=64, kmax=100)
+    st, res, R, y = prob.solve(gen.init_factor(2000, 8, 1), eps_kkt=1e-5, sigma=1.0, max_outer=400)
+    print(f"status {st} outer {res['outer']} promoted at {res['promoted_at_outer']} kkt {res['kkt']:.2e}")
+    assert st == 0 and res["promoted_at_outer"] >= 0
+    Rf = prob.ladder_factor(res["rank"])
+    assert Rf.dtype == torch.float32 and tuple(Rf.shape) == (2000, res["rank"])
+    yh = y.cpu().numpy()
+    lam = oracle.min_eig(po, yh)
+    kf = oracle.kkt(po, Rf.double().cpu().numpy(), yh, lam_min=lam)
+    kb = oracle.kkt(po, R.double().cpu().numpy(), yh, lam_min=lam)
+    print(f"oracle at the float factor: kkt {kf['kkt']:.2e} (pinf {kf['pinf']:.2e}); "
+          f"at the BF16 copy: kkt {kb['kkt']:.2e} (pinf {kb['pinf']:.2e})")
+    assert kf["kkt"] <= 1.5e-5
+    assert kb["pinf"] > kf["pinf"]
+    assert np.allclose(R.float().cpu().numpy(), Rf.to(torch.bfloat16).float().cpu().numpy())
+    with pytest.raises(almbm().AlmBmError):
+        prob.ladder_factor(res["rank"] + 1)
+    prob.close()
+    p64 = _maxcut(g, r_max=16, kmax=20)
+    with pytest.raises(almbm().AlmBmError):
+        p64.ladder_factor(4)
+    p64.close()
+
+
 @pytest.mark.parametrize("n,expect", [(5, math.sqrt(5.0)), (7, 7 * math.cos(math.pi / 7) / (1 + math.cos(math.pi / 7)))])
 def test_solve_lovasz_theta_cycles_with_edge_penalty(n, expect):
     g = gen.cycle_graph(n)
