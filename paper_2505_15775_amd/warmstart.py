@@ -330,14 +330,17 @@ def _held_out_errors(model, feats, targets, pools, ns, ranks):
 
 
 def ablation(graphs, model, eps=1e-5, sigma=16.0, r_default=16, log=None):
-    """Solves of each graph from four starts: the default (y = 0, rank 16), the
-    learned y0 at rank 16, y = 0 at the learned r0, and both (solve_warm's
-    start, without its fallback test).  L-BFGS subproblems of at most 100
-    steps.  Returns per-start totals of outer iterations and seconds."""
+    """Solves of each graph from five starts: the default (y = 0, rank 16), the
+    learned y0 at rank 16, y = 0 at the learned r0, both (solve_warm's start,
+    without its fallback test), and the Gershgorin dual-feasible start
+    y0_i = C_ii - sum_j |C_ij| (feature 4) at rank 16 as a comparator.  L-BFGS
+    subproblems of at most 100 steps.  Returns per-start totals of outer
+    iterations and seconds."""
     import gen
 
     opts = dict(eps_kkt=eps, sigma=sigma, max_outer=300, inner_solver=1, lbfgs_memory=3, max_inner=100)
-    tot = {k: {"outer": 0, "time_s": 0.0, "converged": 0} for k in ("default", "y0_only", "r0_only", "both")}
+    tot = {k: {"outer": 0, "time_s": 0.0, "converged": 0}
+           for k in ("default", "y0_only", "r0_only", "both", "gershgorin")}
     for g in graphs:
         prob = Problem.maxcut(g.n, g.ei, g.ej, g.w, precision="f64", r_max=64, lanczos_kmax=60, validate=False,
                               lbfgs_memory_max=3)
@@ -345,8 +348,9 @@ def ablation(graphs, model, eps=1e-5, sigma=16.0, r_default=16, log=None):
         y0 = model.predict_y0(prob, F)
         r0 = model.predict_r0(pooled(F), g.n, prob.r_max)
         line = f"[warmstart] ablation n={g.n} r0={r0}:"
+        y_gersh = F[:, 4].double().contiguous()
         for k, (r, yy) in {"default": (r_default, None), "y0_only": (r_default, y0), "r0_only": (r0, None),
-                           "both": (r0, y0)}.items():
+                           "both": (r0, y0), "gershgorin": (r_default, y_gersh)}.items():
             st, res, _, _ = prob.solve(gen.init_factor(g.n, r, 1), yy, **opts)
             tot[k]["outer"] += res["outer"]
             tot[k]["time_s"] += res["time_s"]
@@ -377,13 +381,24 @@ def main():
     c.add_argument("--sigma", type=float, default=16.0)
     c.add_argument("--ablation", type=int, default=12, help="held-out graphs solved from the four starts")
     c.add_argument("--out", default=None, help="save the model fitted on the whole training part here")
+    a = sub.add_parser("ablation", help="the start ablation alone, for a saved model")
+    a.add_argument("--count", type=int, default=600, help="size of the seeded set whose first tenth is held out")
+    a.add_argument("--seed", type=int, default=6)
+    a.add_argument("--graphs", type=int, default=12)
+    a.add_argument("--sigma", type=float, default=16.0)
+    a.add_argument("--model", default=MODEL_PATH)
     args = ap.parse_args()
 
     def log(s):
         print(s, file=sys.stderr, flush=True)
 
-    graphs = training_graphs(args.count, args.seed)
     n_hold = max(1, args.count // 10)
+    if args.cmd == "ablation":
+        graphs = training_graphs(min(args.graphs, n_hold), args.seed)  # the first graphs are the held-out ones
+        abl = ablation(graphs, WarmStartModel.load(args.model), sigma=args.sigma, log=log)
+        print(json.dumps({"ablation": abl}), flush=True)
+        return
+    graphs = training_graphs(args.count, args.seed)
     t0 = time.time()
     if args.cmd == "train":
         gen_set = generate_training_set_batched if args.batched else generate_training_set
