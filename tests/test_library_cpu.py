@@ -139,6 +139,8 @@ def test_set_tiles_rejects_bad_values_without_device():
 
     assert _lib.lib.alm_bm_set_tiles(None, 0, 0) == -1
     assert _lib.lib.alm_bm_batch_autotune(None, 3, None, None, None, None) == -1
+    assert _lib.lib.alm_bm_lanczos_block(None, None, 2, 5, 1, None, None, None, None, None) == -1
+    assert _lib.lib.alm_bm_ladder_factor(None, 4, None, None) == -1
 
 
 def _pairs(q):
