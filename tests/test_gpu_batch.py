@@ -199,3 +199,27 @@ def test_batch_lbfgs_rejects_memory_beyond_reservation():
     with pytest.raises(m.AlmBmError):
         batch.solve([gen.init_factor(g.n, r, 1) for g, r in insts], inner_solver=1, lbfgs_memory=3)
     batch.close()
+
+
+def test_batch_lbfgs_float_storage_with_bfloat16_rings():
+    """FP32 storage (L-BFGS rings in BF16, the line-search product gathering the
+    BF16 direction): the batch converges, and each instance's objective agrees
+    with its own single FP32 L-BFGS solve to what 1e-5 KKT fixes."""
+    insts = _instances()[:6]
+    m = _almbm()
+    probs = [m.Problem.maxcut(g.n, g.ei, g.ej, g.w, precision="f32", r_max=48, lanczos_kmax=60, device=DEV,
+                              lbfgs_memory_max=3) for g, _ in insts]
+    batch = m.Batch(probs, rank_stride=48)
+    factors = [gen.init_factor(g.n, r, 1) for g, r in insts]
+    opts = dict(eps_kkt=1e-5, max_outer=300, inner_solver=1, lbfgs_memory=3, max_inner=100)
+    st, sts, res, R, ranks, y = batch.solve(factors, **opts)
+    print(f"f32 batch L-BFGS: status {st} {sts} outer {[x['outer'] for x in res]} ranks {ranks}")
+    assert st == 0 and all(s == 0 for s in sts)
+    for q, p in enumerate(probs):
+        s1, r1, _, _ = p.solve(factors[q], **opts)
+        assert s1 == 0
+        print(f"instance {q}: batch {res[q]['pobj']:.8f} single {r1['pobj']:.8f}")
+        assert abs(res[q]["pobj"] - r1["pobj"]) <= 5e-5 * abs(r1["pobj"])
+    batch.close()
+    for p in probs:
+        p.close()
