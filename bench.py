@@ -608,9 +608,12 @@ def main():
                     help="gradient steps per subproblem in the solve legs (0: 100 for L-BFGS, 500 for GD)")
     ap.add_argument("--inner", default="lbfgs", choices=["lbfgs", "gd"], help="subproblem solver of the solve legs")
     ap.add_argument("--lbfgs-memory", type=int, default=3, help="L-BFGS pairs kept")
-    ap.add_argument("--batch", type=int, default=0, help="also the batched solve of this many instances vs a loop")
+    ap.add_argument("--batch", type=int, default=256,
+                    help="batched solve of this many uneven instances (0: skip); --batch-loop adds the per-instance loop")
     ap.add_argument("--batch-eps", type=float, default=1e-4)
-    ap.add_argument("--batch-no-loop", action="store_true", help="skip the per-instance loop of the batch leg")
+    ap.add_argument("--batch-loop", action="store_true",
+                    help="also solve the batch's instances one by one (about 150 s at 256 instances)")
+    ap.add_argument("--batch-no-loop", action="store_true", help="(default) no per-instance loop")
     ap.add_argument("--only-batch", action="store_true",
                     help="run only the batch leg (--batch N) and print its JSON (profiling; no metric line)")
     ap.add_argument("--batch-no-tune", action="store_true", help="batch leg with the default tiles")
@@ -642,7 +645,8 @@ def main():
         if args.batch < 1:
             print("--only-batch needs --batch N", file=sys.stderr)
             sys.exit(2)
-        out = batch_leg(args.batch, args.batch_eps, args.sigma, "f64", loop=not args.batch_no_loop,
+        out = batch_leg(args.batch, args.batch_eps, args.sigma, "f64",
+                        loop=args.batch_loop and not args.batch_no_loop,
                         tune=not args.batch_no_tune, inner=args.batch_inner)
         print(json.dumps({"batched_solve": out}))
         return
@@ -705,7 +709,8 @@ def main():
         torch.cuda.empty_cache()
         solves = solve_legs(g, args)
 
-    batch = batch_leg(args.batch, args.batch_eps, args.sigma, "f64", loop=not args.batch_no_loop,
+    batch = batch_leg(args.batch, args.batch_eps, args.sigma, "f64",
+                      loop=args.batch_loop and not args.batch_no_loop,
                       tune=not args.batch_no_tune, inner=args.batch_inner) if args.batch > 0 else None
     other = kernels_leg(g) if args.kernels else None
     completion = completion_leg(sigma=args.completion_sigma) if args.completion else None
