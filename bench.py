@@ -617,6 +617,8 @@ def main():
     ap.add_argument("--only-batch", action="store_true",
                     help="run only the batch leg (--batch N) and print its JSON (profiling; no metric line)")
     ap.add_argument("--batch-no-tune", action="store_true", help="batch leg with the default tiles")
+    ap.add_argument("--batch-precision", choices=["f64", "f32"], default="f64",
+                    help="storage precision of the batch leg's instances")
     ap.add_argument("--batch-inner", choices=["lbfgs", "gd"], default="lbfgs",
                     help="subproblem solver of the batch leg (both the batch and the loop)")
     ap.add_argument("--kernels", action="store_true", help="also time the edge-family and warm-start kernels")
@@ -645,7 +647,7 @@ def main():
         if args.batch < 1:
             print("--only-batch needs --batch N", file=sys.stderr)
             sys.exit(2)
-        out = batch_leg(args.batch, args.batch_eps, args.sigma, "f64",
+        out = batch_leg(args.batch, args.batch_eps, args.sigma, args.batch_precision,
                         loop=args.batch_loop and not args.batch_no_loop,
                         tune=not args.batch_no_tune, inner=args.batch_inner)
         print(json.dumps({"batched_solve": out}))
@@ -709,7 +711,7 @@ def main():
         torch.cuda.empty_cache()
         solves = solve_legs(g, args)
 
-    batch = batch_leg(args.batch, args.batch_eps, args.sigma, "f64",
+    batch = batch_leg(args.batch, args.batch_eps, args.sigma, args.batch_precision,
                       loop=args.batch_loop and not args.batch_no_loop,
                       tune=not args.batch_no_tune, inner=args.batch_inner) if args.batch > 0 else None
     other = kernels_leg(g) if args.kernels else None
