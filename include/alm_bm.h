@@ -418,7 +418,11 @@ alm_bm_status alm_bm_autotune(alm_bm_problem* prob, int32_t r, int32_t reps, int
 typedef struct alm_bm_batch alm_bm_batch;
 
 /* descs: host array of count descriptors (device arrays as for alm_bm_create,
- * copied into the batch, so they may be freed afterwards).  1 <= count <= 4096. */
+ * copied into the batch, so they may be freed afterwards).  1 <= count <= 4096.
+ * DIAG family, one precision.  The largest lbfgs_memory_max among the
+ * descriptors reserves the L-BFGS rings of the batch ((sum n) x rank_stride
+ * elements per slot) and one L-BFGS state per instance; rank_block_max and
+ * hub_min_degree do not apply to batches.                                     */
 alm_bm_status alm_bm_batch_create(int32_t count, const alm_bm_problem_desc* descs, int32_t rank_stride,
                                   hipStream_t stream, alm_bm_batch** out);
 alm_bm_status alm_bm_batch_destroy(alm_bm_batch* batch);
@@ -426,7 +430,9 @@ alm_bm_status alm_bm_batch_destroy(alm_bm_batch* batch);
 alm_bm_status alm_bm_batch_offsets(const alm_bm_batch* batch, int64_t* offsets);
 /* R: device (sum n) x rank_stride in the storage precision (in/out); r: host
  * count ranks (in/out); y: device sum n doubles (in/out); results, status: host
- * count each (nullable).  opts as for alm_bm_solve (graph_unroll must be >= 1).
+ * count each (nullable).  opts as for alm_bm_solve (graph_unroll must be >= 1;
+ * inner_solver L-BFGS needs lbfgs_memory <= the reserved memory; the penalty
+ * schedule, rank_block > 1 and resume are for single solves: UNSUPPORTED).
  * Returns ALM_BM_OK when every instance met eps_kkt, else NOT_CONVERGED.        */
 alm_bm_status alm_bm_batch_solve(alm_bm_batch* batch, const alm_bm_options* opts, void* R, int32_t* r,
                                  double* y, alm_bm_result* results, int32_t* status, hipStream_t stream);
