@@ -46,6 +46,10 @@ def test_solve_cycles_closed_form(n):
     print(f"cycle {n}: status {st} value {val:.12f} expect {expect:.12f} outer {res['outer']} rank {res['rank']}")
     assert st == 0
     assert math.isclose(val, expect, rel_tol=1e-6)
+    # the solution's rank is rank(X*) (Sec. 3: 1 for even cycles, 2 for odd ones),
+    # whatever width the factor grew to: the numerical rank of R, not its width
+    sv = np.linalg.svd(R.cpu().numpy(), compute_uv=False)
+    assert int(np.sum(sv > 1e-2 * sv[0])) == (1 if n % 2 == 0 else 2)
 
 
 def test_solve_complete_graph_closed_form():

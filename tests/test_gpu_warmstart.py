@@ -120,11 +120,12 @@ def test_training_reduces_loss():
 def test_trained_warm_start_beats_default_start_on_held_out_graphs():
     """Held-out graphs (the first 10 % of the seeded training set, never used in
     training): outer iterations and wall time to 1e-5 relative KKT from the
-    learned start against the default start; objectives agree."""
+    learned start against the default start and against the Gershgorin
+    dual-feasible start; objectives agree."""
     ws = _ws()
     model = ws.WarmStartModel.load(device=DEV)
     graphs = ws.training_graphs(120, 6)[:4]
-    tot_d = tot_w = 0
+    tot_d = tot_w = tot_g = 0
     t_d = t_w = 0.0
     import paper_2505_15775_amd as almbm
 
@@ -133,6 +134,11 @@ def test_trained_warm_start_beats_default_start_on_held_out_graphs():
         prob = almbm.Problem.maxcut(g.n, g.ei, g.ej, g.w, precision="f64", r_max=64, lanczos_kmax=60, device=DEV)
         st, rd, _, _ = prob.solve(gen.init_factor(g.n, 16, 1), eps_kkt=1e-5, sigma=16.0, max_outer=300)
         stw, rw, _, _, info = ws.solve_warm(prob, model, eps_kkt=1e-5, sigma=16.0, max_outer=300)
+        # comparator: the Gershgorin dual-feasible start y0_i = C_ii - sum_j |C_ij| (feature 4)
+        yg = ws.features(prob)[:, 4].double().contiguous()
+        stg, rg, _, _ = prob.solve(gen.init_factor(g.n, 16, 1), yg, eps_kkt=1e-5, sigma=16.0, max_outer=300)
+        assert stg == 0
+        tot_g += rg["outer"]
         print(f"n={g.n}: default outer {rd['outer']} ({rd['time_s']:.2f}s) warm outer {rw['outer']} "
               f"({info['total_s']:.2f}s, r0 {info['r0']}, fallback {info['fallback']}) "
               f"pobj {rd['pobj']:.8e} vs {rw['pobj']:.8e}")
@@ -145,8 +151,9 @@ def test_trained_warm_start_beats_default_start_on_held_out_graphs():
         t_d += rd["time_s"]
         t_w += info["total_s"]
         prob.close()
-    print(f"total outer iterations: default {tot_d}, warm {tot_w}; time {t_d:.2f}s vs {t_w:.2f}s")
-    assert tot_w < tot_d
+    print(f"total outer iterations: default {tot_d}, warm {tot_w}, Gershgorin {tot_g}; "
+          f"time {t_d:.2f}s vs {t_w:.2f}s")
+    assert tot_w < tot_d and tot_w < tot_g
 
 
 @pytest.mark.parametrize("corrupt", ["nan", "huge"])
