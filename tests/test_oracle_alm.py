@@ -296,3 +296,21 @@ def test_lbfgs_and_gd_solves_agree_on_a_random_graph():
         vals[solver] = (val, sum(h["inner_iters"] for h in out["history"]))
     assert math.isclose(vals["gd"][0], vals["lbfgs"][0], rel_tol=1e-6)
     assert vals["lbfgs"][1] <= vals["gd"][1]
+
+
+def test_inner_gradient_descent_tail_is_log_linear():
+    """Sec. 4 (local linear convergence of gradient descent on the subproblem
+    under quadratic growth): started near a solution of the 9-cycle at a nearby
+    dual, the gradient norm of the exact-step descent falls by a roughly
+    constant factor per 25 steps (each factor < 0.5, largest / smallest < 3)."""
+    p = oracle.maxcut_sdp(gen.cycle_graph(9))
+    sol = oracle.solve(p, gen.init_factor(9, 2, 1), opts=oracle.SolveOptions(eps_kkt=1e-8, max_outer=400,
+                                                                              max_inner=3000))
+    assert sol["status"] == "converged"
+    rng = np.random.default_rng(1)
+    y = sol["y"] + 0.05 * rng.standard_normal(9)
+    R0 = sol["R"] + 0.05 * rng.standard_normal(sol["R"].shape)
+    g = [oracle.inner_gd(p, R0, y, 1.0, 0.0, k)[1]["gnorm"] for k in (25, 50, 75, 100, 125, 150)]
+    ratios = [b / a for a, b in zip(g, g[1:])]
+    assert all(q < 0.5 for q in ratios)
+    assert max(ratios) / min(ratios) < 3.0
