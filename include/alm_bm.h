@@ -439,7 +439,8 @@ alm_bm_status alm_bm_batch_solve(alm_bm_batch* batch, const alm_bm_options* opts
 /* Tile choice of a batch, the batched counterpart of alm_bm_autotune: for every
  * width a batched solve can give an instance (4, 8, 16, ... up to rank_stride),
  * times reps objective/gradient passes over all instances at that width with
- * each tile variant and keeps the fastest; later alm_bm_batch_solve calls
+ * each tile variant and keeps the fastest (another variant must beat variant 0
+ * by 3 %, so that timing noise does not flip the choice); later alm_bm_batch_solve calls
  * launch that variant for that width (untuned widths use variant 0).  The
  * variants sum each row in a different order, so two handles tuned apart may
  * round differently; solves on one handle stay deterministic.  widths, variants:

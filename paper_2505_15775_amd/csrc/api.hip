@@ -2971,7 +2971,10 @@ static alm_bm_status batch_autotune_impl(alm_bm_batch* b, int reps, hipStream_t 
       if (s == ALM_BM_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
         s = fail(ALM_BM_ERR_HIP, "batch_autotune: elapsed time");
       if (s != ALM_BM_OK) break;
-      if (ms < best) {
+      // another variant must beat the default by 3 %: differences inside the
+      // timing noise would make the choice, and with it the rounding of the
+      // row sums and the solve's trajectory, change from run to run
+      if (v == 0 || ms < 0.97f * best) {
         best = ms;
         bv = v;
       }
