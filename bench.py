@@ -590,7 +590,9 @@ def main():
     ap.add_argument("--deg", type=float, default=8.0)
     ap.add_argument("--rank", type=int, default=16)
     ap.add_argument("--seed", type=int, default=5)
-    ap.add_argument("--modes", action="store_true", help="also time the other two precisions")
+    ap.add_argument("--modes", action="store_true", default=True,
+                    help="also time the other two precisions (default on; --no-modes skips)")
+    ap.add_argument("--no-modes", dest="modes", action="store_false")
     ap.add_argument("--no-solve", action="store_true",
                     help="skip the solves to 1e-4 relative KKT (FP64 and BF16-ladder default starts, learned start)")
     ap.add_argument("--solve-legs", default="f64,default,learned",
