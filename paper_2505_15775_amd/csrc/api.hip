@@ -2422,8 +2422,11 @@ static alm_bm_status batch_lanczos_table(alm_bm_batch* b, const std::vector<char
 // instance that meets tol[q] (or exhausts its basis) leaves the launch table,
 // so later steps cost only the instances still running.  Results of the
 // other instances in `out` are left as they are.
+// Start of a pass: 0 a random vector, 1 the Ritz vector in v (a restart),
+// 2 the Ritz vector of the previous outer iteration in v plus a 10 % random
+// share (a warm start).
 static alm_bm_status batch_lanczos_pass(alm_bm_batch* b, const double* y, int kmax, const std::vector<double>& tol,
-                                        uint64_t seed, bool restart, double* v, BatchLanczos& out, hipStream_t st,
+                                        uint64_t seed, int start, double* v, BatchLanczos& out, hipStream_t st,
                                         const std::vector<int32_t>& run) {
   alm_bm_problem* p = b->p;
   const int count = b->count;
@@ -2447,13 +2450,17 @@ static alm_bm_status batch_lanczos_pass(alm_bm_batch* b, const double* y, int km
   STCHK(batch_lanczos_table(b, live, nb, st));
   const BlockTab ltab{b->l_inst, b->l_lo, b->l_hi, p->tab.iblo, p->tab.ibhi, b->l_gid, nullptr};
   VecBatch vb{ltab, count, kp, kp};
-  if (restart) {
+  if (start == 1) {
     launch_resid(n, v, v, 0.0, nullptr, p->lpart2, nb, st, vb);
     launch_fin_sum(p->lpart2, nb, p->lscal, 1, st, vb, 4);
     launch_scale(n, v, p->lscal, p->Q, p->lpart2, nb, nullptr, st, vb, 4);
   } else {
     launch_rand(n, seed, p->lw, p->lpart2, nb, st, vb);
     launch_fin_sum(p->lpart2, nb, p->lscal, 1, st, vb, 4);
+    if (start == 2) {
+      launch_mix(n, 0.1, v, p->lw, p->lscal, 4, p->lpart2, nb, st, vb);
+      launch_fin_sum(p->lpart2, nb, p->lscal, 1, st, vb, 4);
+    }
     launch_scale(n, p->lw, p->lscal, p->Q, p->lpart2, nb, nullptr, st, vb, 4);
   }
   std::vector<double> ha((size_t)count * kp), hb((size_t)count * kp);
@@ -2543,14 +2550,14 @@ static alm_bm_status batch_lanczos_pass(alm_bm_batch* b, const double* y, int km
 // instances are zero.
 static alm_bm_status batch_lanczos(alm_bm_batch* b, const double* y, int kmax, const std::vector<double>& tol,
                                    uint64_t seed, double* v, BatchLanczos& out, hipStream_t st,
-                                   const std::vector<int32_t>& sel, int restarts = 3) {
+                                   const std::vector<int32_t>& sel, int restarts = 3, bool warm = false) {
   const int count = b->count;
   out.theta.assign(count, 0.0);
   out.resid.assign(count, 0.0);
   out.m.assign(count, 0);
   std::vector<int32_t> run(sel);
   for (int rs = 0; rs <= restarts; ++rs) {
-    STCHK(batch_lanczos_pass(b, y, kmax, tol, seed, rs > 0, v, out, st, run));
+    STCHK(batch_lanczos_pass(b, y, kmax, tol, seed, rs > 0 ? 1 : (warm ? 2 : 0), v, out, st, run));
     bool again = false;
     for (int q = 0; q < count; ++q) {
       run[q] = run[q] && out.resid[q] > tol[q];
@@ -2775,8 +2782,10 @@ static alm_bm_status batch_solve_impl(alm_bm_batch* b, const alm_bm_options& o, 
                       count, st);
     BatchLanczos L;
     const double tl = now_s();
+    // from the second outer iteration on, each instance's pass starts from its
+    // previous Ritz vector (plus a random share): the dual moved only a little
     STCHK(batch_lanczos(b, p->ybuf, kmax, ltol, o.seed * 1000003ull + (uint64_t)k, p->lv, L, st, active,
-                        o.lanczos_restarts));
+                        o.lanczos_restarts, k > 0));
     const double tlan = now_s() - tl;
     // KKT per instance at the point as it stands (R, the updated dual):
     // <C, RR^T> and pinf at R, b^T y at y; the final values unless a rank step

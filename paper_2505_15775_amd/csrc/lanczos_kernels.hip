@@ -198,6 +198,25 @@ k_rand(long n, uint64_t seed, double* __restrict__ x, double* __restrict__ part,
   block_sum_store<1>(acc, part + part_slot(tab));
 }
 
+// Warm start of a Lanczos pass: x = v + eps x / ||x|| per instance (x holds a
+// random vector whose per-instance norm is at norms[inst * nstride], v the
+// previous unit Ritz vector); partial ||x||^2.  The random share keeps every
+// eigenvector in the start, so a bottom eigenvector that moved away from v is
+// still found.
+__global__ void __launch_bounds__(kBlock)
+k_mix(long n, double eps, const double* __restrict__ v, double* __restrict__ x, const double* __restrict__ norms,
+      int nstride, double* __restrict__ part, BlockTab tab) {
+  const Rows ch = rows_of(n, tab);
+  const double a = eps / fmax(norms[(long)ch.inst * nstride], 1e-300);
+  double acc[1] = {0.0};
+  for (long i = ch.lo + threadIdx.x; i < ch.hi; i += kBlock) {
+    const double t = v[i] + a * x[i];
+    x[i] = t;
+    acc[0] += t * t;
+  }
+  block_sum_store<1>(acc, part + part_slot(tab));
+}
+
 // v = sum_c Q[c] s[c]; partial ||v||^2.
 __global__ void __launch_bounds__(kBlock)
 k_combine(long n, int ncol, const double* __restrict__ Q, long ldq, const double* __restrict__ s, int sstride,
@@ -410,6 +429,10 @@ void launch_scale(long n, const double* w, const double* beta, double* q, double
 void launch_fin_sum(const double* part, int nb, double* out, int do_sqrt, hipStream_t st, const VecBatch& vb,
                     int ostride) {
   hipLaunchKernelGGL(k_fin_sum, dim3(vb.count), dim3(kBlock), 0, st, part, nb, out, ostride, do_sqrt, vb.tab);
+}
+void launch_mix(long n, double eps, const double* v, double* x, const double* norms, int nstride, double* part,
+                int nb, hipStream_t st, const VecBatch& vb) {
+  hipLaunchKernelGGL(k_mix, dim3(nb), dim3(kBlock), 0, st, n, eps, v, x, norms, nstride, part, vb.tab);
 }
 void launch_rand(long n, uint64_t seed, double* x, double* part, int nb, hipStream_t st, const VecBatch& vb) {
   hipLaunchKernelGGL(k_rand, dim3(nb), dim3(kBlock), 0, st, n, seed, x, part, vb.tab);

@@ -133,6 +133,9 @@ void launch_fin_sum(const double* part, int nb, double* out, int do_sqrt, hipStr
                     const VecBatch& vb = VecBatch{}, int ostride = 0);
 void launch_rand(long n, uint64_t seed, double* x, double* part, int nb, hipStream_t st,
                  const VecBatch& vb = VecBatch{});
+// x <- v + eps x / ||x|| per instance (norms[inst * nstride]), partial ||x||^2.
+void launch_mix(long n, double eps, const double* v, double* x, const double* norms, int nstride, double* part,
+                int nb, hipStream_t st, const VecBatch& vb = VecBatch{});
 // Fourth moments of q <= 8 directions (V n x q column-major) per block of the
 // nb-block grid: part[b * ne + e], ne = np (np + 1) / 2, np = q (q + 1) / 2.
 void launch_gram4(long n, int q, const double* V, double* part, int nb, hipStream_t st);
